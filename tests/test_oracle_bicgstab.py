@@ -1,0 +1,192 @@
+"""Pins for the oracle's per-column Jacobi BiCGStab (Section 2.2: one matrix,
+m right-hand sides; BiCGStab as cited in Section 1).
+
+Independent references: LAPACK dense solves (plain and bordered for the
+singular Neumann/periodic operator), scipy's BiCGStab trajectory with the same
+right preconditioner, closed-form condition numbers for manufactured
+solutions, finite termination on an operator with two distinct eigenvalues,
+one-step convergence on a diagonal operator, and an exactly-zero sigma.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spl
+
+import oracle
+from workloads import grids, rng
+
+
+def dense_to_csr(D):
+    S = sp.csr_matrix(D)
+    S.sort_indices()
+    return grids.CSRMatrix(D.shape[0], S.indptr.astype(np.int32), S.indices.astype(np.int32),
+                           S.data.astype(np.float64))
+
+
+def scipy_of(A):
+    return sp.csr_matrix((A.val, A.col, A.row_ptr), shape=(A.n, A.n))
+
+
+@pytest.mark.parametrize("N", [4, 5, 6])
+def test_dense_lapack_dirichlet(N):
+    A = grids.dirichlet7(N)
+    B = rng.rhs_block(A.n, 3, 21)
+    X, infos, _ = oracle.bicgstab(A, B, tol=1e-12)
+    ref = np.linalg.solve(A.to_dense(), B)
+    lam = [3 * (2 - 2 * np.cos(q * np.pi / (N + 1))) for q in (1, N)]
+    kappa = lam[1] / lam[0]
+    for l in range(3):
+        assert infos[l]["status"] == 0
+        err = np.linalg.norm(X[:, l] - ref[:, l]) / np.linalg.norm(ref[:, l])
+        assert err <= kappa * 1e-12 * 1.01
+
+
+def test_bordered_lapack_singular_channel():
+    nx, ny, nz = 6, 4, 6
+    solid = np.zeros((nz, ny, nx), dtype=bool)
+    solid[2:4, 0:2, 2:4] = True
+    A = grids.channel7(nx, ny, nz, beta=2.0, lx=6.0, ly=4.0, lz=6.0, solid=solid)
+    assert A.n == nx * ny * nz - 8
+    B = rng.rhs_block(A.n, 2, 22, mean_zero=True)
+    X, infos, _ = oracle.bicgstab(A, B, tol=1e-11, nullspace_const=True)
+    D = A.to_dense()
+    K = np.zeros((A.n + 1, A.n + 1))
+    K[:A.n, :A.n] = D
+    K[:A.n, A.n] = 1.0
+    K[A.n, :A.n] = 1.0
+    ev = np.linalg.eigvalsh(D)
+    kappa = ev[-1] / ev[1]               # on the complement of the null space
+    for l in range(2):
+        rhs = np.concatenate([B[:, l], [0.0]])
+        ref = np.linalg.solve(K, rhs)[:A.n]
+        assert infos[l]["status"] == 0
+        assert abs(X[:, l].mean()) <= 1e-14 * np.abs(X[:, l]).max()
+        err = np.linalg.norm(X[:, l] - ref) / np.linalg.norm(ref)
+        assert err <= kappa * 1e-11 * 1.01
+
+
+def nonsymmetric_stencil(N):
+    """Dirichlet 7-point operator with an upwind-like skew in x: (6, -1.3, -0.7)."""
+    A = grids.dirichlet7(N)
+    rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+    val = A.val.copy()
+    val[A.col == rows - 1] = -1.3
+    val[A.col == rows + 1] = -0.7
+    return grids.CSRMatrix(A.n, A.row_ptr, A.col, val)
+
+
+def test_trajectory_matches_scipy_bicgstab():
+    A = nonsymmetric_stencil(10)
+    S = scipy_of(A)
+    b = rng.rhs_block(A.n, 1, 23)[:, 0]
+    dinv = 1.0 / S.diagonal()
+    M = spl.LinearOperator(S.shape, matvec=lambda v: dinv * v)
+    xs = []
+    x_sp, code = spl.bicgstab(S, b, rtol=1e-10, atol=0.0, M=M, maxiter=500,
+                              callback=lambda xk: xs.append(xk.copy()))
+    assert code == 0
+    nb = np.linalg.norm(b)
+    sp_hist = [1.0] + [np.linalg.norm(b - S @ xk) / nb for xk in xs]
+    X, infos, hist = oracle.bicgstab(A, b[:, None], tol=1e-10, hist_len=200)
+    assert infos[0]["status"] == 0 and infos[0]["restarts"] == 0
+    assert abs(infos[0]["iters"] - len(xs)) <= 1
+    # BiCGStab's irregular convergence (residual spikes) amplifies rounding
+    # differences to ~1e-8 relative within 20 steps; 1e-7 still fails on any
+    # changed term, sign or index.
+    k = min(20, len(xs))
+    h = hist[0, :k + 1]
+    assert np.all(np.abs(h - np.array(sp_hist[:k + 1])) <= 1e-7 * np.array(sp_hist[:k + 1]))
+    assert np.linalg.norm(X[:, 0] - x_sp) <= 1e-8 * np.linalg.norm(x_sp)
+
+
+def test_finite_termination_two_eigenvalues():
+    n, c, a = 50, 3.0, 0.05
+    D = c * np.eye(n) + a * np.ones((n, n))      # constant diagonal c + a
+    A = dense_to_csr(D)
+    B = rng.rhs_block(n, 2, 24)
+    X, infos, _ = oracle.bicgstab(A, B, tol=1e-12)
+    for inf in infos:
+        assert inf["status"] == 0
+        assert inf["iters"] <= 2
+        assert inf["relres"] <= 1e-12
+
+
+def test_diagonal_operator_one_step():
+    n = 37
+    d = 1.0 + np.arange(n) / 7.0
+    A = dense_to_csr(np.diag(d))
+    b = rng.rhs_block(n, 1, 25)
+    X, infos, _ = oracle.bicgstab(A, b, tol=1e-14)
+    assert infos[0]["iters"] == 1 and infos[0]["status"] == 0
+    assert np.allclose(X[:, 0], b[:, 0] / d, rtol=1e-15, atol=0)
+
+
+def test_forced_breakdown():
+    A = dense_to_csr(np.array([[1.0, -1.25], [-1.25, 1.0]]))
+    b = np.array([[1.0], [2.0]])
+    # sigma = b^T A b = 1 - 5 + 4 = 0 exactly
+    assert float(b[:, 0] @ A.to_dense() @ b[:, 0]) == 0.0
+    X, infos, _ = oracle.bicgstab(A, b, tol=1e-10, maxit=50)
+    inf = infos[0]
+    assert inf["status"] == oracle.EBREAKDOWN
+    assert inf["breakdowns"] == 4 and inf["restarts"] == 3 and inf["iters"] == 4
+
+
+def test_manufactured_integer_solution():
+    N = 16
+    A = grids.dirichlet7(N)
+    xstar = rng.int_block(A.n, 2, 26, -50, 50)
+    B = oracle.gspmv(A, xstar)                   # exact: integers below 2**53
+    X, infos, _ = oracle.bicgstab(A, B, tol=1e-10)
+    lmin = 3 * (2 - 2 * np.cos(np.pi / (N + 1)))
+    lmax = 3 * (2 - 2 * np.cos(N * np.pi / (N + 1)))
+    assert abs(lmax / lmin - 116.46) < 0.01
+    for l in range(2):
+        err = np.linalg.norm(X[:, l] - xstar[:, l]) / np.linalg.norm(xstar[:, l])
+        assert err <= (lmax / lmin) * infos[l]["relres"] * 1.0001
+
+
+def test_iteration_count_small_dirichlet():
+    A = grids.dirichlet7(16)
+    B = rng.rhs_block(A.n, 4, 1711)
+    X, infos, _ = oracle.bicgstab(A, B, tol=1e-10)
+    for inf in infos:
+        assert inf["status"] == 0 and inf["restarts"] == 0
+        assert 40 <= inf["iters"] <= 70
+        assert inf["relres"] <= 1e-10
+
+
+def test_maxit_reports_noconv():
+    A = grids.dirichlet7(8)
+    B = rng.rhs_block(A.n, 1, 27)
+    X, infos, _ = oracle.bicgstab(A, B, tol=1e-10, maxit=1)
+    assert infos[0]["status"] == oracle.ENOCONV and infos[0]["iters"] == 1
+    assert 0 < infos[0]["relres"] < 1
+
+
+def test_nan_column_isolated_and_zero_rhs():
+    A = grids.dirichlet7(6)
+    B = rng.rhs_block(A.n, 3, 28)
+    B[:, 2] = 0.0
+    Bn = B.copy()
+    Bn[5, 1] = np.nan
+    X, infos, _ = oracle.bicgstab(A, B, tol=1e-10)
+    Xn, infos_n, _ = oracle.bicgstab(A, Bn, tol=1e-10)
+    assert infos_n[1]["status"] == oracle.EBREAKDOWN
+    assert np.array_equal(X[:, 0], Xn[:, 0])
+    assert infos[2]["status"] == 0 and infos[2]["iters"] == 0 and np.all(X[:, 2] == 0)
+
+
+def test_zero_diagonal_rejected():
+    A = dense_to_csr(np.array([[0.0, 1.0], [1.0, 2.0]]))
+    X, infos, _ = oracle.bicgstab(A, np.ones((2, 1)))
+    assert infos[0]["status"] == oracle.EINVAL
+
+
+def test_initial_guess_exact():
+    A = grids.dirichlet7(6)
+    xstar = rng.int_block(A.n, 1, 29, -5, 5)
+    B = oracle.gspmv(A, xstar)
+    X, infos, _ = oracle.bicgstab(A, B, tol=1e-10, X0=xstar)
+    assert infos[0]["iters"] == 0 and infos[0]["status"] == 0
+    assert np.array_equal(X, xstar)
