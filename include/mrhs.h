@@ -1,0 +1,162 @@
+/*
+ * mrhs.h -- block multi-right-hand-side pressure-Poisson solver for MI355X
+ * (gfx950).  C ABI of libmrhs.so.
+ *
+ * Method: B. I. Krasnopolsky, "An Approach for Accelerating Incompressible
+ * Turbulent Flow Simulations Based on Simultaneous Modelling of Multiple
+ * Ensembles" (arXiv 1711.10622).  m flow realizations share one pressure
+ * matrix, so their pressure-Poisson systems form one SLAE with m right-hand
+ * sides (Section 2.2); its cost is dominated by the generalized sparse
+ * matrix-vector product Y = A X over a block of m vectors (Section 2.3,
+ * Figure 1), which reads the matrix once for all m columns.
+ *
+ * Conventions for every call:
+ *  - Every call returns an mrhs_status.  No exception crosses the ABI.  On
+ *    failure mrhs_last_error() returns a message for the calling thread.
+ *  - A matrix is general CRS: row offsets int32[n+1] (row_ptr[0] == 0,
+ *    non-decreasing, row_ptr[n] == nnz), column indices int32[nnz] in
+ *    [0, n), values binary64[nnz].  Column order inside a row is free and a
+ *    repeated column adds (the Figure 1 loop sums every stored entry); an
+ *    empty row yields 0.
+ *  - A block X of m vectors is n x m, row-interleaved: X[i*m + l] is row i
+ *    of vector l ("stored row-wise in single vectors", Section 2.3).
+ *  - 1 <= m <= 16.  Device pointers are HIP device memory of the current
+ *    device, 16-byte aligned (EINVAL otherwise); a stream argument of NULL
+ *    means the null stream.
+ *  - Calls on one matrix handle from several host threads must be
+ *    serialised by the caller, except the solve server, which is
+ *    thread-safe.
+ */
+#ifndef MRHS_H
+#define MRHS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MRHS_OK = 0,
+    MRHS_EAGAIN = 1,          /* solve_server_poll: not finished yet */
+    MRHS_EINVAL = -1,         /* invalid argument or matrix */
+    MRHS_ENOMEM = -2,         /* device or host allocation failed */
+    MRHS_EDEVICE = -3,        /* a HIP call failed */
+    MRHS_ENOCONV = -4,        /* maxit reached; X holds the last iterate */
+    MRHS_EBREAKDOWN = -5,     /* BiCGStab breakdown persisted after restarts */
+    MRHS_EBUDGET = -6,        /* request can never fit the server's budget */
+    MRHS_ESHUTDOWN = -7,      /* server is shutting down */
+    MRHS_ENOTFOUND = -8       /* unknown ticket or matrix id */
+} mrhs_status;
+
+/* element type of a block (gspmv_ex) */
+enum { MRHS_F64 = 0, MRHS_F32 = 1 };
+
+/* csr_create flags */
+#define MRHS_CSR_NULLSPACE_CONST 1u /* A*1 = 0 (pure Neumann/periodic): solves
+                                       return x with its mean removed */
+
+/* block_bicgstab_ex flags */
+#define MRHS_X0_GIVEN 1u   /* X holds the initial guess on entry */
+#define MRHS_MIXED 2u      /* FP32 inner BiCGStab inside FP64 refinement */
+
+typedef struct mrhs_csr_s *mrhs_csr;
+typedef struct mrhs_server_s *mrhs_server;
+
+/* Per-column outcome of a solve. */
+typedef struct {
+    int32_t iters;    /* BiCGStab iterations (inner iterations in total for
+                         MRHS_MIXED) */
+    int32_t restarts; /* restarts from the true residual */
+    int32_t outer;    /* refinement steps (MRHS_MIXED), else 0 */
+    int32_t status;   /* mrhs_status of this column */
+    double relres;    /* ||b - A x||_2 / ||b||_2 in binary64, recomputed from
+                         the returned x (0 when b = 0) */
+} mrhs_col_info;
+
+typedef struct {
+    double p50_ms, p99_ms;   /* request latency, submit to completion */
+    double rhs_per_s;        /* completed right-hand sides per second since
+                                the first submit */
+    int64_t submitted;       /* requests */
+    int64_t completed;       /* requests */
+    int64_t queued;          /* requests waiting for admission */
+    int64_t rhs_completed;   /* right-hand sides */
+    size_t admitted_bytes;   /* device bytes held by admitted work */
+} mrhs_server_stats;
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char *mrhs_last_error(void);
+
+/* Library version string. */
+const char *mrhs_version(void);
+
+/*
+ * Upload a CRS matrix (Section 2.3: row, col, val arrays).  The host arrays
+ * are copied; the caller keeps ownership.  The handle owns device copies of
+ * row_ptr, col_idx and val, plus what the solvers derive from them: the
+ * diagonal and its inverse, the column-scaled matrix A D^-1 (the right
+ * Jacobi preconditioner folded into the values) and binary32 roundings
+ * (round-to-nearest-even) of val and of A D^-1.
+ * EINVAL: n < 0, nnz out of range, a NULL array with n > 0, row_ptr[0] != 0,
+ * decreasing row_ptr, row_ptr[n] != nnz, a column outside [0, n), or a
+ * non-finite value.  A zero diagonal is accepted here and rejected by the
+ * solvers.
+ */
+mrhs_status csr_create(int32_t n, int64_t nnz, const int32_t *row_ptr,
+                       const int32_t *col_idx, const double *val,
+                       uint32_t flags, mrhs_csr *out);
+
+/* Free the handle and its device memory.  NULL is accepted. */
+mrhs_status csr_destroy(mrhs_csr A);
+
+/* Size of the matrix and the device bytes the handle holds. */
+mrhs_status csr_info(mrhs_csr A, int32_t *n, int64_t *nnz, size_t *device_bytes);
+
+/*
+ * Y = A X (Section 2.3, Figure 1) for device blocks X, Y of m binary64
+ * vectors on the null stream; returns when the product is enqueued.
+ * EINVAL: m outside [1, 16], NULL pointers with n > 0, or X == Y.
+ */
+mrhs_status gspmv(mrhs_csr A, const double *X, double *Y, int32_t m);
+
+/*
+ * As gspmv, on a given stream, with the element type dtype: MRHS_F64, or
+ * MRHS_F32 (binary32 blocks and the binary32 rounding of val, products
+ * accumulated in binary32).
+ */
+mrhs_status gspmv_ex(mrhs_csr A, int32_t dtype, const void *X, void *Y,
+                     int32_t m, void *hip_stream);
+
+/*
+ * Solve A X = B for a device block B of m right-hand sides (Section 2.2:
+ * one matrix, m independent realizations), each column by BiCGStab with a
+ * right Jacobi preconditioner; columns run concurrently and share every
+ * matrix read.  Column l stops when ||b_l - A x_l|| <= tol ||b_l|| holds for
+ * the recomputed true residual.  Uses the null stream and blocks until done.
+ * Returns OK only if every column converged, else the worst column status.
+ */
+mrhs_status block_bicgstab(mrhs_csr A, const double *B, double *X, int32_t m,
+                           double tol, int32_t maxit);
+
+/*
+ * Full form.  flags: MRHS_X0_GIVEN, MRHS_MIXED.  workspace: device memory of
+ * at least block_bicgstab_workspace_size() bytes owned by the caller, or NULL
+ * to let the library allocate and free it.  info: host array of m entries or
+ * NULL.  Blocks the calling thread until the solve is done.
+ */
+mrhs_status block_bicgstab_ex(mrhs_csr A, const double *B, double *X, int32_t m,
+                              double tol, int32_t maxit, uint32_t flags,
+                              void *workspace, size_t ws_bytes, void *hip_stream,
+                              mrhs_col_info *info);
+
+/* Bytes of device workspace block_bicgstab_ex needs for (A, m, flags). */
+mrhs_status block_bicgstab_workspace_size(mrhs_csr A, int32_t m, uint32_t flags,
+                                          size_t *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MRHS_H */

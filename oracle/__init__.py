@@ -110,6 +110,40 @@ def gspmv_dot2(A, X):
     return _gspmv_impl("oracle_gspmv_dot2", A, X)
 
 
+class _Rows:
+    def __init__(self, n, row_ptr, col, val):
+        self.n, self.row_ptr, self.col, self.val = n, row_ptr, col, val
+
+
+def row_subset(A, rows):
+    """The rows ``rows`` of A as a CSR with len(rows) rows and A's columns."""
+    rows = np.asarray(rows, dtype=np.int64)
+    rp = A.row_ptr.astype(np.int64)
+    lens = rp[rows + 1] - rp[rows]
+    srp = np.zeros(len(rows) + 1, dtype=np.int64)
+    np.cumsum(lens, out=srp[1:])
+    src = np.repeat(rp[rows] - srp[:-1], lens) + np.arange(int(srp[-1]), dtype=np.int64)
+    return _Rows(len(rows), srp.astype(np.int32), A.col[src], A.val[src])
+
+
+def gspmv_rows(A, X, rows, dot2=False):
+    """Rows ``rows`` of A X, for sampled checks of products too large to
+    recompute whole."""
+    lib = _load()
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    if X.ndim == 1:
+        X = X[:, None]
+    n, m = X.shape
+    assert n == A.n
+    S = row_subset(A, rows)
+    Y = np.empty((S.n, m), dtype=np.float64)
+    rp, ci, va = _csr(S)
+    fn = lib.oracle_gspmv_dot2 if dot2 else lib.oracle_gspmv
+    fn(S.n, _p(rp, ctypes.c_int32), _p(ci, ctypes.c_int32), _p(va, ctypes.c_double), m,
+       _p(X, ctypes.c_double), _p(Y, ctypes.c_double))
+    return Y
+
+
 def bicgstab(A, B, tol=1e-10, maxit=10000, nullspace_const=None, X0=None,
              hist_len=0, threads=1):
     """Solve A x_l = b_l for every column l of B independently.

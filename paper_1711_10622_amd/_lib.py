@@ -1,0 +1,92 @@
+"""ctypes declarations of libmrhs.so (see include/mrhs.h for the contract).
+
+Loading fails loudly when the library is missing or cannot be loaded: there
+is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmrhs.so")
+
+OK, EAGAIN, EINVAL, ENOMEM, EDEVICE, ENOCONV, EBREAKDOWN, EBUDGET, ESHUTDOWN, ENOTFOUND = (
+    0, 1, -1, -2, -3, -4, -5, -6, -7, -8)
+STATUS_NAMES = {0: "OK", 1: "EAGAIN", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOCONV",
+                -5: "EBREAKDOWN", -6: "EBUDGET", -7: "ESHUTDOWN", -8: "ENOTFOUND"}
+F64, F32 = 0, 1
+CSR_NULLSPACE_CONST = 1
+X0_GIVEN, MIXED = 1, 2
+
+# every symbol include/mrhs.h declares
+EXPORTS = (
+    "mrhs_last_error", "mrhs_version", "csr_create", "csr_destroy", "csr_info", "gspmv", "gspmv_ex",
+    "block_bicgstab", "block_bicgstab_ex", "block_bicgstab_workspace_size",
+)
+
+
+class ColInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("restarts", ctypes.c_int32), ("outer", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("relres", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class MrhsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lock = threading.Lock()
+_lib = None
+
+
+def _declare(lib):
+    c = ctypes
+    vp, i32, i64, u32, f64, sz = c.c_void_p, c.c_int32, c.c_int64, c.c_uint32, c.c_double, c.c_size_t
+    lib.mrhs_last_error.restype = c.c_char_p
+    lib.mrhs_last_error.argtypes = []
+    lib.mrhs_version.restype = c.c_char_p
+    lib.mrhs_version.argtypes = []
+    sigs = {
+        "csr_create": [i32, i64, vp, vp, vp, u32, c.POINTER(vp)],
+        "csr_destroy": [vp],
+        "csr_info": [vp, c.POINTER(i32), c.POINTER(i64), c.POINTER(sz)],
+        "gspmv": [vp, vp, vp, i32],
+        "gspmv_ex": [vp, i32, vp, vp, i32, vp],
+        "block_bicgstab": [vp, vp, vp, i32, f64, i32],
+        "block_bicgstab_ex": [vp, vp, vp, i32, f64, i32, u32, vp, sz, vp, c.POINTER(ColInfo)],
+        "block_bicgstab_workspace_size": [vp, i32, u32, c.POINTER(sz)],
+    }
+    for name, args in sigs.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = c.c_int
+
+
+def load(build_if_missing: bool = True):
+    """Load libmrhs.so (building it once if it has never been built)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            if not build_if_missing:
+                raise RuntimeError(f"{LIB_PATH} is not built")
+            from . import build as _build
+            _build.build()
+        lib = ctypes.CDLL(LIB_PATH)
+        _declare(lib)
+        _lib = lib
+        return lib
+
+
+def check(status: int, what: str = ""):
+    if status != OK:
+        msg = load().mrhs_last_error().decode(errors="replace")
+        raise MrhsError(status, f"{what}: {msg}" if what else msg)
+    return status

@@ -1,0 +1,158 @@
+"""Python binding of libmrhs: argument marshalling only.
+
+Device memory and streams come from PyTorch (``torch.cuda``); every step of
+the computation runs in the library's HIP kernels.  Names follow the C ABI
+(include/mrhs.h): ``csr_create`` -> :class:`CsrMatrix`, ``gspmv``,
+``block_bicgstab``.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _check_block(t, n, m, dtype, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.dim() == 1:
+        t = t.view(-1, 1)
+    if tuple(t.shape) != (n, m) or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous ({n}, {m}) block, got {tuple(t.shape)}")
+    return t
+
+
+class CsrMatrix:
+    """A CRS matrix resident on the current GPU (``csr_create``)."""
+
+    def __init__(self, n, row_ptr, col_idx, val, nullspace_const=False):
+        lib = _lib.load()
+        self._lib = lib
+        self.n = int(n)
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+        va = np.ascontiguousarray(val, dtype=np.float64)
+        self.nnz = int(ci.shape[0])
+        self.nullspace_const = bool(nullspace_const)
+        h = ctypes.c_void_p()
+        flags = _lib.CSR_NULLSPACE_CONST if nullspace_const else 0
+        _lib.check(lib.csr_create(self.n, self.nnz, rp.ctypes.data if rp.size else None,
+                                  ci.ctypes.data if ci.size else None,
+                                  va.ctypes.data if va.size else None, flags, ctypes.byref(h)),
+                   "csr_create")
+        self._h = h
+
+    @classmethod
+    def from_csr(cls, A, nullspace_const=None):
+        """From any object with ``n, row_ptr, col, val`` (e.g. the workload generators)."""
+        if nullspace_const is None:
+            nullspace_const = bool(getattr(A, "nullspace_const", False))
+        return cls(A.n, A.row_ptr, A.col, A.val, nullspace_const)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def device_bytes(self) -> int:
+        n, nnz, b = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_size_t()
+        _lib.check(self._lib.csr_info(self._h, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(b)))
+        return int(b.value)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.csr_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- products -------------------------------------------------------------
+    def gspmv(self, X, out=None, stream=None):
+        """Y = A X for an (n, m) block (float64 or float32), m in 1..16."""
+        torch = _torch()
+        squeeze = X.dim() == 1
+        m = 1 if squeeze else int(X.shape[1])
+        if X.dtype not in (torch.float64, torch.float32):
+            raise TypeError("X must be float64 or float32")
+        Xb = _check_block(X, self.n, m, X.dtype, "X")
+        if out is None:
+            out = torch.empty_like(Xb)
+        Yb = _check_block(out, self.n, m, X.dtype, "out")
+        dtype = _lib.F64 if X.dtype == torch.float64 else _lib.F32
+        _lib.check(self._lib.gspmv_ex(self._h, dtype, ctypes.c_void_p(Xb.data_ptr()),
+                                      ctypes.c_void_p(Yb.data_ptr()), m, _stream_handle(stream)),
+                   "gspmv")
+        return out.view(-1) if squeeze else out
+
+    # -- solves ---------------------------------------------------------------
+    def workspace_size(self, m, mixed=False) -> int:
+        b = ctypes.c_size_t()
+        _lib.check(self._lib.block_bicgstab_workspace_size(self._h, int(m), _lib.MIXED if mixed else 0,
+                                                           ctypes.byref(b)))
+        return int(b.value)
+
+    def solve(self, B, tol=1e-10, maxit=20000, mixed=False, X0=None, out=None, workspace=None,
+              stream=None):
+        """Solve A X = B (``block_bicgstab_ex``).
+
+        Returns ``(X, infos, status)``: the float64 (n, m) solution, a list
+        of per-column dicts (iters, restarts, outer, status, relres) and the
+        overall status (OK only if every column converged).  Argument errors
+        and device failures raise :class:`MrhsError`.
+        """
+        torch = _torch()
+        squeeze = B.dim() == 1
+        m = 1 if squeeze else int(B.shape[1])
+        Bb = _check_block(B, self.n, m, torch.float64, "B")
+        flags = _lib.MIXED if mixed else 0
+        if X0 is not None:
+            X0b = _check_block(X0, self.n, m, torch.float64, "X0")
+            if out is None:
+                out = X0b.clone()
+            else:
+                out.copy_(X0b)
+            flags |= _lib.X0_GIVEN
+        elif out is None:
+            out = torch.empty_like(Bb)
+        Xb = _check_block(out, self.n, m, torch.float64, "out")
+        need = self.workspace_size(m, mixed)
+        if workspace is None:
+            workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=Bb.device)
+        elif workspace.numel() * workspace.element_size() < need:
+            raise ValueError(f"workspace needs {need} bytes")
+        infos = (_lib.ColInfo * m)()
+        st = self._lib.block_bicgstab_ex(self._h, ctypes.c_void_p(Bb.data_ptr()),
+                                         ctypes.c_void_p(Xb.data_ptr()), m, float(tol), int(maxit), flags,
+                                         ctypes.c_void_p(workspace.data_ptr()), need,
+                                         _stream_handle(stream), infos)
+        if st not in (_lib.OK, _lib.ENOCONV, _lib.EBREAKDOWN):
+            _lib.check(st, "block_bicgstab")
+        return (out.view(-1) if squeeze else out), [i.as_dict() for i in infos], st
+
+
+def gspmv(A: CsrMatrix, X, out=None, stream=None):
+    return A.gspmv(X, out=out, stream=stream)
+
+
+def block_bicgstab(A: CsrMatrix, B, tol=1e-10, maxit=20000, mixed=False, **kw):
+    return A.solve(B, tol=tol, maxit=maxit, mixed=mixed, **kw)

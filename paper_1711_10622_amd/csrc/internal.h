@@ -1,0 +1,139 @@
+// Host-side internals of libmrhs: the matrix handle, error reporting, grid
+// sizing and kernel launch helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstddef>
+#include <cstdint>
+
+#include "mrhs.h"
+#include "ops.h"
+
+struct mrhs_csr_s {
+    int32_t n = 0;
+    int64_t nnz = 0;
+    uint32_t flags = 0;
+    int device = 0;
+    bool zero_diag = false;
+    int32_t *rp = nullptr;    // [n+1]
+    int32_t *ci = nullptr;    // [nnz]
+    double *val = nullptr;    // [nnz] A
+    double *valh = nullptr;   // [nnz] A D^-1
+    float *val32 = nullptr;   // [nnz] RN32(A)
+    float *valh32 = nullptr;  // [nnz] RN32(A D^-1)
+    double *diag = nullptr;   // [n]
+    double *dinv = nullptr;   // [n]
+    size_t bytes = 0;
+};
+
+namespace mrhs {
+
+// Thread-local last-error message; returns s for convenience.
+mrhs_status set_error(mrhs_status s, const char *fmt, ...);
+void clear_error();
+
+#define MRHS_HIP(expr)                                                                      \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return ::mrhs::set_error(MRHS_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+// Number of workgroups for a tile-looping kernel over n rows: enough to keep
+// every CU at its occupancy limit, never more than there are tiles, rounded
+// up to a multiple of kGroups.
+int grid_for(const void *kernel, int64_t n);
+int max_grid();  // upper bound of grid_for over all kernels (for buffer sizing)
+
+template <typename T>
+inline CsrView<T> view(const mrhs_csr_s &A, bool scaled);
+
+template <>
+inline CsrView<double> view<double>(const mrhs_csr_s &A, bool scaled)
+{
+    return {A.rp, A.ci, scaled ? A.valh : A.val, A.n};
+}
+
+template <>
+inline CsrView<float> view<float>(const mrhs_csr_s &A, bool scaled)
+{
+    return {A.rp, A.ci, scaled ? A.valh32 : A.val32, A.n};
+}
+
+template <typename T, int M, class Op>
+__global__ void __launch_bounds__(kBlock) k_gspmv(CsrView<T> A, Op op, RedBufs<T> rb)
+{
+    Acc<T, Shape<T, M>::VW, Op::NDOT> acc;
+    acc.zero();
+    gspmv_tiles<T, M>(A, op, acc);
+    if constexpr (Op::NDOT > 0)
+        grid_reduce<T, M, Op::NDOT>(acc, rb, op);
+}
+
+template <typename T, int M, class Op>
+__global__ void __launch_bounds__(kBlock) k_stream(int32_t n, Op op, RedBufs<T> rb)
+{
+    Acc<T, Shape<T, M>::VW, Op::NDOT> acc;
+    acc.zero();
+    stream_tiles<T, M>(n, op, acc);
+    if constexpr (Op::NDOT > 0)
+        grid_reduce<T, M, Op::NDOT>(acc, rb, op);
+}
+
+template <typename T, int M, class Op>
+inline hipError_t launch_gspmv(const CsrView<T> &A, const Op &op, const RedBufs<T> &rb, hipStream_t s)
+{
+    const void *fn = reinterpret_cast<const void *>(&k_gspmv<T, M, Op>);
+    const int grid = grid_for(fn, A.n);
+    hipLaunchKernelGGL((k_gspmv<T, M, Op>), dim3(grid), dim3(kBlock), 0, s, A, op, rb);
+    return hipGetLastError();
+}
+
+template <typename T, int M, class Op>
+inline hipError_t launch_stream(int32_t n, const Op &op, const RedBufs<T> &rb, hipStream_t s)
+{
+    const void *fn = reinterpret_cast<const void *>(&k_stream<T, M, Op>);
+    const int grid = grid_for(fn, n);
+    hipLaunchKernelGGL((k_stream<T, M, Op>), dim3(grid), dim3(kBlock), 0, s, n, op, rb);
+    return hipGetLastError();
+}
+
+// Calls f.template operator()<M>() for the runtime value m in [1, 16].
+template <class F>
+inline auto dispatch_m(int m, F &&f)
+{
+    switch (m) {
+    case 1: return f.template operator()<1>();
+    case 2: return f.template operator()<2>();
+    case 3: return f.template operator()<3>();
+    case 4: return f.template operator()<4>();
+    case 5: return f.template operator()<5>();
+    case 6: return f.template operator()<6>();
+    case 7: return f.template operator()<7>();
+    case 8: return f.template operator()<8>();
+    case 9: return f.template operator()<9>();
+    case 10: return f.template operator()<10>();
+    case 11: return f.template operator()<11>();
+    case 12: return f.template operator()<12>();
+    case 13: return f.template operator()<13>();
+    case 14: return f.template operator()<14>();
+    case 15: return f.template operator()<15>();
+    default: return f.template operator()<16>();
+    }
+}
+
+// ---- block solver (solver.hip) ----------------------------------------------
+struct SolveParams {
+    int32_t m;
+    double tol;
+    int32_t maxit;
+    uint32_t flags;
+};
+
+size_t solve_workspace_bytes(const mrhs_csr_s &A, int32_t m, uint32_t flags);
+mrhs_status block_solve(const mrhs_csr_s &A, const double *B, double *X, const SolveParams &p,
+                        void *ws, size_t ws_bytes, hipStream_t s, mrhs_col_info *info);
+
+} // namespace mrhs

@@ -1,0 +1,368 @@
+// C ABI of libmrhs: matrix handles, the generalized SpMV and the block solve.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "internal.h"
+
+#define MRHS_API extern "C" __attribute__((visibility("default")))
+
+namespace mrhs {
+
+namespace {
+thread_local std::string g_error;
+}
+
+mrhs_status set_error(mrhs_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return s;
+}
+
+void clear_error() { g_error.clear(); }
+
+namespace {
+
+std::mutex g_grid_mu;
+std::unordered_map<const void *, int> g_blocks_per_cu;
+int g_num_cu = 0;
+
+int num_cu()
+{
+    if (g_num_cu == 0) {
+        int dev = 0, cu = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cu > 0)
+            g_num_cu = cu;
+        else
+            g_num_cu = 256;
+    }
+    return g_num_cu;
+}
+
+} // namespace
+
+int max_grid()
+{
+    std::lock_guard<std::mutex> lk(g_grid_mu);
+    const int g = num_cu() * (2048 / kBlock);
+    return (g + kGroups - 1) / kGroups * kGroups;
+}
+
+int grid_for(const void *kernel, int64_t n)
+{
+    int per_cu = 1, cus = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_grid_mu);
+        cus = num_cu();
+        auto it = g_blocks_per_cu.find(kernel);
+        if (it == g_blocks_per_cu.end()) {
+            int nb = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, kBlock, 0) != hipSuccess || nb < 1)
+                nb = 1;
+            nb = std::min(nb, 2048 / kBlock);
+            it = g_blocks_per_cu.emplace(kernel, nb).first;
+        }
+        per_cu = it->second;
+    }
+    const int64_t ntiles = (n + kTileRows - 1) / kTileRows;
+    int64_t g = std::min<int64_t>(ntiles, static_cast<int64_t>(per_cu) * cus);
+    g = std::max<int64_t>(g, 1);
+    g = (g + kGroups - 1) / kGroups * kGroups;
+    return static_cast<int>(g);
+}
+
+namespace {
+
+__global__ void k_derive_rows(int32_t n, const double *__restrict__ diag, double *__restrict__ dinv)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n)
+        dinv[i] = diag[i] != 0.0 ? 1.0 / diag[i] : 0.0;
+}
+
+// Ah = A D^-1 (column scaling), and binary32 roundings of A and Ah.
+__global__ void k_derive_vals(int64_t nnz, const int32_t *__restrict__ ci, const double *__restrict__ val,
+                              const double *__restrict__ diag, double *__restrict__ valh,
+                              float *__restrict__ val32, float *__restrict__ valh32)
+{
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j >= nnz)
+        return;
+    const double a = val[j];
+    const double d = diag[ci[j]];
+    const double h = d != 0.0 ? a / d : 0.0;
+    valh[j] = h;
+    val32[j] = static_cast<float>(a);
+    valh32[j] = static_cast<float>(h);
+}
+
+void free_csr(mrhs_csr_s *A)
+{
+    if (!A)
+        return;
+    void *ptrs[] = {A->rp, A->ci, A->val, A->valh, A->val32, A->valh32, A->diag, A->dinv};
+    for (void *p : ptrs)
+        if (p)
+            (void)hipFree(p);
+    delete A;
+}
+
+template <typename T>
+mrhs_status dev_alloc(T **p, size_t count, size_t &total)
+{
+    const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    if (hipMalloc(reinterpret_cast<void **>(p), bytes) != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return set_error(MRHS_ENOMEM, "device allocation of %zu bytes failed", bytes);
+    }
+    total += bytes;
+    return MRHS_OK;
+}
+
+bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+template <typename T>
+struct StoreLaunch {
+    const mrhs_csr_s *A;
+    const void *X;
+    void *Y;
+    hipStream_t s;
+    template <int M>
+    hipError_t operator()() const
+    {
+        return launch_gspmv<T, M>(view<T>(*A, false),
+                                  OpStore<T, M>{static_cast<const T *>(X), static_cast<T *>(Y)},
+                                  RedBufs<T>{nullptr, nullptr, nullptr}, s);
+    }
+};
+
+} // namespace
+} // namespace mrhs
+
+using namespace mrhs;
+
+MRHS_API const char *mrhs_last_error(void) { return g_error.c_str(); }
+
+MRHS_API const char *mrhs_version(void) { return "mrhs 0.1 (gfx950)"; }
+
+MRHS_API mrhs_status csr_create(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                                const double *val, uint32_t flags, mrhs_csr *out)
+{
+    clear_error();
+    if (!out)
+        return set_error(MRHS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 0)
+        return set_error(MRHS_EINVAL, "n = %d < 0", n);
+    if (nnz < 0 || nnz > INT32_MAX)
+        return set_error(MRHS_EINVAL, "nnz = %lld outside [0, 2^31)", static_cast<long long>(nnz));
+    if (flags & ~MRHS_CSR_NULLSPACE_CONST)
+        return set_error(MRHS_EINVAL, "unknown flags 0x%x", flags);
+    if (n > 0 && !row_ptr)
+        return set_error(MRHS_EINVAL, "row_ptr is NULL");
+    if (nnz > 0 && (!col_idx || !val))
+        return set_error(MRHS_EINVAL, "col_idx or val is NULL");
+    std::vector<double> diag(static_cast<size_t>(n), 0.0);
+    if (n > 0) {
+        if (row_ptr[0] != 0)
+            return set_error(MRHS_EINVAL, "row_ptr[0] = %d, must be 0", row_ptr[0]);
+        for (int32_t i = 0; i < n; ++i) {
+            const int32_t a = row_ptr[i], b = row_ptr[i + 1];
+            if (b < a)
+                return set_error(MRHS_EINVAL, "row_ptr decreases at row %d", i);
+            if (b > nnz)
+                return set_error(MRHS_EINVAL, "row_ptr[%d] = %d exceeds nnz", i + 1, b);
+            for (int32_t j = a; j < b; ++j) {
+                const int32_t c = col_idx[j];
+                if (c < 0 || c >= n)
+                    return set_error(MRHS_EINVAL, "col_idx[%d] = %d outside [0, %d)", j, c, n);
+                if (!std::isfinite(val[j]))
+                    return set_error(MRHS_EINVAL, "val[%d] is not finite", j);
+                if (c == i)
+                    diag[i] += val[j];
+            }
+        }
+        if (row_ptr[n] != nnz)
+            return set_error(MRHS_EINVAL, "row_ptr[n] = %d differs from nnz = %lld", row_ptr[n],
+                             static_cast<long long>(nnz));
+    } else if (nnz != 0) {
+        return set_error(MRHS_EINVAL, "nnz must be 0 when n = 0");
+    }
+
+    auto *A = new (std::nothrow) mrhs_csr_s();
+    if (!A)
+        return set_error(MRHS_ENOMEM, "host allocation failed");
+    A->n = n;
+    A->nnz = nnz;
+    A->flags = flags;
+    (void)hipGetDevice(&A->device);
+    for (int32_t i = 0; i < n; ++i)
+        if (diag[i] == 0.0)
+            A->zero_diag = true;
+    if (n == 0) {
+        *out = A;
+        return MRHS_OK;
+    }
+    size_t total = 0;
+    mrhs_status st = MRHS_OK;
+    if ((st = dev_alloc(&A->rp, static_cast<size_t>(n) + 1, total)) ||
+        (st = dev_alloc(&A->ci, static_cast<size_t>(nnz), total)) ||
+        (st = dev_alloc(&A->val, static_cast<size_t>(nnz), total)) ||
+        (st = dev_alloc(&A->valh, static_cast<size_t>(nnz), total)) ||
+        (st = dev_alloc(&A->val32, static_cast<size_t>(nnz), total)) ||
+        (st = dev_alloc(&A->valh32, static_cast<size_t>(nnz), total)) ||
+        (st = dev_alloc(&A->diag, static_cast<size_t>(n), total)) ||
+        (st = dev_alloc(&A->dinv, static_cast<size_t>(n), total))) {
+        free_csr(A);
+        return st;
+    }
+    A->bytes = total;
+    hipError_t e = hipSuccess;
+    if ((e = hipMemcpy(A->rp, row_ptr, sizeof(int32_t) * (static_cast<size_t>(n) + 1), hipMemcpyHostToDevice)) ||
+        (nnz > 0 && (e = hipMemcpy(A->ci, col_idx, sizeof(int32_t) * nnz, hipMemcpyHostToDevice))) ||
+        (nnz > 0 && (e = hipMemcpy(A->val, val, sizeof(double) * nnz, hipMemcpyHostToDevice))) ||
+        (e = hipMemcpy(A->diag, diag.data(), sizeof(double) * n, hipMemcpyHostToDevice))) {
+        free_csr(A);
+        return set_error(MRHS_EDEVICE, "upload failed: %s", hipGetErrorString(e));
+    }
+    hipLaunchKernelGGL(k_derive_rows, dim3((n + 255) / 256), dim3(256), 0, 0, n, A->diag, A->dinv);
+    if (nnz > 0)
+        hipLaunchKernelGGL(k_derive_vals, dim3(static_cast<unsigned>((nnz + 255) / 256)), dim3(256), 0, 0, nnz,
+                           A->ci, A->val, A->diag, A->valh, A->val32, A->valh32);
+    if ((e = hipGetLastError()) != hipSuccess || (e = hipDeviceSynchronize()) != hipSuccess) {
+        free_csr(A);
+        return set_error(MRHS_EDEVICE, "derive kernels failed: %s", hipGetErrorString(e));
+    }
+    *out = A;
+    return MRHS_OK;
+}
+
+MRHS_API mrhs_status csr_destroy(mrhs_csr A)
+{
+    clear_error();
+    if (A) {
+        (void)hipDeviceSynchronize();
+        free_csr(A);
+    }
+    return MRHS_OK;
+}
+
+MRHS_API mrhs_status csr_info(mrhs_csr A, int32_t *n, int64_t *nnz, size_t *device_bytes)
+{
+    clear_error();
+    if (!A)
+        return set_error(MRHS_EINVAL, "matrix handle is NULL");
+    if (n)
+        *n = A->n;
+    if (nnz)
+        *nnz = A->nnz;
+    if (device_bytes)
+        *device_bytes = A->bytes;
+    return MRHS_OK;
+}
+
+MRHS_API mrhs_status gspmv_ex(mrhs_csr A, int32_t dtype, const void *X, void *Y, int32_t m, void *hip_stream)
+{
+    clear_error();
+    if (!A)
+        return set_error(MRHS_EINVAL, "matrix handle is NULL");
+    if (m < 1 || m > kMaxM)
+        return set_error(MRHS_EINVAL, "m = %d outside [1, 16]", m);
+    if (dtype != MRHS_F64 && dtype != MRHS_F32)
+        return set_error(MRHS_EINVAL, "unknown dtype %d", dtype);
+    if (A->n == 0)
+        return MRHS_OK;
+    if (!X || !Y)
+        return set_error(MRHS_EINVAL, "X or Y is NULL");
+    if (X == Y)
+        return set_error(MRHS_EINVAL, "X and Y must not alias");
+    if (!aligned16(X) || !aligned16(Y))
+        return set_error(MRHS_EINVAL, "X and Y must be 16-byte aligned");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    hipError_t e = dtype == MRHS_F64 ? dispatch_m(m, StoreLaunch<double>{A, X, Y, s})
+                                     : dispatch_m(m, StoreLaunch<float>{A, X, Y, s});
+    if (e != hipSuccess)
+        return set_error(MRHS_EDEVICE, "gspmv launch failed: %s", hipGetErrorString(e));
+    return MRHS_OK;
+}
+
+MRHS_API mrhs_status gspmv(mrhs_csr A, const double *X, double *Y, int32_t m)
+{
+    return gspmv_ex(A, MRHS_F64, X, Y, m, nullptr);
+}
+
+MRHS_API mrhs_status block_bicgstab_workspace_size(mrhs_csr A, int32_t m, uint32_t flags, size_t *bytes)
+{
+    clear_error();
+    if (!A || !bytes)
+        return set_error(MRHS_EINVAL, "NULL argument");
+    if (m < 1 || m > kMaxM)
+        return set_error(MRHS_EINVAL, "m = %d outside [1, 16]", m);
+    *bytes = solve_workspace_bytes(*A, m, flags);
+    return MRHS_OK;
+}
+
+MRHS_API mrhs_status block_bicgstab_ex(mrhs_csr A, const double *B, double *X, int32_t m, double tol,
+                                       int32_t maxit, uint32_t flags, void *workspace, size_t ws_bytes,
+                                       void *hip_stream, mrhs_col_info *info)
+{
+    clear_error();
+    if (!A)
+        return set_error(MRHS_EINVAL, "matrix handle is NULL");
+    if (m < 1 || m > kMaxM)
+        return set_error(MRHS_EINVAL, "m = %d outside [1, 16]", m);
+    if (!(tol > 0.0) || !std::isfinite(tol))
+        return set_error(MRHS_EINVAL, "tol must be positive and finite");
+    if (maxit < 1)
+        return set_error(MRHS_EINVAL, "maxit must be at least 1");
+    if (flags & ~(MRHS_X0_GIVEN | MRHS_MIXED))
+        return set_error(MRHS_EINVAL, "unknown flags 0x%x", flags);
+    if (A->n == 0) {
+        if (info)
+            for (int i = 0; i < m; ++i)
+                info[i] = mrhs_col_info{0, 0, 0, MRHS_OK, 0.0};
+        return MRHS_OK;
+    }
+    if (!B || !X)
+        return set_error(MRHS_EINVAL, "B or X is NULL");
+    if (static_cast<const void *>(B) == static_cast<const void *>(X))
+        return set_error(MRHS_EINVAL, "B and X must not alias");
+    if (!aligned16(B) || !aligned16(X) || (workspace && !aligned16(workspace)))
+        return set_error(MRHS_EINVAL, "B, X and the workspace must be 16-byte aligned");
+    if (A->zero_diag)
+        return set_error(MRHS_EINVAL, "the matrix has a zero diagonal entry (Jacobi preconditioner undefined)");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const size_t need = solve_workspace_bytes(*A, m, flags);
+    void *ws = workspace;
+    bool own = false;
+    if (!ws) {
+        if (hipMalloc(&ws, need) != hipSuccess) {
+            (void)hipGetLastError();
+            return set_error(MRHS_ENOMEM, "workspace allocation of %zu bytes failed", need);
+        }
+        own = true;
+        ws_bytes = need;
+    }
+    const mrhs_status st = block_solve(*A, B, X, SolveParams{m, tol, maxit, flags}, ws, ws_bytes, s, info);
+    if (own) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(ws);
+    }
+    return st;
+}
+
+MRHS_API mrhs_status block_bicgstab(mrhs_csr A, const double *B, double *X, int32_t m, double tol, int32_t maxit)
+{
+    return block_bicgstab_ex(A, B, X, m, tol, maxit, 0u, nullptr, 0, nullptr, nullptr);
+}

@@ -1,0 +1,839 @@
+// Per-row operations ("ops") plugged into the tile loops of core.h, and the
+// per-column control logic of block BiCGStab that runs in the last workgroup
+// of a grid reduction.
+//
+// The solve keeps the right Jacobi preconditioner folded into the matrix:
+// with D = diag(A) and Ah = A D^-1 (stored once per matrix), BiCGStab runs on
+// Ah y = b and x = D^-1 y.  In exact arithmetic its iterates are those of
+// BiCGStab on A x = b with p^ = D^-1 p, s^ = D^-1 s (the right-preconditioned
+// form), without a separate preconditioner pass.  Per iteration, for every
+// running column (van der Vorst 1992, as cited in Section 1):
+//
+//   p   = r + beta (p - omega v)        beta = (rho/rho_old)(alpha/omega)
+//   v   = Ah p;   sigma = (r^, v);      alpha = rho / sigma
+//   s   = r - alpha v                   (never stored: recomputed where used)
+//   t   = Ah s;   omega = (t, s)/(t, t)
+//   y  += alpha p + omega s;   r = s - omega t;   rho = (r^, r)
+//
+// Each column follows its own control flow (Section 2.2: the m realizations
+// are independent systems sharing A):
+//   * ||r|| <= tol ||b|| after an iteration, or ||s|| <= tol ||b|| (then the
+//     omega half step is skipped), marks the column for a true-residual check;
+//     the check either confirms convergence or restarts from r = b - A x.
+//   * sigma, omega or rho zero or non-finite is a breakdown: restart from the
+//     true residual; the fourth breakdown in a row ends the column.
+//   * maxit iterations end the column (restarts count toward maxit).
+// The inner solve of mixed-precision refinement runs the same iteration in
+// binary32 without restarts; it ends on its relative tolerance, on a
+// breakdown, on stagnation (no halving of ||r|| over kStagWindow
+// iterations) or on its iteration budget.
+#pragma once
+
+#include "core.h"
+
+namespace mrhs {
+
+enum ColStatus : int32_t {
+    COL_IDLE = 0,        // slot not in use
+    COL_RUN = 1,         // iterating
+    COL_PEND_CHECK = 2,  // recurrence says converged: true residual pending
+    COL_PEND_BD = 3,     // breakdown: restart pending
+    COL_DONE = 4,        // converged (true residual)
+    COL_NOCONV = 5,      // maxit reached
+    COL_BREAKDOWN = 6,   // breakdown persisted / non-finite data
+    COL_INNER_DONE = 7,  // mixed: inner solve finished, correction pending
+    COL_OUTER = 8,       // mixed: outer residual pending
+};
+
+enum IterFlag : int32_t { F_SCONV = 1, F_OMEGA_BAD = 2, F_RESTART = 4, F_ZERO_X = 8 };
+
+enum SolveMode : int32_t { MODE_F64 = 0, MODE_INNER = 1 };
+
+constexpr int kMaxBreakdownRestarts = 3;
+constexpr int kStagWindow = 50;
+
+struct Ctl {
+    int32_t status[kMaxM];
+    int32_t fresh[kMaxM];
+    int32_t flag[kMaxM];
+    int32_t iters[kMaxM];
+    int32_t maxit[kMaxM];
+    int32_t restarts[kMaxM];
+    int32_t breakdowns[kMaxM];
+    int32_t bd_run[kMaxM];
+    int32_t outer[kMaxM];
+    int32_t total_iters[kMaxM];
+    int32_t stag_it[kMaxM];
+    int32_t inner_maxit[kMaxM];
+    double nb[kMaxM];
+    double tol[kMaxM];
+    double rn[kMaxM];
+    double stag_rn[kMaxM];
+    double relres[kMaxM];
+    double rscale[kMaxM];
+    double colsum[kMaxM];
+    double tol_in;
+    int32_t mode;
+    int32_t max_outer;
+    int32_t n;
+    int32_t pad_;
+};
+
+template <typename T>
+struct Kry {
+    T rho[kMaxM];
+    T rho_old[kMaxM];
+    T alpha[kMaxM];
+    T omega[kMaxM];
+    T nbi[kMaxM];
+};
+
+template <typename T>
+__device__ __forceinline__ bool bad(T v)
+{
+    return v == T(0) || !isfinite(v);
+}
+
+__device__ __forceinline__ bool pending(int32_t s) { return s == COL_PEND_CHECK || s == COL_PEND_BD; }
+
+// ---------------------------------------------------------------------------
+// Plain product Y = A X.
+template <typename T, int M>
+struct OpStore {
+    using S = Shape<T, M>;
+    static constexpr int NDOT = 0;
+    const T *X;
+    T *Y;
+    struct Lane {
+        bool on;
+    };
+    __device__ Lane lane(int) const { return {true}; }
+    __device__ __forceinline__ void gather(const Lane &, int32_t c, int g, T *x) const
+    {
+        Vec<T, S::VW>::load(X + static_cast<size_t>(c) * M + g * S::VW, x);
+    }
+    __device__ __forceinline__ void row(const Lane &, int32_t i, int g, const T *sum,
+                                        Acc<T, S::VW, NDOT> &) const
+    {
+        Vec<T, S::VW>::store(Y + static_cast<size_t>(i) * M + g * S::VW, sum);
+    }
+    __device__ void finish(const T *) const {}
+};
+
+// ---------------------------------------------------------------------------
+// Residual R = B - A X with per-column sums of R*R and B*B.  Which columns are
+// computed, and what the last workgroup does with the norms, depends on kind.
+enum ResidKind : int32_t {
+    RES_SETUP = 0,  // first residual of a binary64 solve (all non-idle columns)
+    RES_CHECK = 1,  // true residual of columns with a pending check/breakdown
+    RES_FINAL = 2,  // residual of the returned x (all non-idle columns)
+    RES_OUTER = 3,  // mixed: outer residual of COL_OUTER / COL_INNER_DONE columns
+    RES_NORM = 4,   // only the norms, into ctl->relres (API use)
+};
+
+template <int M>
+struct OpResid {
+    using T = double;
+    using S = Shape<double, M>;
+    static constexpr int NDOT = 2;
+    const double *X;
+    const double *B;
+    double *R;
+    double *R2;  // optional second copy of R (may be null)
+    Ctl *ctl;
+    Kry<double> *kry;
+    int32_t kind;
+    struct Lane {
+        bool on;
+        bool act[S::VW];
+    };
+    __device__ bool col_on(int c) const
+    {
+        const int32_t st = ctl->status[c];
+        switch (kind) {
+        case RES_CHECK:
+            return pending(st);
+        case RES_OUTER:
+            return st == COL_OUTER || st == COL_INNER_DONE;
+        default:
+            return st != COL_IDLE;
+        }
+    }
+    __device__ Lane lane(int g) const
+    {
+        Lane ln;
+        ln.on = false;
+#pragma unroll
+        for (int v = 0; v < S::VW; ++v) {
+            ln.act[v] = col_on(g * S::VW + v);
+            ln.on = ln.on || ln.act[v];
+        }
+        return ln;
+    }
+    __device__ __forceinline__ void gather(const Lane &, int32_t c, int g, double *x) const
+    {
+        Vec<double, S::VW>::load(X + static_cast<size_t>(c) * M + g * S::VW, x);
+    }
+    __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, const double *sum,
+                                        Acc<double, S::VW, NDOT> &acc) const
+    {
+        const size_t o = static_cast<size_t>(i) * M + g * S::VW;
+        double b[S::VW], r[S::VW];
+        Vec<double, S::VW>::load(B + o, b);
+#pragma unroll
+        for (int v = 0; v < S::VW; ++v) {
+            r[v] = b[v] - sum[v];
+            if (ln.act[v]) {
+                acc.a[0][v] += r[v] * r[v];
+                acc.a[1][v] += b[v] * b[v];
+            }
+        }
+        if (R)
+            Vec<double, S::VW>::store(R + o, r);
+        if (R2)
+            Vec<double, S::VW>::store(R2 + o, r);
+    }
+    __device__ void finish(const double *tot) const
+    {
+        const int c = threadIdx.x;
+        if (c >= M || !col_on(c))
+            return;
+        const double rr = tot[c];
+        const double bb = tot[M + c];
+        Ctl &k = *ctl;
+        switch (kind) {
+        case RES_SETUP: {
+            const double nb = sqrt(bb);
+            k.nb[c] = nb;
+            k.fresh[c] = 1;
+            k.flag[c] = 0;
+            kry->rho[c] = rr;
+            kry->rho_old[c] = kry->alpha[c] = kry->omega[c] = 1.0;
+            if (!isfinite(nb)) {
+                k.status[c] = COL_BREAKDOWN;
+                k.flag[c] = F_ZERO_X;
+                k.rn[c] = nb;
+            } else if (nb == 0.0) {
+                k.status[c] = COL_DONE;
+                k.flag[c] = F_ZERO_X;
+                k.rn[c] = 0.0;
+            } else {
+                const double rn = sqrt(rr) / nb;
+                const bool mixed = k.mode == MODE_INNER;
+                k.rn[c] = rn;
+                if (rn <= k.tol[c])
+                    k.status[c] = COL_DONE;
+                else if (bad(rr))
+                    k.status[c] = mixed ? COL_BREAKDOWN : COL_PEND_BD;
+                else if (k.iters[c] >= k.maxit[c])
+                    k.status[c] = COL_NOCONV;
+                else
+                    k.status[c] = mixed ? COL_OUTER : COL_RUN;
+            }
+            break;
+        }
+        case RES_CHECK: {
+            const int32_t st = k.status[c];
+            const double nr = sqrt(rr) / k.nb[c];
+            k.flag[c] = 0;
+            if (st == COL_PEND_BD) {
+                k.breakdowns[c] += 1;
+                if (k.bd_run[c] >= kMaxBreakdownRestarts) {
+                    k.status[c] = COL_BREAKDOWN;
+                    break;
+                }
+                k.bd_run[c] += 1;
+                k.restarts[c] += 1;
+            }
+            k.rn[c] = nr;
+            if (nr <= k.tol[c]) {
+                k.status[c] = COL_DONE;
+                break;
+            }
+            if (st == COL_PEND_CHECK)
+                k.restarts[c] += 1;
+            // restart from the true residual: r = r^ = b - A x
+            kry->rho[c] = rr;
+            kry->rho_old[c] = kry->alpha[c] = kry->omega[c] = 1.0;
+            k.fresh[c] = 1;
+            k.flag[c] = F_RESTART;
+            k.status[c] = (k.iters[c] >= k.maxit[c]) ? COL_NOCONV : COL_RUN;
+            break;
+        }
+        case RES_FINAL:
+        case RES_NORM:
+            k.relres[c] = (k.nb[c] > 0.0) ? sqrt(rr) / k.nb[c] : (k.flag[c] & F_ZERO_X ? 0.0 : sqrt(rr));
+            break;
+        case RES_OUTER: {
+            const double nb = k.nb[c];
+            const double nr = sqrt(rr);
+            k.total_iters[c] += k.iters[c];
+            k.iters[c] = 0;
+            k.rn[c] = nr / nb;
+            if (!isfinite(nr)) {
+                k.status[c] = COL_BREAKDOWN;
+            } else if (nr / nb <= k.tol[c]) {
+                k.status[c] = COL_DONE;
+            } else if (k.outer[c] >= ctl->max_outer || k.total_iters[c] >= k.maxit[c]) {
+                k.status[c] = COL_NOCONV;
+            } else {
+                k.rscale[c] = nr;
+                k.outer[c] += 1;
+                k.inner_maxit[c] = k.maxit[c] - k.total_iters[c];
+                k.status[c] = COL_RUN;
+            }
+            break;
+        }
+        default:
+            break;
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Shared pieces of the Krylov ops: per-lane running flags.
+template <typename T, int M>
+struct RunLane {
+    using S = Shape<T, M>;
+    bool on;
+    bool act[S::VW];
+};
+
+template <typename T, int M>
+__device__ __forceinline__ RunLane<T, M> run_lane(const Ctl *ctl, int g)
+{
+    using S = Shape<T, M>;
+    RunLane<T, M> ln;
+    ln.on = false;
+#pragma unroll
+    for (int v = 0; v < S::VW; ++v) {
+        ln.act[v] = ctl->status[g * S::VW + v] == COL_RUN;
+        ln.on = ln.on || ln.act[v];
+    }
+    return ln;
+}
+
+// p = r + beta (p - omega v), or p = r right after a (re)start.
+template <typename T, int M>
+struct OpPUpdate {
+    using S = Shape<T, M>;
+    static constexpr int NDOT = 0;
+    T *p;
+    const T *r;
+    const T *v;
+    const Ctl *ctl;
+    const Kry<T> *kry;
+    struct Lane {
+        bool on;
+        bool act[S::VW];
+        bool fresh[S::VW];
+        T beta[S::VW], omega[S::VW];
+    };
+    __device__ Lane lane(int g) const
+    {
+        Lane ln;
+        const RunLane<T, M> rl = run_lane<T, M>(ctl, g);
+        ln.on = rl.on;
+#pragma unroll
+        for (int q = 0; q < S::VW; ++q) {
+            const int c = g * S::VW + q;
+            ln.act[q] = rl.act[q];
+            ln.fresh[q] = ctl->fresh[c] != 0;
+            ln.omega[q] = kry->omega[c];
+            ln.beta[q] = (kry->rho[c] / kry->rho_old[c]) * (kry->alpha[c] / kry->omega[c]);
+        }
+        return ln;
+    }
+    __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, Acc<T, S::VW, NDOT> &) const
+    {
+        const size_t o = static_cast<size_t>(i) * M + g * S::VW;
+        T rr[S::VW], pp[S::VW], vv[S::VW];
+        Vec<T, S::VW>::load(r + o, rr);
+        Vec<T, S::VW>::load(p + o, pp);
+        Vec<T, S::VW>::load(v + o, vv);
+#pragma unroll
+        for (int q = 0; q < S::VW; ++q) {
+            if (ln.act[q])
+                pp[q] = ln.fresh[q] ? rr[q] : rr[q] + ln.beta[q] * (pp[q] - ln.omega[q] * vv[q]);
+        }
+        Vec<T, S::VW>::store(p + o, pp);
+    }
+    __device__ void finish(const T *) const {}
+};
+
+// v = Ah p with sigma = (r^, v); the last workgroup forms alpha.
+template <typename T, int M>
+struct OpSpmv1 {
+    using S = Shape<T, M>;
+    static constexpr int NDOT = 1;
+    const T *p;
+    T *v;
+    const T *rh;
+    Ctl *ctl;
+    Kry<T> *kry;
+    using Lane = RunLane<T, M>;
+    __device__ Lane lane(int g) const { return run_lane<T, M>(ctl, g); }
+    __device__ __forceinline__ void gather(const Lane &, int32_t c, int g, T *x) const
+    {
+        Vec<T, S::VW>::load(p + static_cast<size_t>(c) * M + g * S::VW, x);
+    }
+    __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, const T *sum,
+                                        Acc<T, S::VW, NDOT> &acc) const
+    {
+        const size_t o = static_cast<size_t>(i) * M + g * S::VW;
+        T h[S::VW];
+        Vec<T, S::VW>::load(rh + o, h);
+        Vec<T, S::VW>::store(v + o, sum);
+#pragma unroll
+        for (int q = 0; q < S::VW; ++q)
+            if (ln.act[q])
+                acc.a[0][q] += h[q] * sum[q];
+    }
+    __device__ void finish(const T *tot) const
+    {
+        const int c = threadIdx.x;
+        if (c >= M || ctl->status[c] != COL_RUN)
+            return;
+        Ctl &k = *ctl;
+        k.iters[c] += 1;
+        const T sigma = tot[c];
+        if (bad(sigma)) {
+            k.status[c] = (k.mode == MODE_INNER) ? COL_INNER_DONE : COL_PEND_BD;
+            return;
+        }
+        kry->alpha[c] = kry->rho[c] / sigma;
+    }
+};
+
+// t = Ah s with s = r - alpha v formed on the fly from r and v (s is never
+// stored); sums (t,s), (t,t), (s,s).  The last workgroup forms omega.
+template <typename T, int M>
+struct OpSpmv2 {
+    using S = Shape<T, M>;
+    static constexpr int NDOT = 3;
+    const T *r;
+    const T *v;
+    T *t;
+    Ctl *ctl;
+    Kry<T> *kry;
+    struct Lane {
+        bool on;
+        bool act[S::VW];
+        T alpha[S::VW];
+    };
+    __device__ Lane lane(int g) const
+    {
+        Lane ln;
+        const RunLane<T, M> rl = run_lane<T, M>(ctl, g);
+        ln.on = rl.on;
+#pragma unroll
+        for (int q = 0; q < S::VW; ++q) {
+            ln.act[q] = rl.act[q];
+            ln.alpha[q] = kry->alpha[g * S::VW + q];
+        }
+        return ln;
+    }
+    __device__ __forceinline__ void gather(const Lane &ln, int32_t c, int g, T *x) const
+    {
+        const size_t o = static_cast<size_t>(c) * M + g * S::VW;
+        T rr[S::VW], vv[S::VW];
+        Vec<T, S::VW>::load(r + o, rr);
+        Vec<T, S::VW>::load(v + o, vv);
+#pragma unroll
+        for (int q = 0; q < S::VW; ++q)
+            x[q] = rr[q] - ln.alpha[q] * vv[q];
+    }
+    __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, const T *sum,
+                                        Acc<T, S::VW, NDOT> &acc) const
+    {
+        const size_t o = static_cast<size_t>(i) * M + g * S::VW;
+        T s[S::VW];
+        gather(ln, i, g, s);
+        Vec<T, S::VW>::store(t + o, sum);
+#pragma unroll
+        for (int q = 0; q < S::VW; ++q) {
+            if (ln.act[q]) {
+                acc.a[0][q] += sum[q] * s[q];
+                acc.a[1][q] += sum[q] * sum[q];
+                acc.a[2][q] += s[q] * s[q];
+            }
+        }
+    }
+    __device__ void finish(const T *tot) const
+    {
+        const int c = threadIdx.x;
+        if (c >= M || ctl->status[c] != COL_RUN)
+            return;
+        Ctl &k = *ctl;
+        const T ts = tot[c], tt = tot[M + c], ss = tot[2 * M + c];
+        const double nb = (k.mode == MODE_INNER) ? static_cast<double>(kry->nbi[c]) : k.nb[c];
+        const double tol = (k.mode == MODE_INNER) ? k.tol_in : k.tol[c];
+        int32_t f = 0;
+        if (static_cast<double>(sqrt(ss)) / nb <= tol) {
+            f = F_SCONV;
+        } else {
+            const T w = ts / tt;
+            if (bad(w))
+                f = F_OMEGA_BAD;
+            else
+                kry->omega[c] = w;
+        }
+        k.flag[c] = f;
+    }
+};
+
+// y += alpha p + omega s;  r = s - omega t  (s = r - alpha v); sums (r^, r)
+// and (r, r).  The last workgroup updates rho and each column's state.
+template <typename T, int M>
+struct OpXR {
+    using S = Shape<T, M>;
+    static constexpr int NDOT = 2;
+    T *y;
+    T *r;
+    const T *p;
+    const T *v;
+    const T *t;
+    const T *rh;
+    Ctl *ctl;
+    Kry<T> *kry;
+    struct Lane {
+        bool on;
+        bool act[S::VW];
+        bool use_w[S::VW];
+        T alpha[S::VW], omega[S::VW];
+    };
+    __device__ Lane lane(int g) const
+    {
+        Lane ln;
+        const RunLane<T, M> rl = run_lane<T, M>(ctl, g);
+        ln.on = rl.on;
+#pragma unroll
+        for (int q = 0; q < S::VW; ++q) {
+            const int c = g * S::VW + q;
+            ln.act[q] = rl.act[q];
+            ln.use_w[q] = ctl->flag[c] == 0;
+            ln.alpha[q] = kry->alpha[c];
+            ln.omega[q] = ln.use_w[q] ? kry->omega[c] : T(0);
+        }
+        return ln;
+    }
+    __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, Acc<T, S::VW, NDOT> &acc) const
+    {
+        const size_t o = static_cast<size_t>(i) * M + g * S::VW;
+        T yy[S::VW], rr[S::VW], pp[S::VW], vv[S::VW], tt[S::VW], hh[S::VW];
+        Vec<T, S::VW>::load(y + o, yy);
+        Vec<T, S::VW>::load(r + o, rr);
+        Vec<T, S::VW>::load(p + o, pp);
+        Vec<T, S::VW>::load(v + o, vv);
+        Vec<T, S::VW>::load(t + o, tt);
+        Vec<T, S::VW>::load(rh + o, hh);
+#pragma unroll
+        for (int q = 0; q < S::VW; ++q) {
+            if (ln.act[q]) {
+                const T s = rr[q] - ln.alpha[q] * vv[q];
+                if (ln.use_w[q]) {
+                    yy[q] = yy[q] + (ln.alpha[q] * pp[q] + ln.omega[q] * s);
+                    rr[q] = s - ln.omega[q] * tt[q];
+                } else {
+                    yy[q] = yy[q] + ln.alpha[q] * pp[q];
+                    rr[q] = s;
+                }
+                acc.a[0][q] += hh[q] * rr[q];
+                acc.a[1][q] += rr[q] * rr[q];
+            }
+        }
+        Vec<T, S::VW>::store(y + o, yy);
+        Vec<T, S::VW>::store(r + o, rr);
+    }
+    __device__ void finish(const T *tot) const
+    {
+        const int c = threadIdx.x;
+        if (c >= M || ctl->status[c] != COL_RUN)
+            return;
+        Ctl &k = *ctl;
+        const bool inner = k.mode == MODE_INNER;
+        const T rhr = tot[c], rr = tot[M + c];
+        const double nb = inner ? static_cast<double>(kry->nbi[c]) : k.nb[c];
+        const double tol = inner ? k.tol_in : k.tol[c];
+        const double rn = static_cast<double>(sqrt(rr)) / nb;
+        k.rn[c] = rn;
+        const int32_t f = k.flag[c];
+        if (f & F_SCONV) {
+            k.status[c] = inner ? COL_INNER_DONE : COL_PEND_CHECK;
+            return;
+        }
+        if (f & F_OMEGA_BAD) {
+            k.status[c] = inner ? COL_INNER_DONE : COL_PEND_BD;
+            return;
+        }
+        kry->rho_old[c] = kry->rho[c];
+        kry->rho[c] = rhr;
+        k.fresh[c] = 0;
+        k.bd_run[c] = 0;
+        if (rn <= tol) {
+            k.status[c] = inner ? COL_INNER_DONE : COL_PEND_CHECK;
+        } else if (bad(rhr)) {
+            k.status[c] = inner ? COL_INNER_DONE : COL_PEND_BD;
+        } else if (inner) {
+            if (k.iters[c] >= k.inner_maxit[c]) {
+                k.status[c] = COL_INNER_DONE;
+            } else if (k.iters[c] - k.stag_it[c] >= kStagWindow) {
+                if (rn > 0.5 * k.stag_rn[c])
+                    k.status[c] = COL_INNER_DONE;
+                k.stag_it[c] = k.iters[c];
+                k.stag_rn[c] = rn;
+            }
+        } else if (k.iters[c] >= k.maxit[c]) {
+            k.status[c] = COL_NOCONV;
+        }
+    }
+};
+
+// After a check: columns restarting take r = r^ = (true residual) rt.
+template <typename T, int M>
+struct OpRestart {
+    using S = Shape<T, M>;
+    static constexpr int NDOT = 0;
+    const T *rt;
+    T *r;
+    T *rh;
+    const Ctl *ctl;
+    struct Lane {
+        bool on;
+        bool act[S::VW];
+    };
+    __device__ Lane lane(int g) const
+    {
+        Lane ln;
+        ln.on = false;
+#pragma unroll
+        for (int q = 0; q < S::VW; ++q) {
+            const int c = g * S::VW + q;
+            ln.act[q] = (ctl->flag[c] & F_RESTART) && ctl->status[c] == COL_RUN;
+            ln.on = ln.on || ln.act[q];
+        }
+        return ln;
+    }
+    __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, Acc<T, S::VW, NDOT> &) const
+    {
+        const size_t o = static_cast<size_t>(i) * M + g * S::VW;
+        T a[S::VW], b[S::VW], h[S::VW];
+        Vec<T, S::VW>::load(rt + o, a);
+        Vec<T, S::VW>::load(r + o, b);
+        Vec<T, S::VW>::load(rh + o, h);
+#pragma unroll
+        for (int q = 0; q < S::VW; ++q)
+            if (ln.act[q]) {
+                b[q] = a[q];
+                h[q] = a[q];
+            }
+        Vec<T, S::VW>::store(r + o, b);
+        Vec<T, S::VW>::store(rh + o, h);
+    }
+    __device__ void finish(const T *) const {}
+};
+
+// Conversions between y (Ah y = b) and x = D^-1 y, and the null-space
+// projection, for every non-idle column.
+enum ScaleKind : int32_t {
+    SC_IN = 0,        // y = D x          (initial guess given)
+    SC_OUT = 1,       // x = D^-1 y, or 0 where F_ZERO_X
+    SC_ZERO = 2,      // y = 0
+    SC_SUB_MEAN = 3,  // x -= colsum / n
+    SC_FIX_ZERO = 4,  // x = 0 where F_ZERO_X
+};
+
+template <int M>
+struct OpScale {
+    using S = Shape<double, M>;
+    static constexpr int NDOT = 0;
+    double *x;
+    const double *diag;
+    const double *dinv;
+    const Ctl *ctl;
+    int32_t kind;
+    struct Lane {
+        bool on;
+        bool act[S::VW];
+        bool zero[S::VW];
+        double mean[S::VW];
+    };
+    __device__ Lane lane(int g) const
+    {
+        Lane ln;
+        ln.on = false;
+#pragma unroll
+        for (int q = 0; q < S::VW; ++q) {
+            const int c = g * S::VW + q;
+            ln.act[q] = ctl->status[c] != COL_IDLE;
+            ln.zero[q] = (ctl->flag[c] & F_ZERO_X) != 0;
+            ln.mean[q] = ctl->colsum[c] / static_cast<double>(ctl->n);
+            ln.on = ln.on || ln.act[q];
+        }
+        return ln;
+    }
+    __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, Acc<double, S::VW, NDOT> &) const
+    {
+        const size_t o = static_cast<size_t>(i) * M + g * S::VW;
+        double a[S::VW];
+        Vec<double, S::VW>::load(x + o, a);
+        const double di = (kind == SC_IN) ? diag[i] : (kind == SC_OUT ? dinv[i] : 1.0);
+#pragma unroll
+        for (int q = 0; q < S::VW; ++q) {
+            if (!ln.act[q])
+                continue;
+            if (kind == SC_ZERO)
+                a[q] = 0.0;
+            else if (kind == SC_SUB_MEAN)
+                a[q] = a[q] - ln.mean[q];
+            else if ((kind == SC_OUT || kind == SC_FIX_ZERO) && ln.zero[q])
+                a[q] = 0.0;
+            else if (kind == SC_IN || kind == SC_OUT)
+                a[q] = a[q] * di;
+        }
+        Vec<double, S::VW>::store(x + o, a);
+    }
+    __device__ void finish(const double *) const {}
+};
+
+// Column sums of x (for the null-space projection).
+template <int M>
+struct OpColSum {
+    using S = Shape<double, M>;
+    static constexpr int NDOT = 1;
+    const double *x;
+    Ctl *ctl;
+    struct Lane {
+        bool on;
+    };
+    __device__ Lane lane(int) const { return {true}; }
+    __device__ __forceinline__ void row(const Lane &, int32_t i, int g, Acc<double, S::VW, NDOT> &acc) const
+    {
+        double a[S::VW];
+        Vec<double, S::VW>::load(x + static_cast<size_t>(i) * M + g * S::VW, a);
+#pragma unroll
+        for (int q = 0; q < S::VW; ++q)
+            acc.a[0][q] += a[q];
+    }
+    __device__ void finish(const double *tot) const
+    {
+        const int c = threadIdx.x;
+        if (c < M)
+            ctl->colsum[c] = tot[c];
+    }
+};
+
+// Mixed precision: start an inner solve for each COL_RUN column:
+// r32 = r^32 = RN32(r64 / ||r64||), y32 = 0; sums (r32, r32) in binary32.
+template <int M>
+struct OpCast {
+    using S = Shape<float, M>;
+    static constexpr int NDOT = 1;
+    const double *r64;
+    float *r;
+    float *rh;
+    float *y;
+    Ctl *ctl;
+    Kry<float> *kry;
+    struct Lane {
+        bool on;
+        bool act[S::VW];
+        double scale[S::VW];
+    };
+    __device__ Lane lane(int g) const
+    {
+        Lane ln;
+        ln.on = false;
+#pragma unroll
+        for (int q = 0; q < S::VW; ++q) {
+            const int c = g * S::VW + q;
+            ln.act[q] = ctl->status[c] == COL_RUN;
+            ln.scale[q] = ctl->rscale[c];
+            ln.on = ln.on || ln.act[q];
+        }
+        return ln;
+    }
+    __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, Acc<float, S::VW, NDOT> &acc) const
+    {
+        const size_t o = static_cast<size_t>(i) * M + g * S::VW;
+        float a[S::VW], h[S::VW], z[S::VW];
+        Vec<float, S::VW>::load(r + o, a);
+        Vec<float, S::VW>::load(rh + o, h);
+        Vec<float, S::VW>::load(y + o, z);
+#pragma unroll
+        for (int q = 0; q < S::VW; ++q) {
+            if (ln.act[q]) {
+                const float f = static_cast<float>(r64[o + q] / ln.scale[q]);
+                a[q] = f;
+                h[q] = f;
+                z[q] = 0.0f;
+                acc.a[0][q] += f * f;
+            }
+        }
+        Vec<float, S::VW>::store(r + o, a);
+        Vec<float, S::VW>::store(rh + o, h);
+        Vec<float, S::VW>::store(y + o, z);
+    }
+    __device__ void finish(const float *tot) const
+    {
+        const int c = threadIdx.x;
+        if (c >= M || ctl->status[c] != COL_RUN)
+            return;
+        Ctl &k = *ctl;
+        const float rr = tot[c];
+        kry->rho[c] = rr;
+        kry->nbi[c] = sqrtf(rr);
+        kry->rho_old[c] = kry->alpha[c] = kry->omega[c] = 1.0f;
+        k.fresh[c] = 1;
+        k.flag[c] = 0;
+        k.iters[c] = 0;
+        k.stag_it[c] = 0;
+        k.stag_rn[c] = 1.0;
+        if (!(rr > 0.0f) || !isfinite(rr))
+            k.status[c] = COL_INNER_DONE;
+    }
+};
+
+// Mixed precision: x += ||r64|| * D^-1 y32 for columns whose inner solve ended.
+template <int M>
+struct OpCorrect {
+    using S = Shape<double, M>;
+    static constexpr int NDOT = 0;
+    double *x;
+    const float *y;
+    const double *dinv;
+    const Ctl *ctl;
+    struct Lane {
+        bool on;
+        bool act[S::VW];
+        double scale[S::VW];
+    };
+    __device__ Lane lane(int g) const
+    {
+        Lane ln;
+        ln.on = false;
+#pragma unroll
+        for (int q = 0; q < S::VW; ++q) {
+            const int c = g * S::VW + q;
+            ln.act[q] = ctl->status[c] == COL_INNER_DONE;
+            ln.scale[q] = ctl->rscale[c];
+            ln.on = ln.on || ln.act[q];
+        }
+        return ln;
+    }
+    __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, Acc<double, S::VW, NDOT> &) const
+    {
+        const size_t o = static_cast<size_t>(i) * M + g * S::VW;
+        double a[S::VW];
+        Vec<double, S::VW>::load(x + o, a);
+        const double di = dinv[i];
+#pragma unroll
+        for (int q = 0; q < S::VW; ++q)
+            if (ln.act[q])
+                a[q] = a[q] + ln.scale[q] * (di * static_cast<double>(y[o + q]));
+        Vec<double, S::VW>::store(x + o, a);
+    }
+    __device__ void finish(const double *) const {}
+};
+
+} // namespace mrhs

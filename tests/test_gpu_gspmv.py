@@ -1,0 +1,180 @@
+"""GPU parity of the generalized SpMV (Section 2.3, Figure 1) against the oracle.
+
+Tolerances: binary64 products must lie within 1e-13 * (|A||X|)_il of the
+oracle element by element (the rounding bound of a <= 8-term row sum is
+~1e-15 of that scale); binary32 products are compared with the oracle applied
+to the binary32-rounded inputs within gamma_k(2^-24) * (|A32||X32|)_il,
+k = longest row.  Integer-valued inputs must agree bitwise.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import U32, abs_bound, f32_matrix, gamma, max_row_len, round32
+from workloads import configs, grids, rng
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def mrhs():
+    import paper_1711_10622_amd as p
+    p.load(build_if_missing=False)
+    return p
+
+
+def gpu_gspmv(mrhs, torch, A, X, dtype=np.float64):
+    M = mrhs.CsrMatrix.from_csr(A)
+    tdt = torch.float64 if dtype == np.float64 else torch.float32
+    Xt = torch.from_numpy(np.ascontiguousarray(X.astype(dtype))).to("cuda", tdt)
+    Y = M.gspmv(Xt)
+    torch.cuda.synchronize()
+    out = Y.cpu().numpy().astype(np.float64)
+    M.close()
+    return out
+
+
+def small_cases():
+    # (matrix, label): several tiles and a ragged tail (n not a multiple of 256)
+    yield grids.dirichlet7(16), "dir16"
+    yield grids.dirichlet7(13, 11, 7), "dir13x11x7"
+    yield grids.channel7(24, 10, 9, beta=2.0), "chan24x10x9"
+    solid = grids.cube_array_solid(48, 24, 32, ncube=2, h=4, pitch_x=24, pitch_z=16, off_x=4, off_z=4)
+    C = grids.channel7(48, 24, 32, beta=2.0, lx=3.0, ly=1.5, lz=2.0, solid=solid)
+    yield grids.permute_symmetric(C, rng.permutation(C.n, 10622)), "cube48_perm"
+
+
+@pytest.mark.parametrize("m", list(range(1, 17)))
+def test_f64_all_m(torch_cuda, mrhs, m):
+    for A, label in small_cases():
+        X = rng.rhs_block(A.n, m, 100 + m)
+        Y = gpu_gspmv(mrhs, torch_cuda, A, X)
+        ref = oracle.gspmv(A, X)
+        bound = abs_bound(A, X)
+        err = np.abs(Y - ref)
+        assert np.all(err <= 1e-13 * bound), (label, m, float((err / np.maximum(bound, 1e-300)).max()))
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 4, 5, 8, 12, 16])
+def test_f32_all_m(torch_cuda, mrhs, m):
+    for A, label in small_cases():
+        X = round32(rng.rhs_block(A.n, m, 200 + m))
+        A32 = f32_matrix(A)
+        Y = gpu_gspmv(mrhs, torch_cuda, A, X, dtype=np.float32)
+        ref = oracle.gspmv(A32, X)
+        bound = abs_bound(A32, X)
+        tol = gamma(max_row_len(A), U32) * bound
+        assert np.all(np.abs(Y - ref) <= tol), (label, m)
+
+
+@pytest.mark.parametrize("m", [1, 4, 7, 16])
+def test_integer_exact_bitwise(torch_cuda, mrhs, m):
+    A = grids.dirichlet7(16)
+    X = rng.int_block(A.n, m, 300 + m, -1000, 1000)
+    ref = oracle.gspmv(A, X)
+    assert np.array_equal(gpu_gspmv(mrhs, torch_cuda, A, X), ref)
+    assert np.array_equal(gpu_gspmv(mrhs, torch_cuda, A, X, dtype=np.float32), ref)
+
+
+def test_block_equals_single_columns_bitwise(torch_cuda, mrhs):
+    A = grids.channel7(24, 10, 9, beta=2.0)
+    X = rng.rhs_block(A.n, 6, 400)
+    Y = gpu_gspmv(mrhs, torch_cuda, A, X)
+    for l in range(6):
+        y = gpu_gspmv(mrhs, torch_cuda, A, np.ascontiguousarray(X[:, l:l + 1]))
+        assert np.array_equal(Y[:, l], y[:, 0])
+
+
+def test_eigenmode_and_symmetry(torch_cuda, mrhs):
+    N = 20
+    A = grids.dirichlet7(N)
+    i = np.arange(N)
+    cols, lams = [], []
+    for a, b, c in [(1, 1, 1), (3, 7, 2), (20, 20, 20)]:
+        v = (np.sin(c * np.pi * (i + 1) / (N + 1))[:, None, None] * np.sin(b * np.pi * (i + 1) / (N + 1))[None, :, None]
+             * np.sin(a * np.pi * (i + 1) / (N + 1))[None, None, :]).ravel()
+        cols.append(v)
+        lams.append(sum(2 - 2 * np.cos(q * np.pi / (N + 1)) for q in (a, b, c)))
+    X = np.stack(cols, axis=1)
+    Y = gpu_gspmv(mrhs, torch_cuda, A, X)
+    assert np.abs(Y - X * np.array(lams)).max() <= 1e-13 * 12
+    C = grids.channel7(16, 12, 10, beta=2.0)
+    X1 = rng.rhs_block(C.n, 2, 401)
+    X2 = rng.rhs_block(C.n, 2, 402)
+    AX1 = gpu_gspmv(mrhs, torch_cuda, C, X1)
+    AX2 = gpu_gspmv(mrhs, torch_cuda, C, X2)
+    assert np.allclose(np.sum(X1 * AX2, 0), np.sum(AX1 * X2, 0), rtol=1e-12)
+
+
+def test_irregular_rows(torch_cuda, mrhs):
+    # empty rows, duplicates, unsorted columns and one very long row that
+    # overflows the LDS staging of its tile
+    n = 700
+    r = np.random.default_rng(5)
+    rows = []
+    for i in range(n):
+        if i % 17 == 3:
+            rows.append(([], []))
+            continue
+        k = 3000 if i == 300 else r.integers(1, 12)
+        c = r.integers(0, n, size=k)
+        c[0] = i
+        rows.append((c, r.standard_normal(k)))
+    rp = np.zeros(n + 1, dtype=np.int32)
+    rp[1:] = np.cumsum([len(c) for c, _ in rows])
+    col = np.concatenate([np.asarray(c, dtype=np.int32) for c, _ in rows])
+    val = np.concatenate([np.asarray(v, dtype=np.float64) for _, v in rows])
+    A = grids.CSRMatrix(n, rp, col, val)
+    for m in (1, 3, 8, 16):
+        X = rng.rhs_block(n, m, 500 + m)
+        Y = gpu_gspmv(mrhs, torch_cuda, A, X)
+        ref = oracle.gspmv(A, X)
+        assert np.all(np.abs(Y - ref) <= 1e-13 * abs_bound(A, X) + 1e-300)
+        assert np.all(Y[3::17] == 0.0)
+
+
+def test_argument_errors(torch_cuda, mrhs):
+    import paper_1711_10622_amd._lib as L
+    A = grids.dirichlet7(4)
+    M = mrhs.CsrMatrix.from_csr(A)
+    X = torch_cuda.zeros((A.n, 2), dtype=torch_cuda.float64, device="cuda")
+    lib = L.load()
+    import ctypes
+    assert lib.gspmv(M.handle, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(X.data_ptr()), 2) == L.EINVAL
+    assert lib.gspmv(M.handle, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(X.data_ptr()), 17) == L.EINVAL
+    assert lib.gspmv(M.handle, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(X.data_ptr()), 0) == L.EINVAL
+    E = mrhs.CsrMatrix(0, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    assert lib.gspmv(E.handle, None, None, 4) == L.OK
+    M.close()
+    E.close()
+
+
+@pytest.mark.parametrize("m", [1, 8, 16])
+def test_full_size_channel_f64(torch_cuda, mrhs, m):
+    """The 128x64x64 stretched channel at full size, every row checked."""
+    A = configs.MATRICES["chan128"]()
+    X = configs.WORKLOADS["chan128"].rhs(A.n, m)
+    Y = gpu_gspmv(mrhs, torch_cuda, A, X)
+    ref = oracle.gspmv(A, X)
+    assert np.all(np.abs(Y - ref) <= 1e-13 * abs_bound(A, X))
+
+
+def test_large_channel_sampled(torch_cuda, mrhs):
+    """The 256x192x256 channel (12.6M rows, m = 16), on 20k sampled rows
+    including the first and last tiles."""
+    A = configs.MATRICES["chan256"]()
+    X = configs.WORKLOADS["chan256"].rhs(A.n, 16)
+    Y = gpu_gspmv(mrhs, torch_cuda, A, X)
+    r = np.random.default_rng(0)
+    rows = np.unique(np.concatenate([np.arange(512), np.arange(A.n - 512, A.n),
+                                     r.integers(0, A.n, size=20000)]))
+    ref = oracle.gspmv_rows(A, X, rows)
+    bound = abs_bound(A, X, rows)
+    assert np.all(np.abs(Y[rows] - ref) <= 1e-13 * bound)

@@ -1,0 +1,155 @@
+"""GPU parity of the block BiCGStab solve (Section 2.2: one matrix, m
+right-hand sides) against the FP64 oracle.
+
+Several solutions satisfy the stopping rule, so parity is: every column's
+true relative residual (recomputed with compensated products) <= tol, the
+solution within kappa * 2 tol of the oracle's (mean-free for the singular
+channel operator), and iteration counts within 10% of the oracle's.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import mean_free, true_relres
+from workloads import configs, grids, rng
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def mrhs():
+    import paper_1711_10622_amd as p
+    p.load(build_if_missing=False)
+    return p
+
+
+def gpu_solve(mrhs, torch, A, B, **kw):
+    M = mrhs.CsrMatrix.from_csr(A)
+    Bt = torch.from_numpy(np.ascontiguousarray(B)).to("cuda")
+    X0 = kw.pop("X0", None)
+    if X0 is not None:
+        kw["X0"] = torch.from_numpy(np.ascontiguousarray(X0)).to("cuda")
+    X, infos, st = M.solve(Bt, **kw)
+    torch.cuda.synchronize()
+    out = X.cpu().numpy()
+    M.close()
+    return out, infos, st
+
+
+def dir16_kappa():
+    N = 16
+    return (2 - 2 * np.cos(N * np.pi / (N + 1))) / (2 - 2 * np.cos(np.pi / (N + 1)))
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_dir16_m4(torch_cuda, mrhs, mixed):
+    A = configs.MATRICES["dir16"]()
+    B = configs.WORKLOADS["dir16"].rhs(A.n, 4)
+    X, infos, st = gpu_solve(mrhs, torch_cuda, A, B, tol=1e-10, mixed=mixed)
+    Xo, io, _ = oracle.bicgstab(A, B, tol=1e-10)
+    assert st == 0
+    rr = true_relres(A, X, B)
+    assert np.all(rr <= 1e-10), rr
+    for l in range(4):
+        assert infos[l]["status"] == 0
+        assert abs(infos[l]["relres"] - rr[l]) <= 1e-3 * rr[l] + 1e-16
+        err = np.linalg.norm(X[:, l] - Xo[:, l]) / np.linalg.norm(Xo[:, l])
+        assert err <= dir16_kappa() * 2e-10
+        if not mixed:
+            assert abs(infos[l]["iters"] - io[l]["iters"]) <= max(2, 0.1 * io[l]["iters"])
+
+
+@pytest.mark.parametrize("m", [1, 3, 8, 16])
+def test_channel_small_all_shapes(torch_cuda, mrhs, m):
+    A = grids.channel7(32, 16, 24, beta=2.0)
+    B = rng.rhs_block(A.n, m, 700 + m, mean_zero=True)
+    X, infos, st = gpu_solve(mrhs, torch_cuda, A, B, tol=1e-10)
+    assert st == 0
+    assert np.all(true_relres(A, X, B) <= 1e-10)
+    assert np.abs(X.mean(axis=0)).max() <= 1e-12 * np.abs(X).max()
+    Xo, io, _ = oracle.bicgstab(A, B[:, :2], tol=1e-10)
+    for l in range(min(m, 2)):
+        assert abs(infos[l]["iters"] - io[l]["iters"]) <= max(3, 0.1 * io[l]["iters"])
+        assert np.linalg.norm(mean_free(X[:, l:l + 1]) - Xo[:, l:l + 1]) <= 1e-6 * np.linalg.norm(Xo[:, l])
+
+
+def test_block_equals_singles(torch_cuda, mrhs):
+    A = grids.dirichlet7(12, 10, 14)
+    B = rng.rhs_block(A.n, 5, 800)
+    X, infos, st = gpu_solve(mrhs, torch_cuda, A, B, tol=1e-11)
+    for l in range(5):
+        x1, i1, _ = gpu_solve(mrhs, torch_cuda, A, np.ascontiguousarray(B[:, l:l + 1]), tol=1e-11)
+        assert abs(i1[0]["iters"] - infos[l]["iters"]) <= 2
+        assert np.linalg.norm(x1[:, 0] - X[:, l]) <= 1e-8 * np.linalg.norm(X[:, l])
+
+
+def test_nan_column_isolated_zero_rhs_and_determinism(torch_cuda, mrhs):
+    A = grids.dirichlet7(10)
+    B = rng.rhs_block(A.n, 4, 900)
+    B[:, 2] = 0.0
+    X1, i1, _ = gpu_solve(mrhs, torch_cuda, A, B, tol=1e-10)
+    X2, _, _ = gpu_solve(mrhs, torch_cuda, A, B, tol=1e-10)
+    assert np.array_equal(X1, X2)                 # bitwise reproducible
+    assert i1[2]["status"] == 0 and i1[2]["iters"] == 0 and np.all(X1[:, 2] == 0)
+    Bn = B.copy()
+    Bn[7, 1] = np.nan
+    Xn, inn, st = gpu_solve(mrhs, torch_cuda, A, Bn, tol=1e-10)
+    assert st == -5 and inn[1]["status"] == -5
+    for l in (0, 3):
+        assert np.array_equal(Xn[:, l], X1[:, l])  # other columns untouched
+
+
+def test_maxit_forced_breakdown_zero_diag(torch_cuda, mrhs):
+    A = grids.dirichlet7(8)
+    B = rng.rhs_block(A.n, 2, 901)
+    X, infos, st = gpu_solve(mrhs, torch_cuda, A, B, tol=1e-10, maxit=1)
+    assert st == -4 and all(i["status"] == -4 and i["iters"] == 1 for i in infos)
+    assert all(0 < i["relres"] < 1 for i in infos)
+    import scipy.sparse as sp
+    D = sp.csr_matrix(np.array([[1.0, -1.25], [-1.25, 1.0]]))
+    A2 = grids.CSRMatrix(2, D.indptr.astype(np.int32), D.indices.astype(np.int32), D.data)
+    X, infos, st = gpu_solve(mrhs, torch_cuda, A2, np.array([[1.0], [2.0]]), tol=1e-10, maxit=50)
+    _, io, _ = oracle.bicgstab(A2, np.array([[1.0], [2.0]]), tol=1e-10, maxit=50)
+    assert st == -5 and infos[0]["status"] == -5
+    assert infos[0]["iters"] == io[0]["iters"] == 4 and infos[0]["restarts"] == io[0]["restarts"] == 3
+    Z = sp.csr_matrix(np.array([[0.0, 1.0], [1.0, 2.0]]))
+    A3 = grids.CSRMatrix(2, Z.indptr.astype(np.int32), Z.indices.astype(np.int32), Z.data)
+    import paper_1711_10622_amd as p
+    with pytest.raises(p.MrhsError):
+        gpu_solve(mrhs, torch_cuda, A3, np.ones((2, 1)))
+
+
+def test_initial_guess(torch_cuda, mrhs):
+    A = grids.dirichlet7(9)
+    xs = rng.int_block(A.n, 3, 902, -5, 5)
+    B = oracle.gspmv(A, xs)
+    X, infos, st = gpu_solve(mrhs, torch_cuda, A, B, tol=1e-10, X0=xs)
+    assert st == 0 and all(i["iters"] == 0 for i in infos)
+    assert np.array_equal(X, xs)
+    for mixed in (False, True):
+        X, infos, st = gpu_solve(mrhs, torch_cuda, A, B, tol=1e-10, X0=xs + 0.01, mixed=mixed)
+        assert st == 0 and np.all(true_relres(A, X, B) <= 1e-10)
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_channel_full_m16(torch_cuda, mrhs, mixed):
+    """The 128x64x64 stretched channel at full size with m = 16."""
+    A = configs.MATRICES["chan128"]()
+    B = configs.WORKLOADS["chan128"].rhs(A.n, 16)
+    X, infos, st = gpu_solve(mrhs, torch_cuda, A, B, tol=1e-10, maxit=20000, mixed=mixed)
+    assert st == 0, infos
+    rr = true_relres(A, X, B)
+    assert np.all(rr <= 1e-10), rr
+    Xo, io, _ = oracle.bicgstab(A, B[:, :2], tol=1e-10, threads=2)
+    for l in range(2):
+        err = np.linalg.norm(X[:, l] - Xo[:, l]) / np.linalg.norm(Xo[:, l])
+        assert err <= 1e-5, err
+        if not mixed:
+            assert abs(infos[l]["iters"] - io[l]["iters"]) <= 0.1 * io[l]["iters"]
