@@ -155,6 +155,19 @@ mrhs_status block_bicgstab_ex(mrhs_csr A, const double *B, double *X, int32_t m,
 mrhs_status block_bicgstab_workspace_size(mrhs_csr A, int32_t m, uint32_t flags,
                                           size_t *bytes);
 
+/*
+ * Kernel timing.  mrhs_trace_enable(1) clears the statistics and starts
+ * bracketing every kernel launch of the library with a pair of HIP events on
+ * the launch's own stream; mrhs_trace_enable(0) stops.  mrhs_trace_read
+ * waits for the recorded events and writes a NUL-terminated JSON object
+ * {"<kernel>/<f64|f32>/m<M>/g<grid>": {"launches", "total_ms", "min_ms",
+ * "max_ms"}, ...} into buf (cap bytes); *len receives the length needed
+ * (without the NUL).  EINVAL if the text did not fit (it is truncated).
+ * Not for use while other threads launch library kernels.
+ */
+mrhs_status mrhs_trace_enable(int on);
+mrhs_status mrhs_trace_read(char *buf, size_t cap, size_t *len);
+
 #ifdef __cplusplus
 }
 #endif

@@ -24,6 +24,7 @@ X0_GIVEN, MIXED = 1, 2
 EXPORTS = (
     "mrhs_last_error", "mrhs_version", "csr_create", "csr_destroy", "csr_info", "gspmv", "gspmv_ex",
     "block_bicgstab", "block_bicgstab_ex", "block_bicgstab_workspace_size",
+    "mrhs_trace_enable", "mrhs_trace_read",
 )
 
 
@@ -61,6 +62,8 @@ def _declare(lib):
         "block_bicgstab": [vp, vp, vp, i32, f64, i32],
         "block_bicgstab_ex": [vp, vp, vp, i32, f64, i32, u32, vp, sz, vp, c.POINTER(ColInfo)],
         "block_bicgstab_workspace_size": [vp, i32, u32, c.POINTER(sz)],
+        "mrhs_trace_enable": [c.c_int],
+        "mrhs_trace_read": [c.c_char_p, sz, c.POINTER(sz)],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)

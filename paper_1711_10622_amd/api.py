@@ -156,3 +156,19 @@ def gspmv(A: CsrMatrix, X, out=None, stream=None):
 
 def block_bicgstab(A: CsrMatrix, B, tol=1e-10, maxit=20000, mixed=False, **kw):
     return A.solve(B, tol=tol, maxit=maxit, mixed=mixed, **kw)
+
+
+def trace_enable(on: bool = True):
+    """Start (clearing old statistics) or stop per-launch kernel timing."""
+    _lib.check(_lib.load().mrhs_trace_enable(1 if on else 0), "mrhs_trace_enable")
+
+
+def trace_read() -> dict:
+    """Per-kernel-class launch counts and durations recorded since trace_enable."""
+    import json
+    lib = _lib.load()
+    need = ctypes.c_size_t()
+    _lib.check(lib.mrhs_trace_read(None, 0, ctypes.byref(need)), "mrhs_trace_read")
+    buf = ctypes.create_string_buffer(need.value + 1)
+    _lib.check(lib.mrhs_trace_read(buf, need.value + 1, ctypes.byref(need)), "mrhs_trace_read")
+    return json.loads(buf.value.decode())

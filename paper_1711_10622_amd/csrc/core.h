@@ -30,24 +30,48 @@
 
 namespace mrhs {
 
+#ifndef MRHS_TILE_ROWS
+#define MRHS_TILE_ROWS 256
+#endif
+#ifndef MRHS_NZ_PER_ROW
+#define MRHS_NZ_PER_ROW 8
+#endif
+#ifndef MRHS_GATHER_BATCH
+#define MRHS_GATHER_BATCH 8
+#endif
+#ifndef MRHS_XCD_GROUPS
+#define MRHS_XCD_GROUPS 1
+#endif
+
 constexpr int kBlock = 256;
-constexpr int kTileRows = 256;
-constexpr int kNzCap = 2048;  // staged nonzeros per tile (8 per row on average)
+constexpr int kTileRows = MRHS_TILE_ROWS;
+constexpr int kNzCap = MRHS_TILE_ROWS * MRHS_NZ_PER_ROW;  // staged nonzeros per tile
 constexpr int kGroups = 8;
 constexpr int kMaxM = 16;
-constexpr int kMaxDots = 3;
+constexpr int kMaxDots = 8;  // largest NDOT of any reduction (GCR projections)
 
 constexpr int next_pow2(int x) { return x <= 1 ? 1 : 2 * next_pow2((x + 1) / 2); }
 
+#ifndef MRHS_WIDE
+#define MRHS_WIDE 0
+#endif
+
 template <typename T, int M>
 struct Shape {
+#if MRHS_WIDE
+    static constexpr int VW = std::is_same<T, double>::value
+                                  ? (M % 4 == 0 ? 4 : (M % 2 == 0 ? 2 : 1))
+                                  : (M % 8 == 0 ? 8 : (M % 4 == 0 ? 4 : (M % 2 == 0 ? 2 : 1)));
+#else
     static constexpr int VW = std::is_same<T, double>::value ? (M % 2 == 0 ? 2 : 1)
                                                              : (M % 4 == 0 ? 4 : (M % 2 == 0 ? 2 : 1));
+#endif
     static constexpr int G = M / VW;       // lanes that hold data in a row
     static constexpr int L = next_pow2(G); // lanes per row
     static constexpr int RPP = kBlock / L; // rows per pass of the workgroup
     static constexpr int PASSES = kTileRows / RPP;
     static_assert(G * VW == M, "lane width must divide M");
+    static_assert(PASSES >= 1 && PASSES * RPP == kTileRows, "a tile must hold whole passes");
     static_assert(L <= 64, "a row must fit one wave");
 };
 
@@ -59,6 +83,7 @@ template <typename T>
 struct Vec<T, 1> {
     static __device__ __forceinline__ void load(const T *p, T *v) { v[0] = *p; }
     static __device__ __forceinline__ void store(T *p, const T *v) { *p = v[0]; }
+    static __device__ __forceinline__ void store_nt(T *p, const T *v) { __builtin_nontemporal_store(v[0], p); }
 };
 
 template <>
@@ -77,6 +102,13 @@ struct Vec<double, 2> {
         t.y = v[1];
         *reinterpret_cast<v2 *>(p) = t;
     }
+    static __device__ __forceinline__ void store_nt(double *p, const double *v)
+    {
+        v2 t;
+        t.x = v[0];
+        t.y = v[1];
+        __builtin_nontemporal_store(t, reinterpret_cast<v2 *>(p));
+    }
 };
 
 template <>
@@ -94,6 +126,13 @@ struct Vec<float, 2> {
         t.x = v[0];
         t.y = v[1];
         *reinterpret_cast<v2 *>(p) = t;
+    }
+    static __device__ __forceinline__ void store_nt(float *p, const float *v)
+    {
+        v2 t;
+        t.x = v[0];
+        t.y = v[1];
+        __builtin_nontemporal_store(t, reinterpret_cast<v2 *>(p));
     }
 };
 
@@ -117,6 +156,75 @@ struct Vec<float, 4> {
         t.w = v[3];
         *reinterpret_cast<v4 *>(p) = t;
     }
+    static __device__ __forceinline__ void store_nt(float *p, const float *v)
+    {
+        v4 t;
+        t.x = v[0];
+        t.y = v[1];
+        t.z = v[2];
+        t.w = v[3];
+        __builtin_nontemporal_store(t, reinterpret_cast<v4 *>(p));
+    }
+};
+
+// Address of element (row, col0) of an n x M row-interleaved block.  With
+// MRHS_OFF32 the byte offset is formed in 32 bits (blocks under 4 GiB), which
+// lets the compiler address with a scalar base and one offset register.
+template <typename T, int M>
+__device__ __forceinline__ const T *blk(const T *base, int32_t row, int col0)
+{
+#ifdef MRHS_OFF32
+    const uint32_t off = static_cast<uint32_t>(row) * static_cast<uint32_t>(M * sizeof(T)) +
+                         static_cast<uint32_t>(col0 * sizeof(T));
+    return reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + off);
+#else
+    return base + static_cast<size_t>(row) * M + col0;
+#endif
+}
+
+template <typename T, int M>
+__device__ __forceinline__ T *blk(T *base, int32_t row, int col0)
+{
+    return const_cast<T *>(blk<T, M>(const_cast<const T *>(base), row, col0));
+}
+
+// 32-byte lanes: two 16-byte accesses
+template <>
+struct Vec<double, 4> {
+    static __device__ __forceinline__ void load(const double *p, double *v)
+    {
+        Vec<double, 2>::load(p, v);
+        Vec<double, 2>::load(p + 2, v + 2);
+    }
+    static __device__ __forceinline__ void store(double *p, const double *v)
+    {
+        Vec<double, 2>::store(p, v);
+        Vec<double, 2>::store(p + 2, v + 2);
+    }
+    static __device__ __forceinline__ void store_nt(double *p, const double *v)
+    {
+        Vec<double, 2>::store_nt(p, v);
+        Vec<double, 2>::store_nt(p + 2, v + 2);
+    }
+};
+
+template <>
+struct Vec<float, 8> {
+    static __device__ __forceinline__ void load(const float *p, float *v)
+    {
+        Vec<float, 4>::load(p, v);
+        Vec<float, 4>::load(p + 4, v + 4);
+    }
+    static __device__ __forceinline__ void store(float *p, const float *v)
+    {
+        Vec<float, 4>::store(p, v);
+        Vec<float, 4>::store(p + 4, v + 4);
+    }
+    static __device__ __forceinline__ void store_nt(float *p, const float *v)
+    {
+        Vec<float, 4>::store_nt(p, v);
+        Vec<float, 4>::store_nt(p + 4, v + 4);
+    }
 };
 
 // ---- tile schedule ------------------------------------------------------------
@@ -126,6 +234,9 @@ struct TileRange {
 
 __device__ __forceinline__ TileRange tile_range(int64_t ntiles)
 {
+#if !MRHS_XCD_GROUPS
+    return {blockIdx.x, ntiles, gridDim.x};
+#endif
     const int b = blockIdx.x;
     const int grp = b % kGroups;
     const int q = b / kGroups;
@@ -145,37 +256,39 @@ struct CsrView {
 };
 
 // One row of the product: sum over the row's entries in storage order of
-// val[j] * Xrow(col[j]) for this lane's VW columns.  Four entries are issued
-// together so their gathers overlap.
+// val[j] * Xrow(col[j]) for this lane's VW columns.  Entries are taken NB at a
+// time and all NB gathers are issued before any is consumed, so a stencil row
+// costs one memory round trip.  Slots past the row's end re-read the row's
+// last entry (always a valid index, a cache hit) and are not accumulated.
 template <typename T, int VW, class Op, typename PI, typename PV>
 __device__ __forceinline__ void row_product(PI cis, PV vas, int j0, int j1, int g, const Op &op,
                                             const typename Op::Lane &ln, T *sum)
 {
-    int j = j0;
-    for (; j + 4 <= j1; j += 4) {
-        const int32_t c0 = cis[j], c1 = cis[j + 1], c2 = cis[j + 2], c3 = cis[j + 3];
-        const T a0 = vas[j], a1 = vas[j + 1], a2 = vas[j + 2], a3 = vas[j + 3];
-        T x0[VW], x1[VW], x2[VW], x3[VW];
-        op.gather(ln, c0, g, x0);
-        op.gather(ln, c1, g, x1);
-        op.gather(ln, c2, g, x2);
-        op.gather(ln, c3, g, x3);
+    constexpr int NB = MRHS_GATHER_BATCH;
+    for (int j = j0; j < j1; j += NB) {
+        int32_t c[NB];
+        T a[NB], x[NB][VW];
+        bool ok[NB];
 #pragma unroll
-        for (int v = 0; v < VW; ++v) {
-            sum[v] += a0 * x0[v];
-            sum[v] += a1 * x1[v];
-            sum[v] += a2 * x2[v];
-            sum[v] += a3 * x3[v];
+        for (int k = 0; k < NB; ++k) {
+            ok[k] = j + k < j1;
+            const int jj = ok[k] ? j + k : j1 - 1;
+#ifdef MRHS_DIAG_LOCAL
+            c[k] = cis[j0 + (j1 - j0) / 2];
+#else
+            c[k] = cis[jj];
+#endif
+            a[k] = vas[jj];
         }
-    }
-    for (; j < j1; ++j) {
-        const int32_t c = cis[j];
-        const T a = vas[j];
-        T x[VW];
-        op.gather(ln, c, g, x);
 #pragma unroll
-        for (int v = 0; v < VW; ++v)
-            sum[v] += a * x[v];
+        for (int k = 0; k < NB; ++k)
+            op.gather(ln, c[k], g, x[k]);
+#pragma unroll
+        for (int k = 0; k < NB; ++k)
+#pragma unroll
+            for (int v = 0; v < VW; ++v)
+                if (ok[k])
+                    sum[v] += a[k] * x[k][v];
     }
 }
 
@@ -204,8 +317,8 @@ __device__ __forceinline__ void gspmv_tiles(const CsrView<T> &A, const Op &op,
 {
     using S = Shape<T, M>;
     __shared__ int32_t s_rp[kTileRows + 1];
-    __shared__ int32_t s_ci[kNzCap];
-    __shared__ T s_va[kNzCap];
+    __shared__ __align__(16) int32_t s_ci[kNzCap + 4];
+    __shared__ __align__(16) T s_va[kNzCap + 4];
     const int tid = threadIdx.x;
     const int g = tid % S::L;
     const int rl = tid / S::L;
@@ -221,14 +334,108 @@ __device__ __forceinline__ void gspmv_tiles(const CsrView<T> &A, const Op &op,
         __syncthreads();
         const int32_t z0 = s_rp[0];
         const int cnt = s_rp[nr] - z0;
-        const bool staged = cnt <= kNzCap;
+        // 16-byte loads from the 4-aligned index zb <= z0 (the matrix arrays
+        // carry 4 elements of padding, so whole vectors stay in bounds); every
+        // thread issues all of its loads before writing any of them to LDS
+        const int32_t zb = z0 & ~3;
+        const int lead = z0 - zb;
+        const bool staged = cnt + lead <= kNzCap;
         if (staged) {
-            for (int k = tid; k < cnt; k += kBlock) {
-                s_ci[k] = __builtin_nontemporal_load(A.ci + z0 + k);
-                s_va[k] = __builtin_nontemporal_load(A.va + z0 + k);
+            using I4 = int __attribute__((ext_vector_type(4)));
+            constexpr int VV = 16 / static_cast<int>(sizeof(T));
+            using TV = T __attribute__((ext_vector_type(VV)));
+            constexpr int CI_PT = ((kNzCap + 4) / 4 + kBlock - 1) / kBlock;
+            constexpr int VA_PT = ((kNzCap + 4) / VV + kBlock - 1) / kBlock;
+            const int nci = (cnt + lead + 3) / 4;
+            const int nva = (cnt + lead + VV - 1) / VV;
+            const I4 *gci = reinterpret_cast<const I4 *>(A.ci + zb);
+            const TV *gva = reinterpret_cast<const TV *>(A.va + zb);
+            I4 bci[CI_PT];
+            TV bva[VA_PT];
+#pragma unroll
+            for (int u = 0; u < CI_PT; ++u) {
+                const int k = tid + u * kBlock;
+                if (k < nci)
+                    bci[u] = __builtin_nontemporal_load(gci + k);
+            }
+#pragma unroll
+            for (int u = 0; u < VA_PT; ++u) {
+                const int k = tid + u * kBlock;
+                if (k < nva)
+                    bva[u] = __builtin_nontemporal_load(gva + k);
+            }
+#pragma unroll
+            for (int u = 0; u < CI_PT; ++u) {
+                const int k = tid + u * kBlock;
+                if (k < nci)
+                    reinterpret_cast<I4 *>(s_ci)[k] = bci[u];
+            }
+#pragma unroll
+            for (int u = 0; u < VA_PT; ++u) {
+                const int k = tid + u * kBlock;
+                if (k < nva)
+                    reinterpret_cast<TV *>(s_va)[k] = bva[u];
             }
         }
         __syncthreads();
+        const int32_t *lci = s_ci + lead;
+        const T *lva = s_va + lead;
+#ifdef MRHS_PIPE2
+        if (staged) {  // uniform over the workgroup: one barrier on every path
+          if (lane_on) {
+            // two passes in flight: the gathers of pass p+1 are issued before
+            // pass p is consumed; rows longer than NB finish in row_product
+            constexpr int NB = MRHS_GATHER_BATCH;
+            int32_t cc[2][NB];
+            T aa[2][NB], xx[2][NB][S::VW];
+            int jj0[2], jj1[2];
+            auto issue = [&](int slot, int p) {
+                const int row_l = p * S::RPP + rl;
+                const bool live = row_l < nr;
+                const int j0 = live ? s_rp[row_l] - z0 : 0;
+                const int j1 = live ? s_rp[row_l + 1] - z0 : 0;
+                jj0[slot] = j0;
+                jj1[slot] = j1;
+#pragma unroll
+                for (int k = 0; k < NB; ++k) {
+                    const bool ok = j0 + k < j1;
+                    const int j = ok ? j0 + k : (j1 > j0 ? j1 - 1 : -1);
+                    cc[slot][k] = j >= 0 ? lci[j] : -1;
+                    aa[slot][k] = (ok && j >= 0) ? lva[j] : T(0);
+                }
+#pragma unroll
+                for (int k = 0; k < NB; ++k)
+                    if (cc[slot][k] >= 0)
+                        op.gather(ln, cc[slot][k], g, xx[slot][k]);
+            };
+            issue(0, 0);
+#pragma unroll
+            for (int p = 0; p < S::PASSES; ++p) {
+                const int cur = p & 1;
+                if (p + 1 < S::PASSES)
+                    issue(cur ^ 1, p + 1);
+                const int row_l = p * S::RPP + rl;
+                if (row_l < nr) {
+                    T sum[S::VW];
+#pragma unroll
+                    for (int v = 0; v < S::VW; ++v)
+                        sum[v] = T(0);
+#pragma unroll
+                    for (int k = 0; k < NB; ++k)
+#pragma unroll
+                        for (int v = 0; v < S::VW; ++v)
+                            if (jj0[cur] + k < jj1[cur])
+                                sum[v] += aa[cur][k] * xx[cur][k][v];
+                    if (jj1[cur] - jj0[cur] > NB)
+                        row_product<T, S::VW>(lci, lva, jj0[cur] + NB, jj1[cur], g, op, ln, sum);
+                    op.row(ln, r0 + row_l, g, sum, acc);
+                }
+            }
+          }
+          __syncthreads();
+          continue;
+        }
+#endif
 #pragma unroll 1
         for (int p = 0; p < S::PASSES; ++p) {
             const int row_l = p * S::RPP + rl;
@@ -240,7 +447,7 @@ __device__ __forceinline__ void gspmv_tiles(const CsrView<T> &A, const Op &op,
                 for (int v = 0; v < S::VW; ++v)
                     sum[v] = T(0);
                 if (staged)
-                    row_product<T, S::VW>(s_ci, s_va, j0, j1, g, op, ln, sum);
+                    row_product<T, S::VW>(lci, lva, j0, j1, g, op, ln, sum);
                 else
                     row_product<T, S::VW>(A.ci + z0, A.va + z0, j0, j1, g, op, ln, sum);
                 op.row(ln, r0 + row_l, g, sum, acc);
@@ -276,6 +483,61 @@ __device__ __forceinline__ void stream_tiles(int32_t n, const Op &op,
                 op.row(ln, r0 + row_l, g, acc);
         }
     }
+}
+
+// ---- cross-workgroup publication without device-wide fences ----------------
+// The L2 of each XCD is not coherent with the others, so a device-scope fence
+// must write back and invalidate a whole L2: a per-workgroup fence serialises
+// badly.  Values that another workgroup must read are instead stored and
+// loaded with agent-scope atomics (they bypass the non-coherent caches), and
+// ordering against the ticket counter only needs each thread's own memory
+// operations to have completed (vmcnt = 0) plus a workgroup-scope fence that
+// keeps the compiler from reordering across it.
+template <typename T>
+struct Bits;
+template <>
+struct Bits<double> {
+    using U = unsigned long long;
+};
+template <>
+struct Bits<float> {
+    using U = unsigned int;
+};
+
+template <typename T>
+__device__ __forceinline__ void publish(T *p, T v)
+{
+    using U = typename Bits<T>::U;
+    __hip_atomic_store(reinterpret_cast<U *>(p), __builtin_bit_cast(U, v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+__device__ __forceinline__ T fetch_published(const T *p)
+{
+    using U = typename Bits<T>::U;
+    return __builtin_bit_cast(T, __hip_atomic_load(reinterpret_cast<const U *>(p), __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT));
+}
+
+// vmcnt(0), expcnt/lgkmcnt unconstrained (gfx9 s_waitcnt encoding)
+#define MRHS_WAIT_VMEM() __builtin_amdgcn_s_waitcnt(0 | (0x7 << 4) | (0xf << 8))
+
+__device__ __forceinline__ void release_order()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    MRHS_WAIT_VMEM();
+}
+
+__device__ __forceinline__ void acquire_order()
+{
+    MRHS_WAIT_VMEM();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__device__ __forceinline__ unsigned take_ticket(unsigned *t)
+{
+    return __hip_atomic_fetch_add(t, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---- deterministic grid reduction ------------------------------------------
@@ -331,23 +593,23 @@ __device__ __forceinline__ void grid_reduce(Acc<T, Shape<T, M>::VW, NDOT> &acc, 
 #pragma unroll
         for (int w = 1; w < kBlock / 64; ++w)
             s += s_w[w][tid];
-        rb.part[static_cast<size_t>(b) * V + tid] = s;
+        publish(&rb.part[static_cast<size_t>(b) * V + tid], s);
+        release_order();
     }
-    __threadfence();
     __syncthreads();
     if (tid == 0)
-        s_flag = atomicAdd(&rb.tickets[grp], 1u) == static_cast<unsigned>(gx - 1);
+        s_flag = take_ticket(&rb.tickets[grp]) == static_cast<unsigned>(gx - 1);
     __syncthreads();
     if (!s_flag)
         return;
-    __threadfence();
+    acquire_order();
     // this workgroup is the last of its group: sum the group's partials
     if (tid < TPV * V) {
         const int v = tid % V;
         const int k = tid / V;
         T s = T(0);
         for (int q = k; q < gx; q += TPV)
-            s += rb.part[static_cast<size_t>(grp + q * kGroups) * V + v];
+            s += fetch_published(&rb.part[static_cast<size_t>(grp + q * kGroups) * V + v]);
         s_k[k][v] = s;
     }
     __syncthreads();
@@ -355,25 +617,25 @@ __device__ __forceinline__ void grid_reduce(Acc<T, Shape<T, M>::VW, NDOT> &acc, 
         T s = s_k[0][tid];
         for (int k = 1; k < TPV; ++k)
             s += s_k[k][tid];
-        rb.gpart[grp * V + tid] = s;
+        publish(&rb.gpart[grp * V + tid], s);
+        release_order();
     }
-    __threadfence();
     __syncthreads();
     if (tid == 0)
-        s_flag = atomicAdd(&rb.tickets[kGroups], 1u) == static_cast<unsigned>(kGroups - 1);
+        s_flag = take_ticket(&rb.tickets[kGroups]) == static_cast<unsigned>(kGroups - 1);
     __syncthreads();
     if (!s_flag)
         return;
-    __threadfence();
+    acquire_order();
     if (tid < V) {
-        T s = rb.gpart[tid];
+        T s = fetch_published(&rb.gpart[tid]);
 #pragma unroll
         for (int x = 1; x < kGroups; ++x)
-            s += rb.gpart[x * V + tid];
+            s += fetch_published(&rb.gpart[x * V + tid]);
         s_tot[tid] = s;
     }
     if (tid <= kGroups)
-        rb.tickets[tid] = 0u;
+        __hip_atomic_store(&rb.tickets[tid], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     op.finish(s_tot);
 }

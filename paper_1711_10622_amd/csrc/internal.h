@@ -82,12 +82,22 @@ __global__ void __launch_bounds__(kBlock) k_stream(int32_t n, Op op, RedBufs<T> 
         grid_reduce<T, M, Op::NDOT>(acc, rb, op);
 }
 
+// ---- optional per-launch timing (mrhs_trace_enable) ---------------------
+// When enabled, every kernel launch is bracketed by a pair of HIP events on
+// its own stream; mrhs_trace_read aggregates the durations per kernel class.
+extern bool g_trace_on;
+int trace_begin(hipStream_t s);
+void trace_end(int slot, hipStream_t s, const char *name, int elem_bytes, int m, int grid);
+
 template <typename T, int M, class Op>
 inline hipError_t launch_gspmv(const CsrView<T> &A, const Op &op, const RedBufs<T> &rb, hipStream_t s)
 {
     const void *fn = reinterpret_cast<const void *>(&k_gspmv<T, M, Op>);
     const int grid = grid_for(fn, A.n);
+    const int slot = g_trace_on ? trace_begin(s) : -1;
     hipLaunchKernelGGL((k_gspmv<T, M, Op>), dim3(grid), dim3(kBlock), 0, s, A, op, rb);
+    if (slot >= 0)
+        trace_end(slot, s, Op::kName, static_cast<int>(sizeof(T)), M, grid);
     return hipGetLastError();
 }
 
@@ -96,7 +106,10 @@ inline hipError_t launch_stream(int32_t n, const Op &op, const RedBufs<T> &rb, h
 {
     const void *fn = reinterpret_cast<const void *>(&k_stream<T, M, Op>);
     const int grid = grid_for(fn, n);
+    const int slot = g_trace_on ? trace_begin(s) : -1;
     hipLaunchKernelGGL((k_stream<T, M, Op>), dim3(grid), dim3(kBlock), 0, s, n, op, rb);
+    if (slot >= 0)
+        trace_end(slot, s, Op::kName, static_cast<int>(sizeof(T)), M, grid);
     return hipGetLastError();
 }
 

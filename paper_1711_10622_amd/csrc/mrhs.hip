@@ -75,10 +75,104 @@ int grid_for(const void *kernel, int64_t n)
         per_cu = it->second;
     }
     const int64_t ntiles = (n + kTileRows - 1) / kTileRows;
+#ifdef MRHS_GRID_ALL_TILES  // tuning experiments of the reduction-free product only
+    int64_t g = ntiles;
+#else
     int64_t g = std::min<int64_t>(ntiles, static_cast<int64_t>(per_cu) * cus);
+#endif
     g = std::max<int64_t>(g, 1);
     g = (g + kGroups - 1) / kGroups * kGroups;
     return static_cast<int>(g);
+}
+
+// ---- launch tracing ---------------------------------------------------------
+bool g_trace_on = false;
+
+namespace {
+
+struct TraceRec {
+    hipEvent_t a = nullptr, b = nullptr;
+    std::string key;
+    bool open = false;
+};
+
+struct TraceStat {
+    int64_t launches = 0;
+    double total_ms = 0.0, min_ms = 1e300, max_ms = 0.0;
+};
+
+std::mutex g_trace_mu;
+std::unordered_map<int, TraceRec> g_trace_recs;  // by slot id
+int g_trace_next = 0;
+std::vector<std::pair<hipEvent_t, hipEvent_t>> g_trace_pool;
+std::vector<std::pair<std::string, TraceStat>> g_trace_stats;
+
+TraceStat &trace_stat(const std::string &key)
+{
+    for (auto &kv : g_trace_stats)
+        if (kv.first == key)
+            return kv.second;
+    g_trace_stats.emplace_back(key, TraceStat{});
+    return g_trace_stats.back().second;
+}
+
+// Folds every completed record into the statistics (events are synchronised).
+void trace_drain_locked()
+{
+    for (auto it = g_trace_recs.begin(); it != g_trace_recs.end();) {
+        TraceRec &r = it->second;
+        if (r.open) {
+            ++it;
+            continue;
+        }
+        float ms = 0.0f;
+        if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            TraceStat &st = trace_stat(r.key);
+            st.launches += 1;
+            st.total_ms += ms;
+            st.min_ms = std::min<double>(st.min_ms, ms);
+            st.max_ms = std::max<double>(st.max_ms, ms);
+        }
+        g_trace_pool.emplace_back(r.a, r.b);
+        it = g_trace_recs.erase(it);
+    }
+}
+
+} // namespace
+
+int trace_begin(hipStream_t s)
+{
+    std::lock_guard<std::mutex> lk(g_trace_mu);
+    TraceRec r;
+    if (!g_trace_pool.empty()) {
+        r.a = g_trace_pool.back().first;
+        r.b = g_trace_pool.back().second;
+        g_trace_pool.pop_back();
+    } else if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) {
+        return -1;
+    }
+    r.open = true;
+    (void)hipEventRecord(r.a, s);
+    const int slot = g_trace_next;
+    g_trace_next = (g_trace_next + 1) & 0x3fffffff;
+    g_trace_recs[slot] = r;
+    return slot;
+}
+
+void trace_end(int slot, hipStream_t s, const char *name, int elem_bytes, int m, int grid)
+{
+    std::lock_guard<std::mutex> lk(g_trace_mu);
+    auto it = g_trace_recs.find(slot);
+    if (it == g_trace_recs.end())
+        return;
+    TraceRec &r = it->second;
+    (void)hipEventRecord(r.b, s);
+    char key[128];
+    std::snprintf(key, sizeof(key), "%s/%s/m%d/g%d", name, elem_bytes == 8 ? "f64" : "f32", m, grid);
+    r.key = key;
+    r.open = false;
+    if (g_trace_recs.size() >= 4096)
+        trace_drain_locked();
 }
 
 namespace {
@@ -129,6 +223,8 @@ mrhs_status dev_alloc(T **p, size_t count, size_t &total)
     total += bytes;
     return MRHS_OK;
 }
+
+constexpr size_t kPad = 4;  // elements of padding after the nnz entries
 
 bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
@@ -217,11 +313,11 @@ MRHS_API mrhs_status csr_create(int32_t n, int64_t nnz, const int32_t *row_ptr, 
     size_t total = 0;
     mrhs_status st = MRHS_OK;
     if ((st = dev_alloc(&A->rp, static_cast<size_t>(n) + 1, total)) ||
-        (st = dev_alloc(&A->ci, static_cast<size_t>(nnz), total)) ||
-        (st = dev_alloc(&A->val, static_cast<size_t>(nnz), total)) ||
-        (st = dev_alloc(&A->valh, static_cast<size_t>(nnz), total)) ||
-        (st = dev_alloc(&A->val32, static_cast<size_t>(nnz), total)) ||
-        (st = dev_alloc(&A->valh32, static_cast<size_t>(nnz), total)) ||
+        (st = dev_alloc(&A->ci, static_cast<size_t>(nnz) + kPad, total)) ||
+        (st = dev_alloc(&A->val, static_cast<size_t>(nnz) + kPad, total)) ||
+        (st = dev_alloc(&A->valh, static_cast<size_t>(nnz) + kPad, total)) ||
+        (st = dev_alloc(&A->val32, static_cast<size_t>(nnz) + kPad, total)) ||
+        (st = dev_alloc(&A->valh32, static_cast<size_t>(nnz) + kPad, total)) ||
         (st = dev_alloc(&A->diag, static_cast<size_t>(n), total)) ||
         (st = dev_alloc(&A->dinv, static_cast<size_t>(n), total))) {
         free_csr(A);
@@ -229,6 +325,15 @@ MRHS_API mrhs_status csr_create(int32_t n, int64_t nnz, const int32_t *row_ptr, 
     }
     A->bytes = total;
     hipError_t e = hipSuccess;
+    // the padding past nnz is read (never used) by whole-vector tile loads
+    if ((e = hipMemset(A->ci + nnz, 0, sizeof(int32_t) * kPad)) ||
+        (e = hipMemset(A->val + nnz, 0, sizeof(double) * kPad)) ||
+        (e = hipMemset(A->valh + nnz, 0, sizeof(double) * kPad)) ||
+        (e = hipMemset(A->val32 + nnz, 0, sizeof(float) * kPad)) ||
+        (e = hipMemset(A->valh32 + nnz, 0, sizeof(float) * kPad))) {
+        free_csr(A);
+        return set_error(MRHS_EDEVICE, "padding fill failed: %s", hipGetErrorString(e));
+    }
     if ((e = hipMemcpy(A->rp, row_ptr, sizeof(int32_t) * (static_cast<size_t>(n) + 1), hipMemcpyHostToDevice)) ||
         (nnz > 0 && (e = hipMemcpy(A->ci, col_idx, sizeof(int32_t) * nnz, hipMemcpyHostToDevice))) ||
         (nnz > 0 && (e = hipMemcpy(A->val, val, sizeof(double) * nnz, hipMemcpyHostToDevice))) ||
@@ -365,4 +470,43 @@ MRHS_API mrhs_status block_bicgstab_ex(mrhs_csr A, const double *B, double *X, i
 MRHS_API mrhs_status block_bicgstab(mrhs_csr A, const double *B, double *X, int32_t m, double tol, int32_t maxit)
 {
     return block_bicgstab_ex(A, B, X, m, tol, maxit, 0u, nullptr, 0, nullptr, nullptr);
+}
+
+MRHS_API mrhs_status mrhs_trace_enable(int on)
+{
+    clear_error();
+    std::lock_guard<std::mutex> lk(g_trace_mu);
+    trace_drain_locked();
+    if (on)
+        g_trace_stats.clear();
+    g_trace_on = on != 0;
+    return MRHS_OK;
+}
+
+MRHS_API mrhs_status mrhs_trace_read(char *buf, size_t cap, size_t *len)
+{
+    clear_error();
+    std::lock_guard<std::mutex> lk(g_trace_mu);
+    trace_drain_locked();
+    std::string out = "{";
+    bool first = true;
+    for (const auto &kv : g_trace_stats) {
+        char item[320];
+        std::snprintf(item, sizeof(item), "%s\"%s\": {\"launches\": %lld, \"total_ms\": %.6f, \"min_ms\": %.6f, \"max_ms\": %.6f}",
+                      first ? "" : ", ", kv.first.c_str(), static_cast<long long>(kv.second.launches),
+                      kv.second.total_ms, kv.second.min_ms, kv.second.max_ms);
+        out += item;
+        first = false;
+    }
+    out += "}";
+    if (len)
+        *len = out.size();
+    if (buf && cap > 0) {
+        const size_t k = std::min(cap - 1, out.size());
+        std::memcpy(buf, out.data(), k);
+        buf[k] = '\0';
+        if (k < out.size())
+            return set_error(MRHS_EINVAL, "buffer of %zu bytes too small for %zu", cap, out.size() + 1);
+    }
+    return MRHS_OK;
 }

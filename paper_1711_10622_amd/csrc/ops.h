@@ -41,8 +41,8 @@ enum ColStatus : int32_t {
     COL_DONE = 4,        // converged (true residual)
     COL_NOCONV = 5,      // maxit reached
     COL_BREAKDOWN = 6,   // breakdown persisted / non-finite data
-    COL_INNER_DONE = 7,  // mixed: inner solve finished, correction pending
-    COL_OUTER = 8,       // mixed: outer residual pending
+    COL_INNER_DONE = 7,  // mixed: inner solve finished, refinement step pending
+    COL_OUTER = 8,       // mixed: next inner solve pending (r, ||r|| known)
 };
 
 enum IterFlag : int32_t { F_SCONV = 1, F_OMEGA_BAD = 2, F_RESTART = 4, F_ZERO_X = 8 };
@@ -50,6 +50,7 @@ enum IterFlag : int32_t { F_SCONV = 1, F_OMEGA_BAD = 2, F_RESTART = 4, F_ZERO_X 
 enum SolveMode : int32_t { MODE_F64 = 0, MODE_INNER = 1 };
 
 constexpr int kMaxBreakdownRestarts = 3;
+constexpr int kGcrMax = 8;  // stored refinement directions (mixed precision)
 constexpr int kStagWindow = 50;
 
 struct Ctl {
@@ -72,6 +73,9 @@ struct Ctl {
     double relres[kMaxM];
     double rscale[kMaxM];
     double colsum[kMaxM];
+    double gamma[kMaxM];                 // mixed: step length of the refinement step
+    double beta[kGcrMax][kMaxM];         // mixed: projections on the stored directions
+    double wnorm2[kGcrMax][kMaxM];       // mixed: ||w_j||^2 of the stored directions
     double tol_in;
     int32_t mode;
     int32_t max_outer;
@@ -88,6 +92,23 @@ struct Kry {
     T nbi[kMaxM];
 };
 
+#ifndef MRHS_NT_STORE
+#define MRHS_NT_STORE 1
+#endif
+
+// Block outputs are written with streaming (nontemporal) stores: every block
+// is far larger than the caches, and keeping written lines out of L2 leaves
+// it to the gathered block rows.
+template <typename T, int VW>
+__device__ __forceinline__ void put(T *p, const T *v)
+{
+#if MRHS_NT_STORE
+    Vec<T, VW>::store_nt(p, v);
+#else
+    Vec<T, VW>::store(p, v);
+#endif
+}
+
 template <typename T>
 __device__ __forceinline__ bool bad(T v)
 {
@@ -100,6 +121,7 @@ __device__ __forceinline__ bool pending(int32_t s) { return s == COL_PEND_CHECK 
 // Plain product Y = A X.
 template <typename T, int M>
 struct OpStore {
+    static constexpr const char *kName = "gspmv";
     using S = Shape<T, M>;
     static constexpr int NDOT = 0;
     const T *X;
@@ -110,12 +132,17 @@ struct OpStore {
     __device__ Lane lane(int) const { return {true}; }
     __device__ __forceinline__ void gather(const Lane &, int32_t c, int g, T *x) const
     {
-        Vec<T, S::VW>::load(X + static_cast<size_t>(c) * M + g * S::VW, x);
+        Vec<T, S::VW>::load(blk<T, M>(X, c, g * S::VW), x);
     }
     __device__ __forceinline__ void row(const Lane &, int32_t i, int g, const T *sum,
                                         Acc<T, S::VW, NDOT> &) const
     {
-        Vec<T, S::VW>::store(Y + static_cast<size_t>(i) * M + g * S::VW, sum);
+#ifdef MRHS_DIAG_NOSTORE
+        if (sum[0] == T(123456.789))
+            put<T, S::VW>(blk<T, M>(Y, i, g * S::VW), sum);
+#else
+        put<T, S::VW>(blk<T, M>(Y, i, g * S::VW), sum);
+#endif
     }
     __device__ void finish(const T *) const {}
 };
@@ -127,12 +154,13 @@ enum ResidKind : int32_t {
     RES_SETUP = 0,  // first residual of a binary64 solve (all non-idle columns)
     RES_CHECK = 1,  // true residual of columns with a pending check/breakdown
     RES_FINAL = 2,  // residual of the returned x (all non-idle columns)
-    RES_OUTER = 3,  // mixed: outer residual of COL_OUTER / COL_INNER_DONE columns
     RES_NORM = 4,   // only the norms, into ctl->relres (API use)
+    RES_MIXCHECK = 5,  // mixed: true residual of columns whose refinement converged
 };
 
 template <int M>
 struct OpResid {
+    static constexpr const char *kName = "resid";
     using T = double;
     using S = Shape<double, M>;
     static constexpr int NDOT = 2;
@@ -152,9 +180,8 @@ struct OpResid {
         const int32_t st = ctl->status[c];
         switch (kind) {
         case RES_CHECK:
+        case RES_MIXCHECK:
             return pending(st);
-        case RES_OUTER:
-            return st == COL_OUTER || st == COL_INNER_DONE;
         default:
             return st != COL_IDLE;
         }
@@ -172,7 +199,7 @@ struct OpResid {
     }
     __device__ __forceinline__ void gather(const Lane &, int32_t c, int g, double *x) const
     {
-        Vec<double, S::VW>::load(X + static_cast<size_t>(c) * M + g * S::VW, x);
+        Vec<double, S::VW>::load(blk<T, M>(X, c, g * S::VW), x);
     }
     __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, const double *sum,
                                         Acc<double, S::VW, NDOT> &acc) const
@@ -188,10 +215,27 @@ struct OpResid {
                 acc.a[1][v] += b[v] * b[v];
             }
         }
-        if (R)
-            Vec<double, S::VW>::store(R + o, r);
-        if (R2)
-            Vec<double, S::VW>::store(R2 + o, r);
+        bool all = true;
+#pragma unroll
+        for (int v = 0; v < S::VW; ++v)
+            all = all && ln.act[v];
+        if (all) {
+            if (R)
+                put<double, S::VW>(R + o, r);
+            if (R2)
+                put<double, S::VW>(R2 + o, r);
+        } else {
+            // only the columns this kind owns are written
+#pragma unroll
+            for (int v = 0; v < S::VW; ++v) {
+                if (!ln.act[v])
+                    continue;
+                if (R)
+                    R[o + v] = r[v];
+                if (R2)
+                    R2[o + v] = r[v];
+            }
+        }
     }
     __device__ void finish(const double *tot) const
     {
@@ -229,6 +273,7 @@ struct OpResid {
                     k.status[c] = COL_NOCONV;
                 else
                     k.status[c] = mixed ? COL_OUTER : COL_RUN;
+                k.rscale[c] = sqrt(rr);
             }
             break;
         }
@@ -264,23 +309,19 @@ struct OpResid {
         case RES_NORM:
             k.relres[c] = (k.nb[c] > 0.0) ? sqrt(rr) / k.nb[c] : (k.flag[c] & F_ZERO_X ? 0.0 : sqrt(rr));
             break;
-        case RES_OUTER: {
-            const double nb = k.nb[c];
+        case RES_MIXCHECK: {
             const double nr = sqrt(rr);
-            k.total_iters[c] += k.iters[c];
-            k.iters[c] = 0;
-            k.rn[c] = nr / nb;
+            k.rn[c] = nr / k.nb[c];
             if (!isfinite(nr)) {
                 k.status[c] = COL_BREAKDOWN;
-            } else if (nr / nb <= k.tol[c]) {
+            } else if (nr / k.nb[c] <= k.tol[c]) {
                 k.status[c] = COL_DONE;
             } else if (k.outer[c] >= ctl->max_outer || k.total_iters[c] >= k.maxit[c]) {
                 k.status[c] = COL_NOCONV;
             } else {
+                k.restarts[c] += 1;  // continue from the true residual
                 k.rscale[c] = nr;
-                k.outer[c] += 1;
-                k.inner_maxit[c] = k.maxit[c] - k.total_iters[c];
-                k.status[c] = COL_RUN;
+                k.status[c] = COL_OUTER;
             }
             break;
         }
@@ -316,6 +357,7 @@ __device__ __forceinline__ RunLane<T, M> run_lane(const Ctl *ctl, int g)
 // p = r + beta (p - omega v), or p = r right after a (re)start.
 template <typename T, int M>
 struct OpPUpdate {
+    static constexpr const char *kName = "p_update";
     using S = Shape<T, M>;
     static constexpr int NDOT = 0;
     T *p;
@@ -356,7 +398,7 @@ struct OpPUpdate {
             if (ln.act[q])
                 pp[q] = ln.fresh[q] ? rr[q] : rr[q] + ln.beta[q] * (pp[q] - ln.omega[q] * vv[q]);
         }
-        Vec<T, S::VW>::store(p + o, pp);
+        put<T, S::VW>(p + o, pp);
     }
     __device__ void finish(const T *) const {}
 };
@@ -364,6 +406,7 @@ struct OpPUpdate {
 // v = Ah p with sigma = (r^, v); the last workgroup forms alpha.
 template <typename T, int M>
 struct OpSpmv1 {
+    static constexpr const char *kName = "spmv_sigma";
     using S = Shape<T, M>;
     static constexpr int NDOT = 1;
     const T *p;
@@ -375,7 +418,7 @@ struct OpSpmv1 {
     __device__ Lane lane(int g) const { return run_lane<T, M>(ctl, g); }
     __device__ __forceinline__ void gather(const Lane &, int32_t c, int g, T *x) const
     {
-        Vec<T, S::VW>::load(p + static_cast<size_t>(c) * M + g * S::VW, x);
+        Vec<T, S::VW>::load(blk<T, M>(p, c, g * S::VW), x);
     }
     __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, const T *sum,
                                         Acc<T, S::VW, NDOT> &acc) const
@@ -383,7 +426,7 @@ struct OpSpmv1 {
         const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         T h[S::VW];
         Vec<T, S::VW>::load(rh + o, h);
-        Vec<T, S::VW>::store(v + o, sum);
+        put<T, S::VW>(v + o, sum);
 #pragma unroll
         for (int q = 0; q < S::VW; ++q)
             if (ln.act[q])
@@ -409,6 +452,7 @@ struct OpSpmv1 {
 // stored); sums (t,s), (t,t), (s,s).  The last workgroup forms omega.
 template <typename T, int M>
 struct OpSpmv2 {
+    static constexpr const char *kName = "spmv_omega";
     using S = Shape<T, M>;
     static constexpr int NDOT = 3;
     const T *r;
@@ -449,7 +493,7 @@ struct OpSpmv2 {
         const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         T s[S::VW];
         gather(ln, i, g, s);
-        Vec<T, S::VW>::store(t + o, sum);
+        put<T, S::VW>(t + o, sum);
 #pragma unroll
         for (int q = 0; q < S::VW; ++q) {
             if (ln.act[q]) {
@@ -486,6 +530,7 @@ struct OpSpmv2 {
 // and (r, r).  The last workgroup updates rho and each column's state.
 template <typename T, int M>
 struct OpXR {
+    static constexpr const char *kName = "xr_update";
     using S = Shape<T, M>;
     static constexpr int NDOT = 2;
     T *y;
@@ -542,8 +587,8 @@ struct OpXR {
                 acc.a[1][q] += rr[q] * rr[q];
             }
         }
-        Vec<T, S::VW>::store(y + o, yy);
-        Vec<T, S::VW>::store(r + o, rr);
+        put<T, S::VW>(y + o, yy);
+        put<T, S::VW>(r + o, rr);
     }
     __device__ void finish(const T *tot) const
     {
@@ -592,6 +637,7 @@ struct OpXR {
 // After a check: columns restarting take r = r^ = (true residual) rt.
 template <typename T, int M>
 struct OpRestart {
+    static constexpr const char *kName = "restart";
     using S = Shape<T, M>;
     static constexpr int NDOT = 0;
     const T *rt;
@@ -627,8 +673,8 @@ struct OpRestart {
                 b[q] = a[q];
                 h[q] = a[q];
             }
-        Vec<T, S::VW>::store(r + o, b);
-        Vec<T, S::VW>::store(rh + o, h);
+        put<T, S::VW>(r + o, b);
+        put<T, S::VW>(rh + o, h);
     }
     __device__ void finish(const T *) const {}
 };
@@ -645,6 +691,7 @@ enum ScaleKind : int32_t {
 
 template <int M>
 struct OpScale {
+    static constexpr const char *kName = "scale";
     using S = Shape<double, M>;
     static constexpr int NDOT = 0;
     double *x;
@@ -691,7 +738,7 @@ struct OpScale {
             else if (kind == SC_IN || kind == SC_OUT)
                 a[q] = a[q] * di;
         }
-        Vec<double, S::VW>::store(x + o, a);
+        put<double, S::VW>(x + o, a);
     }
     __device__ void finish(const double *) const {}
 };
@@ -699,6 +746,7 @@ struct OpScale {
 // Column sums of x (for the null-space projection).
 template <int M>
 struct OpColSum {
+    static constexpr const char *kName = "colsum";
     using S = Shape<double, M>;
     static constexpr int NDOT = 1;
     const double *x;
@@ -727,6 +775,7 @@ struct OpColSum {
 // r32 = r^32 = RN32(r64 / ||r64||), y32 = 0; sums (r32, r32) in binary32.
 template <int M>
 struct OpCast {
+    static constexpr const char *kName = "cast32";
     using S = Shape<float, M>;
     static constexpr int NDOT = 1;
     const double *r64;
@@ -747,7 +796,7 @@ struct OpCast {
 #pragma unroll
         for (int q = 0; q < S::VW; ++q) {
             const int c = g * S::VW + q;
-            ln.act[q] = ctl->status[c] == COL_RUN;
+            ln.act[q] = ctl->status[c] == COL_OUTER;
             ln.scale[q] = ctl->rscale[c];
             ln.on = ln.on || ln.act[q];
         }
@@ -770,16 +819,18 @@ struct OpCast {
                 acc.a[0][q] += f * f;
             }
         }
-        Vec<float, S::VW>::store(r + o, a);
-        Vec<float, S::VW>::store(rh + o, h);
-        Vec<float, S::VW>::store(y + o, z);
+        put<float, S::VW>(r + o, a);
+        put<float, S::VW>(rh + o, h);
+        put<float, S::VW>(y + o, z);
     }
     __device__ void finish(const float *tot) const
     {
         const int c = threadIdx.x;
-        if (c >= M || ctl->status[c] != COL_RUN)
+        if (c >= M || ctl->status[c] != COL_OUTER)
             return;
         Ctl &k = *ctl;
+        k.status[c] = COL_RUN;
+        k.inner_maxit[c] = k.maxit[c] - k.total_iters[c];
         const float rr = tot[c];
         kry->rho[c] = rr;
         kry->nbi[c] = sqrtf(rr);
@@ -794,12 +845,39 @@ struct OpCast {
     }
 };
 
-// Mixed precision: x += ||r64|| * D^-1 y32 for columns whose inner solve ended.
+// ---------------------------------------------------------------------------
+// Mixed precision refinement step (binary64), for every column whose binary32
+// inner solve ended.  The inner solve of Ah32 y = r/||r|| gives the correction
+// z = ||r|| D^-1 y; with w = A z the step is made minimal-residual over the
+// current and the stored directions (generalized conjugate residuals):
+//   w -= sum_j beta_j w_j, z -= sum_j beta_j z_j, beta_j = (w, w_j)/(w_j, w_j)
+//   gamma = (r, w)/(w, w);  x += gamma z;  r -= gamma w.
+struct GcrBlocks {
+    double *z[kGcrMax];
+    double *w[kGcrMax];
+};
+
 template <int M>
-struct OpCorrect {
+__device__ __forceinline__ RunLane<double, M> inner_done_lane(const Ctl *ctl, int g)
+{
     using S = Shape<double, M>;
+    RunLane<double, M> ln;
+    ln.on = false;
+#pragma unroll
+    for (int q = 0; q < S::VW; ++q) {
+        ln.act[q] = ctl->status[g * S::VW + q] == COL_INNER_DONE;
+        ln.on = ln.on || ln.act[q];
+    }
+    return ln;
+}
+
+// z_k = ||r|| * D^-1 * y32 (zero in other columns)
+template <int M>
+struct OpGcrZ {
+    using S = Shape<double, M>;
+    static constexpr const char *kName = "gcr_z";
     static constexpr int NDOT = 0;
-    double *x;
+    double *z;
     const float *y;
     const double *dinv;
     const Ctl *ctl;
@@ -811,13 +889,12 @@ struct OpCorrect {
     __device__ Lane lane(int g) const
     {
         Lane ln;
-        ln.on = false;
+        ln.on = true;
 #pragma unroll
         for (int q = 0; q < S::VW; ++q) {
             const int c = g * S::VW + q;
             ln.act[q] = ctl->status[c] == COL_INNER_DONE;
             ln.scale[q] = ctl->rscale[c];
-            ln.on = ln.on || ln.act[q];
         }
         return ln;
     }
@@ -825,15 +902,203 @@ struct OpCorrect {
     {
         const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         double a[S::VW];
-        Vec<double, S::VW>::load(x + o, a);
         const double di = dinv[i];
 #pragma unroll
         for (int q = 0; q < S::VW; ++q)
-            if (ln.act[q])
-                a[q] = a[q] + ln.scale[q] * (di * static_cast<double>(y[o + q]));
-        Vec<double, S::VW>::store(x + o, a);
+            a[q] = ln.act[q] ? ln.scale[q] * (di * static_cast<double>(y[o + q])) : 0.0;
+        put<double, S::VW>(z + o, a);
     }
     __device__ void finish(const double *) const {}
+};
+
+// beta_j = (w_k, w_j) / (w_j, w_j) for j < k
+template <int M>
+struct OpGcrDots {
+    using S = Shape<double, M>;
+    static constexpr const char *kName = "gcr_dots";
+    static constexpr int NDOT = kGcrMax;
+    GcrBlocks b;
+    int32_t k;
+    Ctl *ctl;
+    using Lane = RunLane<double, M>;
+    __device__ Lane lane(int g) const { return inner_done_lane<M>(ctl, g); }
+    __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, Acc<double, S::VW, NDOT> &acc) const
+    {
+        const size_t o = static_cast<size_t>(i) * M + g * S::VW;
+        double wk[S::VW];
+        Vec<double, S::VW>::load(b.w[k] + o, wk);
+#pragma unroll
+        for (int j = 0; j < kGcrMax; ++j) {
+            if (j >= k)
+                break;
+            double wj[S::VW];
+            Vec<double, S::VW>::load(b.w[j] + o, wj);
+#pragma unroll
+            for (int q = 0; q < S::VW; ++q)
+                if (ln.act[q])
+                    acc.a[j][q] += wk[q] * wj[q];
+        }
+    }
+    __device__ void finish(const double *tot) const
+    {
+        const int c = threadIdx.x;
+        if (c >= M || ctl->status[c] != COL_INNER_DONE)
+            return;
+        for (int j = 0; j < kGcrMax; ++j) {
+            const double d = ctl->wnorm2[j][c];
+            ctl->beta[j][c] = (j < k && d > 0.0 && isfinite(d)) ? tot[j * M + c] / d : 0.0;
+        }
+    }
+};
+
+// w_k -= sum beta_j w_j, z_k -= sum beta_j z_j; sums (w_k, w_k), (r, w_k)
+template <int M>
+struct OpGcrOrth {
+    using S = Shape<double, M>;
+    static constexpr const char *kName = "gcr_orth";
+    static constexpr int NDOT = 2;
+    GcrBlocks b;
+    const double *r;
+    int32_t k;
+    Ctl *ctl;
+    struct Lane {
+        bool on;
+        bool act[S::VW];
+        double beta[kGcrMax][S::VW];
+    };
+    __device__ Lane lane(int g) const
+    {
+        Lane ln;
+        const RunLane<double, M> rl = inner_done_lane<M>(ctl, g);
+        ln.on = rl.on;
+#pragma unroll
+        for (int q = 0; q < S::VW; ++q) {
+            ln.act[q] = rl.act[q];
+#pragma unroll
+            for (int j = 0; j < kGcrMax; ++j)
+                ln.beta[j][q] = ctl->beta[j][g * S::VW + q];
+        }
+        return ln;
+    }
+    __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, Acc<double, S::VW, NDOT> &acc) const
+    {
+        const size_t o = static_cast<size_t>(i) * M + g * S::VW;
+        double wk[S::VW], zk[S::VW], rr[S::VW];
+        Vec<double, S::VW>::load(b.w[k] + o, wk);
+        Vec<double, S::VW>::load(b.z[k] + o, zk);
+        Vec<double, S::VW>::load(r + o, rr);
+#pragma unroll
+        for (int j = 0; j < kGcrMax; ++j) {
+            if (j >= k)
+                break;
+            double wj[S::VW], zj[S::VW];
+            Vec<double, S::VW>::load(b.w[j] + o, wj);
+            Vec<double, S::VW>::load(b.z[j] + o, zj);
+#pragma unroll
+            for (int q = 0; q < S::VW; ++q) {
+                if (ln.act[q]) {
+                    wk[q] -= ln.beta[j][q] * wj[q];
+                    zk[q] -= ln.beta[j][q] * zj[q];
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < S::VW; ++q) {
+            if (ln.act[q]) {
+                acc.a[0][q] += wk[q] * wk[q];
+                acc.a[1][q] += rr[q] * wk[q];
+            }
+        }
+        if (k > 0) {
+            put<double, S::VW>(b.w[k] + o, wk);
+            put<double, S::VW>(b.z[k] + o, zk);
+        }
+    }
+    __device__ void finish(const double *tot) const
+    {
+        const int c = threadIdx.x;
+        if (c >= M)
+            return;
+        if (ctl->status[c] != COL_INNER_DONE) {
+            ctl->wnorm2[k][c] = 0.0;  // this slot holds no direction of column c
+            return;
+        }
+        const double ww = tot[c], rw = tot[M + c];
+        ctl->wnorm2[k][c] = ww;
+        ctl->gamma[c] = (ww > 0.0 && isfinite(ww) && isfinite(rw)) ? rw / ww : 0.0;
+    }
+};
+
+// x += gamma z_k;  r -= gamma w_k; sums (r, r).  The last workgroup decides
+// each column's next state.
+template <int M>
+struct OpGcrUpdate {
+    using S = Shape<double, M>;
+    static constexpr const char *kName = "gcr_update";
+    static constexpr int NDOT = 1;
+    double *x;
+    double *r;
+    const double *z;
+    const double *w;
+    Ctl *ctl;
+    struct Lane {
+        bool on;
+        bool act[S::VW];
+        double gamma[S::VW];
+    };
+    __device__ Lane lane(int g) const
+    {
+        Lane ln;
+        const RunLane<double, M> rl = inner_done_lane<M>(ctl, g);
+        ln.on = rl.on;
+#pragma unroll
+        for (int q = 0; q < S::VW; ++q) {
+            ln.act[q] = rl.act[q];
+            ln.gamma[q] = ctl->gamma[g * S::VW + q];
+        }
+        return ln;
+    }
+    __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, Acc<double, S::VW, NDOT> &acc) const
+    {
+        const size_t o = static_cast<size_t>(i) * M + g * S::VW;
+        double xx[S::VW], rr[S::VW], zz[S::VW], ww[S::VW];
+        Vec<double, S::VW>::load(x + o, xx);
+        Vec<double, S::VW>::load(r + o, rr);
+        Vec<double, S::VW>::load(z + o, zz);
+        Vec<double, S::VW>::load(w + o, ww);
+#pragma unroll
+        for (int q = 0; q < S::VW; ++q) {
+            if (ln.act[q]) {
+                xx[q] += ln.gamma[q] * zz[q];
+                rr[q] -= ln.gamma[q] * ww[q];
+                acc.a[0][q] += rr[q] * rr[q];
+            }
+        }
+        put<double, S::VW>(x + o, xx);
+        put<double, S::VW>(r + o, rr);
+    }
+    __device__ void finish(const double *tot) const
+    {
+        const int c = threadIdx.x;
+        if (c >= M || ctl->status[c] != COL_INNER_DONE)
+            return;
+        Ctl &k = *ctl;
+        const double nr = sqrt(tot[c]);
+        k.total_iters[c] += k.iters[c];
+        k.iters[c] = 0;
+        k.outer[c] += 1;
+        k.rn[c] = nr / k.nb[c];
+        if (!isfinite(nr)) {
+            k.status[c] = COL_BREAKDOWN;
+        } else if (nr / k.nb[c] <= k.tol[c]) {
+            k.status[c] = COL_PEND_CHECK;
+        } else if (k.outer[c] >= k.max_outer || k.total_iters[c] >= k.maxit[c]) {
+            k.status[c] = COL_NOCONV;
+        } else {
+            k.rscale[c] = nr;
+            k.status[c] = COL_OUTER;
+        }
+    }
 };
 
 } // namespace mrhs

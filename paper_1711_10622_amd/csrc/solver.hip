@@ -18,11 +18,18 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
     size_t ctl, kry64, kry32, tickets, part, gpart;
-    size_t v64[5];  // r, r^, p, v, t                 (binary64 solve)
-    size_t r64;     // outer residual                 (mixed)
-    size_t v32[6];  // r, r^, p, v, t, y              (mixed, binary32)
+    size_t v64[5];           // r, r^, p, v, t                 (binary64 solve)
+    size_t r64;              // refinement residual            (mixed)
+    size_t z[kGcrMax];       // refinement directions z_j      (mixed)
+    size_t w[kGcrMax];       // and w_j = A z_j                (mixed)
+    size_t v32[6];           // r, r^, p, v, t, y              (mixed, binary32)
     size_t total;
 };
+
+int env_int(const char *name, int dflt, int lo, int hi);
+
+// Stored refinement directions (1..kGcrMax; MRHS_GCR_DIRS overrides the default).
+int gcr_dirs() { return env_int("MRHS_GCR_DIRS", kGcrMax, 1, kGcrMax); }
 
 Layout layout(int32_t n, int32_t m, uint32_t flags)
 {
@@ -44,6 +51,10 @@ Layout layout(int32_t n, int32_t m, uint32_t flags)
     const size_t blk32 = sizeof(float) * static_cast<size_t>(n) * m;
     if (flags & MRHS_MIXED) {
         L.r64 = take(blk64);
+        for (int i = 0; i < gcr_dirs(); ++i) {
+            L.z[i] = take(blk64);
+            L.w[i] = take(blk64);
+        }
         for (int i = 0; i < 6; ++i)
             L.v32[i] = take(blk32);
     } else {
@@ -74,6 +85,7 @@ struct Ctx {
     RedBufs<float> rb32;
     double *r, *rh, *p, *v, *t;
     double *r64;
+    GcrBlocks gcr;
     float *r32, *rh32, *p32, *v32, *t32, *y32;
 };
 
@@ -140,11 +152,23 @@ struct Steps {
                                        OpResid<M>{c.X, c.B, c.r64, nullptr, c.ctl, c.kry64, RES_SETUP},
                                        c.rb64, c.s);
     }
-    static hipError_t mixed_outer(Ctx &c)
+    // one refinement step on slot k for every column whose inner solve ended
+    static hipError_t mixed_step(Ctx &c, int k)
     {
-        MRHS_TRY((launch_stream<double, M>(c.n, OpCorrect<M>{c.X, c.y32, c.A->dinv, c.ctl}, c.rb64, c.s)));
+        MRHS_TRY((launch_stream<double, M>(c.n, OpGcrZ<M>{c.gcr.z[k], c.y32, c.A->dinv, c.ctl}, c.rb64, c.s)));
+        MRHS_TRY((launch_gspmv<double, M>(view<double>(*c.A, false), OpStore<double, M>{c.gcr.z[k], c.gcr.w[k]},
+                                           c.rb64, c.s)));
+        if (k > 0)
+            MRHS_TRY((launch_stream<double, M>(c.n, OpGcrDots<M>{c.gcr, k, c.ctl}, c.rb64, c.s)));
+        MRHS_TRY((launch_stream<double, M>(c.n, OpGcrOrth<M>{c.gcr, c.r64, k, c.ctl}, c.rb64, c.s)));
+        return launch_stream<double, M>(c.n, OpGcrUpdate<M>{c.X, c.r64, c.gcr.z[k], c.gcr.w[k], c.ctl}, c.rb64,
+                                        c.s);
+    }
+    // true residual of columns whose refinement residual met the tolerance
+    static hipError_t mixed_check(Ctx &c)
+    {
         return launch_gspmv<double, M>(view<double>(*c.A, false),
-                                       OpResid<M>{c.X, c.B, c.r64, nullptr, c.ctl, c.kry64, RES_OUTER},
+                                       OpResid<M>{c.X, c.B, c.r64, nullptr, c.ctl, c.kry64, RES_MIXCHECK},
                                        c.rb64, c.s);
     }
     static hipError_t mixed_cast(Ctx &c)
@@ -176,7 +200,8 @@ struct StepTable {
     hipError_t (*f64_check)(Ctx &);
     hipError_t (*finish)(Ctx &, bool, bool);
     hipError_t (*mixed_setup)(Ctx &, bool);
-    hipError_t (*mixed_outer)(Ctx &);
+    hipError_t (*mixed_step)(Ctx &, int);
+    hipError_t (*mixed_check)(Ctx &);
     hipError_t (*mixed_cast)(Ctx &);
     hipError_t (*inner_iterate)(Ctx &, int);
 };
@@ -186,7 +211,7 @@ struct MakeTable {
     StepTable operator()() const
     {
         return {&Steps<M>::f64_setup, &Steps<M>::f64_iterate, &Steps<M>::f64_check, &Steps<M>::finish,
-                &Steps<M>::mixed_setup, &Steps<M>::mixed_outer, &Steps<M>::mixed_cast,
+                &Steps<M>::mixed_setup, &Steps<M>::mixed_step, &Steps<M>::mixed_check, &Steps<M>::mixed_cast,
                 &Steps<M>::inner_iterate};
     }
 };
@@ -223,7 +248,7 @@ Ctl *host_ctl()
 }
 
 struct StatusCount {
-    int run = 0, pending = 0, inner_done = 0;
+    int run = 0, pending = 0, inner_done = 0, outer = 0;
 };
 
 StatusCount count(const Ctl &h, int m)
@@ -234,6 +259,7 @@ StatusCount count(const Ctl &h, int m)
         c.run += st == COL_RUN;
         c.pending += st == COL_PEND_CHECK || st == COL_PEND_BD;
         c.inner_done += st == COL_INNER_DONE;
+        c.outer += st == COL_OUTER;
     }
     return c;
 }
@@ -291,6 +317,10 @@ mrhs_status block_solve(const mrhs_csr_s &A, const double *B, double *X, const S
     c.rb32 = {reinterpret_cast<float *>(base + L.part), reinterpret_cast<float *>(base + L.gpart), tickets};
     if (mixed) {
         c.r64 = reinterpret_cast<double *>(base + L.r64);
+        for (int i = 0; i < gcr_dirs(); ++i) {
+            c.gcr.z[i] = reinterpret_cast<double *>(base + L.z[i]);
+            c.gcr.w[i] = reinterpret_cast<double *>(base + L.w[i]);
+        }
         float **v32[6] = {&c.r32, &c.rh32, &c.p32, &c.v32, &c.t32, &c.y32};
         for (int i = 0; i < 6; ++i)
             *v32[i] = reinterpret_cast<float *>(base + L.v32[i]);
@@ -311,8 +341,8 @@ mrhs_status block_solve(const mrhs_csr_s &A, const double *B, double *X, const S
         h->inner_maxit[i] = p.maxit;
     }
     h->mode = mixed ? MODE_INNER : MODE_F64;
-    h->tol_in = env_double("MRHS_INNER_TOL", 1e-4);
-    h->max_outer = env_int("MRHS_MAX_OUTER", 30, 1, 1000);
+    h->tol_in = env_double("MRHS_INNER_TOL", 0.1);
+    h->max_outer = env_int("MRHS_MAX_OUTER", 500, 1, 100000);
     h->n = A.n;
     const int chunk = env_int("MRHS_POLL_ITERS", 16, 1, 1024);
 
@@ -343,11 +373,19 @@ mrhs_status block_solve(const mrhs_csr_s &A, const double *B, double *X, const S
             MRHS_HIP(read_status());
         }
     } else {
+        // binary32 inner solves, binary64 refinement steps (all columns in
+        // step: every inner phase runs until no column is iterating)
+        const int ndirs = gcr_dirs();
+        int slot = 0;
         MRHS_HIP(T.mixed_setup(c, x0));
         for (;;) {
-            MRHS_HIP(T.mixed_outer(c));
             MRHS_HIP(read_status());
-            if (!count(*h, m).run)
+            const StatusCount sc = count(*h, m);
+            if (sc.pending) {
+                MRHS_HIP(T.mixed_check(c));
+                continue;
+            }
+            if (!sc.outer)
                 break;
             MRHS_HIP(T.mixed_cast(c));
             for (;;) {
@@ -356,6 +394,8 @@ mrhs_status block_solve(const mrhs_csr_s &A, const double *B, double *X, const S
                     break;
                 MRHS_HIP(T.inner_iterate(c, chunk));
             }
+            MRHS_HIP(T.mixed_step(c, slot));
+            slot = (slot + 1) % ndirs;
         }
     }
     MRHS_HIP(T.finish(c, mixed, nullspace));
