@@ -156,6 +156,64 @@ mrhs_status block_bicgstab_workspace_size(mrhs_csr A, int32_t m, uint32_t flags,
                                           size_t *bytes);
 
 /*
+ * Solve server: continuous batching of pressure solves from independent
+ * ensemble members (Section 2: every realization needs the same operator with
+ * its own right-hand side).  Registered matrices stay resident on the device.
+ * Each matrix has one block of 16 column slots; submitted right-hand sides
+ * join the block as slots free up (between rounds of iterations) and leave it
+ * as soon as their column has converged, so requests that arrive while others
+ * are being solved share the matrix reads of those already running.  Every
+ * column's arithmetic is independent of the other columns in its block.
+ * Different matrices are solved by their own host thread on their own stream
+ * and overlap on the device.
+ *
+ * Device memory is admitted against hbm_budget_bytes: registered matrices
+ * (their csr_info device bytes) plus the engine of every matrix that has work
+ * (its block workspace).  An idle matrix gives its engine memory back when
+ * another matrix waits for budget.  All functions are thread-safe.
+ */
+#define MRHS_SERVER_MIXED 1u /* binary32 inner solves with binary64 refinement */
+
+/* Create a server.  flags: 0 (binary64 solves) or MRHS_SERVER_MIXED. */
+mrhs_status solve_server_create(size_t hbm_budget_bytes, uint32_t flags,
+                                mrhs_server *out);
+
+/*
+ * Make matrix A servable; *matrix_id names it in submits.  A must outlive
+ * the server.  EBUDGET when A and its engine can never fit the budget;
+ * EINVAL for an empty matrix or a zero diagonal entry.
+ */
+mrhs_status solve_server_register(mrhs_server S, mrhs_csr A, int32_t *matrix_id);
+
+/*
+ * Queue k >= 1 right-hand sides B (host memory, n x k row-major: B[i*k + j]
+ * is row i of right-hand side j) for matrix_id, each solved to
+ * ||b - A x|| <= tol ||b|| within maxit iterations.  B is copied; the caller
+ * may free it on return.  *ticket identifies the request.  ENOTFOUND for an
+ * unknown matrix id; ESHUTDOWN after solve_server_destroy has begun.
+ */
+mrhs_status solve_server_submit(mrhs_server S, int32_t matrix_id, const double *B,
+                                int32_t k, double tol, int32_t maxit,
+                                uint64_t *ticket);
+
+/*
+ * EAGAIN while the request is in progress.  When it is complete: copies the
+ * solutions into X (host memory, n x k row-major, may be NULL) and the k
+ * per-column outcomes into info (may be NULL), forgets the ticket, and
+ * returns OK if every column converged, else the worst column status.
+ * ENOTFOUND for an unknown (or already collected) ticket.
+ */
+mrhs_status solve_server_poll(mrhs_server S, uint64_t ticket, double *X,
+                              mrhs_col_info *info);
+
+/* Latency percentiles over completed requests, throughput and occupancy. */
+mrhs_status solve_server_stats(mrhs_server S, mrhs_server_stats *out);
+
+/* Stop the serving threads (work in progress is abandoned) and free the
+ * server.  NULL is accepted. */
+mrhs_status solve_server_destroy(mrhs_server S);
+
+/*
  * Kernel timing.  mrhs_trace_enable(1) clears the statistics and starts
  * bracketing every kernel launch of the library with a pair of HIP events on
  * the launch's own stream; mrhs_trace_enable(0) stops.  mrhs_trace_read

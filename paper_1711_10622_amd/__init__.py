@@ -8,4 +8,4 @@ iterations built on the generalized sparse matrix-vector product Y = A X
 C ABI, include/mrhs.h); this package only marshals arguments.
 """
 from ._lib import MrhsError, load  # noqa: F401
-from .api import CsrMatrix, block_bicgstab, gspmv, trace_enable, trace_read  # noqa: F401
+from .api import CsrMatrix, SolveServer, block_bicgstab, gspmv, trace_enable, trace_read  # noqa: F401

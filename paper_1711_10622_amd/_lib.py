@@ -19,11 +19,14 @@ STATUS_NAMES = {0: "OK", 1: "EAGAIN", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE",
 F64, F32 = 0, 1
 CSR_NULLSPACE_CONST = 1
 X0_GIVEN, MIXED = 1, 2
+SERVER_MIXED = 1
 
 # every symbol include/mrhs.h declares
 EXPORTS = (
     "mrhs_last_error", "mrhs_version", "csr_create", "csr_destroy", "csr_info", "gspmv", "gspmv_ex",
     "block_bicgstab", "block_bicgstab_ex", "block_bicgstab_workspace_size",
+    "solve_server_create", "solve_server_register", "solve_server_submit", "solve_server_poll",
+    "solve_server_stats", "solve_server_destroy",
     "mrhs_trace_enable", "mrhs_trace_read",
 )
 
@@ -31,6 +34,15 @@ EXPORTS = (
 class ColInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("restarts", ctypes.c_int32), ("outer", ctypes.c_int32),
                 ("status", ctypes.c_int32), ("relres", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("rhs_per_s", ctypes.c_double),
+                ("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("queued", ctypes.c_int64),
+                ("rhs_completed", ctypes.c_int64), ("admitted_bytes", ctypes.c_size_t)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -62,6 +74,12 @@ def _declare(lib):
         "block_bicgstab": [vp, vp, vp, i32, f64, i32],
         "block_bicgstab_ex": [vp, vp, vp, i32, f64, i32, u32, vp, sz, vp, c.POINTER(ColInfo)],
         "block_bicgstab_workspace_size": [vp, i32, u32, c.POINTER(sz)],
+        "solve_server_create": [sz, u32, c.POINTER(vp)],
+        "solve_server_register": [vp, vp, c.POINTER(i32)],
+        "solve_server_submit": [vp, i32, vp, i32, f64, i32, c.POINTER(c.c_uint64)],
+        "solve_server_poll": [vp, c.c_uint64, vp, c.POINTER(ColInfo)],
+        "solve_server_stats": [vp, c.POINTER(ServerStats)],
+        "solve_server_destroy": [vp],
         "mrhs_trace_enable": [c.c_int],
         "mrhs_trace_read": [c.c_char_p, sz, c.POINTER(sz)],
     }

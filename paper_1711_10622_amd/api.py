@@ -172,3 +172,77 @@ def trace_read() -> dict:
     buf = ctypes.create_string_buffer(need.value + 1)
     _lib.check(lib.mrhs_trace_read(buf, need.value + 1, ctypes.byref(need)), "mrhs_trace_read")
     return json.loads(buf.value.decode())
+
+
+class SolveServer:
+    """Continuous-batching solve server (``solve_server_*``): host-memory
+    right-hand sides in, host-memory solutions out."""
+
+    def __init__(self, hbm_budget_bytes, mixed=False):
+        lib = _lib.load()
+        self._lib = lib
+        h = ctypes.c_void_p()
+        _lib.check(lib.solve_server_create(int(hbm_budget_bytes), _lib.SERVER_MIXED if mixed else 0,
+                                           ctypes.byref(h)), "solve_server_create")
+        self._h = h
+        self._n = {}
+        self._k = {}
+
+    def register(self, A: CsrMatrix) -> int:
+        mid = ctypes.c_int32()
+        _lib.check(self._lib.solve_server_register(self._h, A.handle, ctypes.byref(mid)), "solve_server_register")
+        self._n[mid.value] = A.n
+        return mid.value
+
+    def submit(self, matrix_id, B, tol=1e-10, maxit=20000) -> int:
+        B = np.ascontiguousarray(B, dtype=np.float64)
+        if B.ndim == 1:
+            B = B[:, None]
+        n, k = B.shape
+        if n != self._n.get(matrix_id, n):
+            raise ValueError(f"B has {n} rows, matrix {matrix_id} has {self._n[matrix_id]}")
+        t = ctypes.c_uint64()
+        _lib.check(self._lib.solve_server_submit(self._h, int(matrix_id), B.ctypes.data, k, float(tol), int(maxit),
+                                                 ctypes.byref(t)), "solve_server_submit")
+        self._k[t.value] = (n, k)
+        return t.value
+
+    def poll(self, ticket):
+        """None while running, else ``(X, infos, status)``."""
+        n, k = self._k[ticket]
+        X = np.empty((n, k), dtype=np.float64)
+        infos = (_lib.ColInfo * k)()
+        st = self._lib.solve_server_poll(self._h, ctypes.c_uint64(ticket), X.ctypes.data, infos)
+        if st == _lib.EAGAIN:
+            return None
+        if st not in (_lib.OK, _lib.ENOCONV, _lib.EBREAKDOWN, _lib.EDEVICE, _lib.ENOMEM):
+            _lib.check(st, "solve_server_poll")
+        del self._k[ticket]
+        return X, [i.as_dict() for i in infos], st
+
+    def wait(self, ticket, timeout=600.0, interval=1e-3):
+        import time
+        t0 = time.monotonic()
+        while True:
+            r = self.poll(ticket)
+            if r is not None:
+                return r
+            if time.monotonic() - t0 > timeout:
+                raise TimeoutError(f"ticket {ticket} not done after {timeout} s")
+            time.sleep(interval)
+
+    def stats(self) -> dict:
+        s = _lib.ServerStats()
+        _lib.check(self._lib.solve_server_stats(self._h, ctypes.byref(s)), "solve_server_stats")
+        return s.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.solve_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -137,7 +137,77 @@ inline auto dispatch_m(int m, F &&f)
     }
 }
 
-// ---- block solver (solver.hip) ----------------------------------------------
+// ---- block solver engine (solver.hip) ---------------------------------------
+struct Ctx {
+    const mrhs_csr_s *A;
+    const double *B;
+    double *X;
+    int32_t n;
+    hipStream_t s;
+    Ctl *ctl;
+    Kry<double> *kry64;
+    Kry<float> *kry32;
+    RedBufs<double> rb64;
+    RedBufs<float> rb32;
+    double *r, *rh, *p, *v, *t;
+    double *r64;
+    GcrBlocks gcr;
+    float *r32, *rh32, *p32, *v32, *t32, *y32;
+};
+
+struct StepTable {
+    hipError_t (*f64_start)(Ctx &, uint32_t, bool);
+    hipError_t (*f64_iterate)(Ctx &, int);
+    hipError_t (*f64_check)(Ctx &);
+    hipError_t (*finish)(Ctx &, uint32_t, bool, bool);
+    hipError_t (*mixed_start)(Ctx &, uint32_t, bool);
+    hipError_t (*mixed_step)(Ctx &);
+    hipError_t (*mixed_check)(Ctx &);
+    hipError_t (*mixed_cast)(Ctx &);
+    hipError_t (*inner_iterate)(Ctx &, int);
+};
+
+// m column slots over one matrix, with blocks B (right-hand sides) and X
+// (solutions) of n x m in device memory and a workspace of workspace_bytes().
+// start() admits columns (their B, and X when x0, must be in place), advance()
+// runs one round, finish() forms the returned x and its residual for
+// finished columns.  Not thread-safe; one engine per host thread.
+class Engine {
+  public:
+    static size_t workspace_bytes(const mrhs_csr_s &A, int32_t m, uint32_t flags);
+    Engine(const mrhs_csr_s &A, int m, uint32_t flags, void *ws, const double *B, double *X, hipStream_t s);
+    ~Engine();
+    Engine(const Engine &) = delete;
+    Engine &operator=(const Engine &) = delete;
+    mrhs_status reset();
+    mrhs_status start(uint32_t cmask, const double *tol, const int32_t *maxit, bool x0);
+    mrhs_status advance(bool *busy);  // reads the column states, then enqueues one round
+    mrhs_status finish(uint32_t cmask);
+    mrhs_status read_status();
+    mrhs_status read_ctl();
+    const Ctl &host() const { return *host_; }
+    uint32_t terminal_mask() const;  // per the last read states
+    static bool terminal(int32_t st);
+    int m() const { return m_; }
+
+  private:
+    const mrhs_csr_s &A_;
+    int m_;
+    bool mixed_, nullspace_;
+    hipStream_t s_;
+    const StepTable *T_;
+    Ctx c_{};
+    unsigned *tickets_ = nullptr;
+    Ctl *host_ = nullptr;
+    int chunk_ = 16, ndirs_ = kGcrMax, gcr_steps_ = 0, max_outer_ = 500;
+    double tol_in_ = 0.1;
+};
+
+mrhs_status column_status(int32_t st);
+int env_int(const char *name, int dflt, int lo, int hi);
+double env_double(const char *name, double dflt);
+int gcr_dirs();
+
 struct SolveParams {
     int32_t m;
     double tol;

@@ -43,6 +43,7 @@ enum ColStatus : int32_t {
     COL_BREAKDOWN = 6,   // breakdown persisted / non-finite data
     COL_INNER_DONE = 7,  // mixed: inner solve finished, refinement step pending
     COL_OUTER = 8,       // mixed: next inner solve pending (r, ||r|| known)
+    COL_INIT = 9,        // admitted: first residual pending
 };
 
 enum IterFlag : int32_t { F_SCONV = 1, F_OMEGA_BAD = 2, F_RESTART = 4, F_ZERO_X = 8 };
@@ -73,6 +74,8 @@ struct Ctl {
     double relres[kMaxM];
     double rscale[kMaxM];
     double colsum[kMaxM];
+    int32_t kcol[kMaxM];                 // mixed: slot of the column's next stored direction
+    double wnew2[kMaxM];                 // mixed: ||w||^2 of the new direction
     double gamma[kMaxM];                 // mixed: step length of the refinement step
     double beta[kGcrMax][kMaxM];         // mixed: projections on the stored directions
     double wnorm2[kGcrMax][kMaxM];       // mixed: ||w_j||^2 of the stored directions
@@ -151,9 +154,9 @@ struct OpStore {
 // Residual R = B - A X with per-column sums of R*R and B*B.  Which columns are
 // computed, and what the last workgroup does with the norms, depends on kind.
 enum ResidKind : int32_t {
-    RES_SETUP = 0,  // first residual of a binary64 solve (all non-idle columns)
+    RES_SETUP = 0,  // first residual of newly admitted (COL_INIT) columns
     RES_CHECK = 1,  // true residual of columns with a pending check/breakdown
-    RES_FINAL = 2,  // residual of the returned x (all non-idle columns)
+    RES_FINAL = 2,  // residual of the returned x (columns in cmask)
     RES_NORM = 4,   // only the norms, into ctl->relres (API use)
     RES_MIXCHECK = 5,  // mixed: true residual of columns whose refinement converged
 };
@@ -171,6 +174,7 @@ struct OpResid {
     Ctl *ctl;
     Kry<double> *kry;
     int32_t kind;
+    uint32_t cmask;  // columns of RES_FINAL / RES_NORM
     struct Lane {
         bool on;
         bool act[S::VW];
@@ -179,11 +183,13 @@ struct OpResid {
     {
         const int32_t st = ctl->status[c];
         switch (kind) {
+        case RES_SETUP:
+            return st == COL_INIT;
         case RES_CHECK:
         case RES_MIXCHECK:
             return pending(st);
         default:
-            return st != COL_IDLE;
+            return (cmask >> c) & 1u;
         }
     }
     __device__ Lane lane(int g) const
@@ -699,6 +705,7 @@ struct OpScale {
     const double *dinv;
     const Ctl *ctl;
     int32_t kind;
+    uint32_t cmask;
     struct Lane {
         bool on;
         bool act[S::VW];
@@ -712,7 +719,7 @@ struct OpScale {
 #pragma unroll
         for (int q = 0; q < S::VW; ++q) {
             const int c = g * S::VW + q;
-            ln.act[q] = ctl->status[c] != COL_IDLE;
+            ln.act[q] = (cmask >> c) & 1u;
             ln.zero[q] = (ctl->flag[c] & F_ZERO_X) != 0;
             ln.mean[q] = ctl->colsum[c] / static_cast<double>(ctl->n);
             ln.on = ln.on || ln.act[q];
@@ -751,22 +758,35 @@ struct OpColSum {
     static constexpr int NDOT = 1;
     const double *x;
     Ctl *ctl;
+    uint32_t cmask;
     struct Lane {
         bool on;
+        bool act[S::VW];
     };
-    __device__ Lane lane(int) const { return {true}; }
-    __device__ __forceinline__ void row(const Lane &, int32_t i, int g, Acc<double, S::VW, NDOT> &acc) const
+    __device__ Lane lane(int g) const
+    {
+        Lane ln;
+        ln.on = false;
+#pragma unroll
+        for (int q = 0; q < S::VW; ++q) {
+            ln.act[q] = (cmask >> (g * S::VW + q)) & 1u;
+            ln.on = ln.on || ln.act[q];
+        }
+        return ln;
+    }
+    __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, Acc<double, S::VW, NDOT> &acc) const
     {
         double a[S::VW];
         Vec<double, S::VW>::load(x + static_cast<size_t>(i) * M + g * S::VW, a);
 #pragma unroll
         for (int q = 0; q < S::VW; ++q)
-            acc.a[0][q] += a[q];
+            if (ln.act[q])
+                acc.a[0][q] += a[q];
     }
     __device__ void finish(const double *tot) const
     {
         const int c = threadIdx.x;
-        if (c < M)
+        if (c < M && ((cmask >> c) & 1u))
             ctl->colsum[c] = tot[c];
     }
 };
@@ -849,12 +869,19 @@ struct OpCast {
 // Mixed precision refinement step (binary64), for every column whose binary32
 // inner solve ended.  The inner solve of Ah32 y = r/||r|| gives the correction
 // z = ||r|| D^-1 y; with w = A z the step is made minimal-residual over the
-// current and the stored directions (generalized conjugate residuals):
+// new and the column's stored directions (generalized conjugate residuals,
+// truncated to the most recent ndirs directions):
 //   w -= sum_j beta_j w_j, z -= sum_j beta_j z_j, beta_j = (w, w_j)/(w_j, w_j)
 //   gamma = (r, w)/(w, w);  x += gamma z;  r -= gamma w.
+// Every column keeps its own directions (slot kcol[c] receives the next one),
+// so a column's arithmetic never depends on the other columns of the block.
 struct GcrBlocks {
     double *z[kGcrMax];
     double *w[kGcrMax];
+    double *znew;
+    double *wnew;
+    int32_t ndirs;  // directions kept per column
+    int32_t jmax;   // slots that can hold a direction of any column so far
 };
 
 template <int M>
@@ -871,7 +898,7 @@ __device__ __forceinline__ RunLane<double, M> inner_done_lane(const Ctl *ctl, in
     return ln;
 }
 
-// z_k = ||r|| * D^-1 * y32 (zero in other columns)
+// z_new = ||r|| * D^-1 * y32 (zero in the other columns)
 template <int M>
 struct OpGcrZ {
     using S = Shape<double, M>;
@@ -911,32 +938,32 @@ struct OpGcrZ {
     __device__ void finish(const double *) const {}
 };
 
-// beta_j = (w_k, w_j) / (w_j, w_j) for j < k
+// beta_j = (w_new, w_j) / (w_j, w_j) over the column's stored directions
+// (slot kcol[c] is about to be replaced and is left out)
 template <int M>
 struct OpGcrDots {
     using S = Shape<double, M>;
     static constexpr const char *kName = "gcr_dots";
     static constexpr int NDOT = kGcrMax;
     GcrBlocks b;
-    int32_t k;
     Ctl *ctl;
     using Lane = RunLane<double, M>;
     __device__ Lane lane(int g) const { return inner_done_lane<M>(ctl, g); }
     __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, Acc<double, S::VW, NDOT> &acc) const
     {
         const size_t o = static_cast<size_t>(i) * M + g * S::VW;
-        double wk[S::VW];
-        Vec<double, S::VW>::load(b.w[k] + o, wk);
+        double wn[S::VW];
+        Vec<double, S::VW>::load(b.wnew + o, wn);
 #pragma unroll
         for (int j = 0; j < kGcrMax; ++j) {
-            if (j >= k)
+            if (j >= b.jmax)
                 break;
             double wj[S::VW];
             Vec<double, S::VW>::load(b.w[j] + o, wj);
 #pragma unroll
             for (int q = 0; q < S::VW; ++q)
                 if (ln.act[q])
-                    acc.a[j][q] += wk[q] * wj[q];
+                    acc.a[j][q] += wn[q] * wj[q];
         }
     }
     __device__ void finish(const double *tot) const
@@ -946,12 +973,16 @@ struct OpGcrDots {
             return;
         for (int j = 0; j < kGcrMax; ++j) {
             const double d = ctl->wnorm2[j][c];
-            ctl->beta[j][c] = (j < k && d > 0.0 && isfinite(d)) ? tot[j * M + c] / d : 0.0;
+            const bool valid = j < b.jmax && j != ctl->kcol[c] && d > 0.0 && isfinite(d);
+            const double bj = valid ? tot[j * M + c] / d : 0.0;
+            ctl->beta[j][c] = isfinite(bj) ? bj : 0.0;
         }
     }
 };
 
-// w_k -= sum beta_j w_j, z_k -= sum beta_j z_j; sums (w_k, w_k), (r, w_k)
+// w_new -= sum beta_j w_j, z_new -= sum beta_j z_j; sums (w_new, w_new) and
+// (r, w_new).  Terms with beta_j = 0 are skipped, so slots holding stale data
+// of other requests never enter a column's arithmetic.
 template <int M>
 struct OpGcrOrth {
     using S = Shape<double, M>;
@@ -959,7 +990,6 @@ struct OpGcrOrth {
     static constexpr int NDOT = 2;
     GcrBlocks b;
     const double *r;
-    int32_t k;
     Ctl *ctl;
     struct Lane {
         bool on;
@@ -983,54 +1013,51 @@ struct OpGcrOrth {
     __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, Acc<double, S::VW, NDOT> &acc) const
     {
         const size_t o = static_cast<size_t>(i) * M + g * S::VW;
-        double wk[S::VW], zk[S::VW], rr[S::VW];
-        Vec<double, S::VW>::load(b.w[k] + o, wk);
-        Vec<double, S::VW>::load(b.z[k] + o, zk);
+        double wn[S::VW], zn[S::VW], rr[S::VW];
+        Vec<double, S::VW>::load(b.wnew + o, wn);
+        Vec<double, S::VW>::load(b.znew + o, zn);
         Vec<double, S::VW>::load(r + o, rr);
 #pragma unroll
         for (int j = 0; j < kGcrMax; ++j) {
-            if (j >= k)
+            if (j >= b.jmax)
                 break;
             double wj[S::VW], zj[S::VW];
             Vec<double, S::VW>::load(b.w[j] + o, wj);
             Vec<double, S::VW>::load(b.z[j] + o, zj);
 #pragma unroll
             for (int q = 0; q < S::VW; ++q) {
-                if (ln.act[q]) {
-                    wk[q] -= ln.beta[j][q] * wj[q];
-                    zk[q] -= ln.beta[j][q] * zj[q];
+                if (ln.act[q] && ln.beta[j][q] != 0.0) {
+                    wn[q] -= ln.beta[j][q] * wj[q];
+                    zn[q] -= ln.beta[j][q] * zj[q];
                 }
             }
         }
 #pragma unroll
         for (int q = 0; q < S::VW; ++q) {
             if (ln.act[q]) {
-                acc.a[0][q] += wk[q] * wk[q];
-                acc.a[1][q] += rr[q] * wk[q];
+                acc.a[0][q] += wn[q] * wn[q];
+                acc.a[1][q] += rr[q] * wn[q];
             }
         }
-        if (k > 0) {
-            put<double, S::VW>(b.w[k] + o, wk);
-            put<double, S::VW>(b.z[k] + o, zk);
+        if (b.jmax > 0) {
+            put<double, S::VW>(b.wnew + o, wn);
+            put<double, S::VW>(b.znew + o, zn);
         }
     }
     __device__ void finish(const double *tot) const
     {
         const int c = threadIdx.x;
-        if (c >= M)
+        if (c >= M || ctl->status[c] != COL_INNER_DONE)
             return;
-        if (ctl->status[c] != COL_INNER_DONE) {
-            ctl->wnorm2[k][c] = 0.0;  // this slot holds no direction of column c
-            return;
-        }
         const double ww = tot[c], rw = tot[M + c];
-        ctl->wnorm2[k][c] = ww;
+        ctl->wnew2[c] = ww;
         ctl->gamma[c] = (ww > 0.0 && isfinite(ww) && isfinite(rw)) ? rw / ww : 0.0;
     }
 };
 
-// x += gamma z_k;  r -= gamma w_k; sums (r, r).  The last workgroup decides
-// each column's next state.
+// x += gamma z_new;  r -= gamma w_new; the new direction is stored in the
+// column's slot kcol[c]; sums (r, r).  The last workgroup decides each
+// column's next state.
 template <int M>
 struct OpGcrUpdate {
     using S = Shape<double, M>;
@@ -1038,13 +1065,14 @@ struct OpGcrUpdate {
     static constexpr int NDOT = 1;
     double *x;
     double *r;
-    const double *z;
-    const double *w;
+    GcrBlocks b;
     Ctl *ctl;
     struct Lane {
         bool on;
         bool act[S::VW];
         double gamma[S::VW];
+        double *zs[S::VW];
+        double *ws[S::VW];
     };
     __device__ Lane lane(int g) const
     {
@@ -1053,8 +1081,12 @@ struct OpGcrUpdate {
         ln.on = rl.on;
 #pragma unroll
         for (int q = 0; q < S::VW; ++q) {
+            const int c = g * S::VW + q;
             ln.act[q] = rl.act[q];
-            ln.gamma[q] = ctl->gamma[g * S::VW + q];
+            ln.gamma[q] = ctl->gamma[c];
+            const int k = ctl->kcol[c];
+            ln.zs[q] = b.z[k];
+            ln.ws[q] = b.w[k];
         }
         return ln;
     }
@@ -1064,14 +1096,16 @@ struct OpGcrUpdate {
         double xx[S::VW], rr[S::VW], zz[S::VW], ww[S::VW];
         Vec<double, S::VW>::load(x + o, xx);
         Vec<double, S::VW>::load(r + o, rr);
-        Vec<double, S::VW>::load(z + o, zz);
-        Vec<double, S::VW>::load(w + o, ww);
+        Vec<double, S::VW>::load(b.znew + o, zz);
+        Vec<double, S::VW>::load(b.wnew + o, ww);
 #pragma unroll
         for (int q = 0; q < S::VW; ++q) {
             if (ln.act[q]) {
                 xx[q] += ln.gamma[q] * zz[q];
                 rr[q] -= ln.gamma[q] * ww[q];
                 acc.a[0][q] += rr[q] * rr[q];
+                __builtin_nontemporal_store(zz[q], ln.zs[q] + o + q);
+                __builtin_nontemporal_store(ww[q], ln.ws[q] + o + q);
             }
         }
         put<double, S::VW>(x + o, xx);
@@ -1083,6 +1117,9 @@ struct OpGcrUpdate {
         if (c >= M || ctl->status[c] != COL_INNER_DONE)
             return;
         Ctl &k = *ctl;
+        const int slot = k.kcol[c];
+        k.wnorm2[slot][c] = k.wnew2[c];
+        k.kcol[c] = (slot + 1) % b.ndirs;
         const double nr = sqrt(tot[c]);
         k.total_iters[c] += k.iters[c];
         k.iters[c] = 0;
@@ -1099,6 +1136,12 @@ struct OpGcrUpdate {
             k.status[c] = COL_OUTER;
         }
     }
+};
+
+// Admission of columns into a block: reset their control state.
+struct SlotInit {
+    double tol[kMaxM];
+    int32_t maxit[kMaxM];
 };
 
 } // namespace mrhs

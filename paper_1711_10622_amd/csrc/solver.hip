@@ -1,7 +1,8 @@
-// Block BiCGStab drivers: binary64, and binary32 inner solves inside binary64
-// iterative refinement.  The iteration itself runs entirely on the device
-// (ops.h); the host enqueues chunks of iterations and reads the m column
-// states once per chunk.
+// Block BiCGStab engine: m column slots sharing one matrix, driven from the
+// host in rounds.  Each round reads the column states once and enqueues what
+// the columns need next (true-residual checks, refinement steps, a chunk of
+// iterations); every decision inside an iteration is taken on the device
+// (ops.h).  A one-shot block solve and the solve server both run on it.
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
@@ -9,6 +10,26 @@
 #include "internal.h"
 
 namespace mrhs {
+
+int env_int(const char *name, int dflt, int lo, int hi)
+{
+    const char *v = std::getenv(name);
+    if (!v || !*v)
+        return dflt;
+    const int x = std::atoi(v);
+    return std::min(hi, std::max(lo, x));
+}
+
+double env_double(const char *name, double dflt)
+{
+    const char *v = std::getenv(name);
+    if (!v || !*v)
+        return dflt;
+    const double x = std::atof(v);
+    return x > 0 ? x : dflt;
+}
+
+int gcr_dirs() { return env_int("MRHS_GCR_DIRS", kGcrMax, 1, kGcrMax); }
 
 namespace {
 
@@ -18,18 +39,14 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
     size_t ctl, kry64, kry32, tickets, part, gpart;
-    size_t v64[5];           // r, r^, p, v, t                 (binary64 solve)
-    size_t r64;              // refinement residual            (mixed)
-    size_t z[kGcrMax];       // refinement directions z_j      (mixed)
-    size_t w[kGcrMax];       // and w_j = A z_j                (mixed)
-    size_t v32[6];           // r, r^, p, v, t, y              (mixed, binary32)
+    size_t v64[5];      // r, r^, p, v, t                  (binary64 solve)
+    size_t r64;         // refinement residual             (mixed)
+    size_t z[kGcrMax];  // stored directions z_j           (mixed)
+    size_t w[kGcrMax];  // and w_j = A z_j                 (mixed)
+    size_t znew, wnew;  // the direction being formed      (mixed)
+    size_t v32[6];      // r, r^, p, v, t, y               (mixed, binary32)
     size_t total;
 };
-
-int env_int(const char *name, int dflt, int lo, int hi);
-
-// Stored refinement directions (1..kGcrMax; MRHS_GCR_DIRS overrides the default).
-int gcr_dirs() { return env_int("MRHS_GCR_DIRS", kGcrMax, 1, kGcrMax); }
 
 Layout layout(int32_t n, int32_t m, uint32_t flags)
 {
@@ -55,6 +72,8 @@ Layout layout(int32_t n, int32_t m, uint32_t flags)
             L.z[i] = take(blk64);
             L.w[i] = take(blk64);
         }
+        L.znew = take(blk64);
+        L.wnew = take(blk64);
         for (int i = 0; i < 6; ++i)
             L.v32[i] = take(blk32);
     } else {
@@ -72,40 +91,70 @@ __global__ void k_fill_u32(unsigned *p, int count, unsigned value)
         p[i] = value;
 }
 
-struct Ctx {
-    const mrhs_csr_s *A;
-    const double *B;
-    double *X;
-    int32_t n;
-    hipStream_t s;
-    Ctl *ctl;
-    Kry<double> *kry64;
-    Kry<float> *kry32;
-    RedBufs<double> rb64;
-    RedBufs<float> rb32;
-    double *r, *rh, *p, *v, *t;
-    double *r64;
-    GcrBlocks gcr;
-    float *r32, *rh32, *p32, *v32, *t32, *y32;
-};
+// Admission of columns into a block: reset their control state.
+__global__ void k_slot_init(Ctl *ctl, uint32_t cmask, SlotInit si)
+{
+    const int c = threadIdx.x;
+    if (c >= kMaxM || !((cmask >> c) & 1u))
+        return;
+    Ctl &k = *ctl;
+    k.status[c] = COL_INIT;
+    k.fresh[c] = 1;
+    k.flag[c] = 0;
+    k.iters[c] = 0;
+    k.maxit[c] = si.maxit[c];
+    k.restarts[c] = 0;
+    k.breakdowns[c] = 0;
+    k.bd_run[c] = 0;
+    k.outer[c] = 0;
+    k.total_iters[c] = 0;
+    k.stag_it[c] = 0;
+    k.inner_maxit[c] = si.maxit[c];
+    k.nb[c] = 0.0;
+    k.tol[c] = si.tol[c];
+    k.rn[c] = 0.0;
+    k.stag_rn[c] = 1.0;
+    k.relres[c] = 0.0;
+    k.rscale[c] = 0.0;
+    k.colsum[c] = 0.0;
+    k.kcol[c] = 0;
+    k.wnew2[c] = 0.0;
+    k.gamma[c] = 0.0;
+    for (int j = 0; j < kGcrMax; ++j) {
+        k.beta[j][c] = 0.0;
+        k.wnorm2[j][c] = 0.0;
+    }
+}
 
-#define MRHS_TRY(expr)                    \
-    do {                                  \
-        hipError_t e_ = (expr);           \
-        if (e_ != hipSuccess)             \
-            return e_;                    \
+__global__ void k_ctl_reset(Ctl *ctl, int32_t mode, double tol_in, int32_t max_outer, int32_t n)
+{
+    if (threadIdx.x == 0) {
+        Ctl &k = *ctl;
+        for (int c = 0; c < kMaxM; ++c)
+            k.status[c] = COL_IDLE;
+        k.mode = mode;
+        k.tol_in = tol_in;
+        k.max_outer = max_outer;
+        k.n = n;
+    }
+}
+
+#define MRHS_TRY(expr)          \
+    do {                        \
+        hipError_t e_ = (expr); \
+        if (e_ != hipSuccess)   \
+            return e_;          \
     } while (0)
 
 template <int M>
 struct Steps {
-    static hipError_t f64_setup(Ctx &c, bool x0)
+    static hipError_t f64_start(Ctx &c, uint32_t cmask, bool x0)
     {
-        MRHS_TRY((launch_stream<double, M>(c.n, OpScale<M>{c.X, c.A->diag, c.A->dinv, c.ctl,
-                                                             x0 ? SC_IN : SC_ZERO},
-                                            c.rb64, c.s)));
+        MRHS_TRY((launch_stream<double, M>(
+            c.n, OpScale<M>{c.X, c.A->diag, c.A->dinv, c.ctl, x0 ? SC_IN : SC_ZERO, cmask}, c.rb64, c.s)));
         return launch_gspmv<double, M>(view<double>(*c.A, true),
-                                       OpResid<M>{c.X, c.B, c.r, c.rh, c.ctl, c.kry64, RES_SETUP},
-                                       c.rb64, c.s);
+                                       OpResid<M>{c.X, c.B, c.r, c.rh, c.ctl, c.kry64, RES_SETUP, 0u}, c.rb64,
+                                       c.s);
     }
     static hipError_t f64_iterate(Ctx &c, int k)
     {
@@ -125,56 +174,54 @@ struct Steps {
     static hipError_t f64_check(Ctx &c)
     {
         MRHS_TRY((launch_gspmv<double, M>(view<double>(*c.A, true),
-                                           OpResid<M>{c.X, c.B, c.t, nullptr, c.ctl, c.kry64, RES_CHECK},
+                                           OpResid<M>{c.X, c.B, c.t, nullptr, c.ctl, c.kry64, RES_CHECK, 0u},
                                            c.rb64, c.s)));
         return launch_stream<double, M>(c.n, OpRestart<double, M>{c.t, c.r, c.rh, c.ctl}, c.rb64, c.s);
     }
-    static hipError_t finish(Ctx &c, bool mixed, bool nullspace)
+    static hipError_t finish(Ctx &c, uint32_t cmask, bool mixed, bool nullspace)
     {
-        MRHS_TRY((launch_stream<double, M>(c.n, OpScale<M>{c.X, c.A->diag, c.A->dinv, c.ctl,
-                                                             mixed ? SC_FIX_ZERO : SC_OUT},
-                                            c.rb64, c.s)));
+        MRHS_TRY((launch_stream<double, M>(
+            c.n, OpScale<M>{c.X, c.A->diag, c.A->dinv, c.ctl, mixed ? SC_FIX_ZERO : SC_OUT, cmask}, c.rb64, c.s)));
         if (nullspace) {
-            MRHS_TRY((launch_stream<double, M>(c.n, OpColSum<M>{c.X, c.ctl}, c.rb64, c.s)));
+            MRHS_TRY((launch_stream<double, M>(c.n, OpColSum<M>{c.X, c.ctl, cmask}, c.rb64, c.s)));
             MRHS_TRY((launch_stream<double, M>(
-                c.n, OpScale<M>{c.X, c.A->diag, c.A->dinv, c.ctl, SC_SUB_MEAN}, c.rb64, c.s)));
+                c.n, OpScale<M>{c.X, c.A->diag, c.A->dinv, c.ctl, SC_SUB_MEAN, cmask}, c.rb64, c.s)));
         }
         return launch_gspmv<double, M>(view<double>(*c.A, false),
-                                       OpResid<M>{c.X, c.B, nullptr, nullptr, c.ctl, c.kry64, RES_FINAL},
+                                       OpResid<M>{c.X, c.B, nullptr, nullptr, c.ctl, c.kry64, RES_FINAL, cmask},
                                        c.rb64, c.s);
     }
-    static hipError_t mixed_setup(Ctx &c, bool x0)
+    static hipError_t mixed_start(Ctx &c, uint32_t cmask, bool x0)
     {
         if (!x0)
             MRHS_TRY((launch_stream<double, M>(
-                c.n, OpScale<M>{c.X, c.A->diag, c.A->dinv, c.ctl, SC_ZERO}, c.rb64, c.s)));
+                c.n, OpScale<M>{c.X, c.A->diag, c.A->dinv, c.ctl, SC_ZERO, cmask}, c.rb64, c.s)));
         return launch_gspmv<double, M>(view<double>(*c.A, false),
-                                       OpResid<M>{c.X, c.B, c.r64, nullptr, c.ctl, c.kry64, RES_SETUP},
+                                       OpResid<M>{c.X, c.B, c.r64, nullptr, c.ctl, c.kry64, RES_SETUP, 0u},
                                        c.rb64, c.s);
     }
-    // one refinement step on slot k for every column whose inner solve ended
-    static hipError_t mixed_step(Ctx &c, int k)
+    // one refinement step for every column whose inner solve ended
+    static hipError_t mixed_step(Ctx &c)
     {
-        MRHS_TRY((launch_stream<double, M>(c.n, OpGcrZ<M>{c.gcr.z[k], c.y32, c.A->dinv, c.ctl}, c.rb64, c.s)));
-        MRHS_TRY((launch_gspmv<double, M>(view<double>(*c.A, false), OpStore<double, M>{c.gcr.z[k], c.gcr.w[k]},
+        MRHS_TRY((launch_stream<double, M>(c.n, OpGcrZ<M>{c.gcr.znew, c.y32, c.A->dinv, c.ctl}, c.rb64, c.s)));
+        MRHS_TRY((launch_gspmv<double, M>(view<double>(*c.A, false), OpStore<double, M>{c.gcr.znew, c.gcr.wnew},
                                            c.rb64, c.s)));
-        if (k > 0)
-            MRHS_TRY((launch_stream<double, M>(c.n, OpGcrDots<M>{c.gcr, k, c.ctl}, c.rb64, c.s)));
-        MRHS_TRY((launch_stream<double, M>(c.n, OpGcrOrth<M>{c.gcr, c.r64, k, c.ctl}, c.rb64, c.s)));
-        return launch_stream<double, M>(c.n, OpGcrUpdate<M>{c.X, c.r64, c.gcr.z[k], c.gcr.w[k], c.ctl}, c.rb64,
-                                        c.s);
+        if (c.gcr.jmax > 0)
+            MRHS_TRY((launch_stream<double, M>(c.n, OpGcrDots<M>{c.gcr, c.ctl}, c.rb64, c.s)));
+        MRHS_TRY((launch_stream<double, M>(c.n, OpGcrOrth<M>{c.gcr, c.r64, c.ctl}, c.rb64, c.s)));
+        return launch_stream<double, M>(c.n, OpGcrUpdate<M>{c.X, c.r64, c.gcr, c.ctl}, c.rb64, c.s);
     }
     // true residual of columns whose refinement residual met the tolerance
     static hipError_t mixed_check(Ctx &c)
     {
         return launch_gspmv<double, M>(view<double>(*c.A, false),
-                                       OpResid<M>{c.X, c.B, c.r64, nullptr, c.ctl, c.kry64, RES_MIXCHECK},
+                                       OpResid<M>{c.X, c.B, c.r64, nullptr, c.ctl, c.kry64, RES_MIXCHECK, 0u},
                                        c.rb64, c.s);
     }
     static hipError_t mixed_cast(Ctx &c)
     {
-        return launch_stream<float, M>(c.n, OpCast<M>{c.r64, c.r32, c.rh32, c.y32, c.ctl, c.kry32},
-                                       c.rb32, c.s);
+        return launch_stream<float, M>(c.n, OpCast<M>{c.r64, c.r32, c.rh32, c.y32, c.ctl, c.kry32}, c.rb32,
+                                       c.s);
     }
     static hipError_t inner_iterate(Ctx &c, int k)
     {
@@ -194,103 +241,18 @@ struct Steps {
     }
 };
 
-struct StepTable {
-    hipError_t (*f64_setup)(Ctx &, bool);
-    hipError_t (*f64_iterate)(Ctx &, int);
-    hipError_t (*f64_check)(Ctx &);
-    hipError_t (*finish)(Ctx &, bool, bool);
-    hipError_t (*mixed_setup)(Ctx &, bool);
-    hipError_t (*mixed_step)(Ctx &, int);
-    hipError_t (*mixed_check)(Ctx &);
-    hipError_t (*mixed_cast)(Ctx &);
-    hipError_t (*inner_iterate)(Ctx &, int);
-};
-
 struct MakeTable {
     template <int M>
     StepTable operator()() const
     {
-        return {&Steps<M>::f64_setup, &Steps<M>::f64_iterate, &Steps<M>::f64_check, &Steps<M>::finish,
-                &Steps<M>::mixed_setup, &Steps<M>::mixed_step, &Steps<M>::mixed_check, &Steps<M>::mixed_cast,
-                &Steps<M>::inner_iterate};
+        return {&Steps<M>::f64_start,   &Steps<M>::f64_iterate, &Steps<M>::f64_check,
+                &Steps<M>::finish,      &Steps<M>::mixed_start, &Steps<M>::mixed_step,
+                &Steps<M>::mixed_check, &Steps<M>::mixed_cast,  &Steps<M>::inner_iterate};
     }
 };
 
-int env_int(const char *name, int dflt, int lo, int hi)
+const StepTable &table(int m)
 {
-    const char *v = std::getenv(name);
-    if (!v || !*v)
-        return dflt;
-    const int x = std::atoi(v);
-    return std::min(hi, std::max(lo, x));
-}
-
-double env_double(const char *name, double dflt)
-{
-    const char *v = std::getenv(name);
-    if (!v || !*v)
-        return dflt;
-    const double x = std::atof(v);
-    return x > 0 ? x : dflt;
-}
-
-// Pinned host mirror of the control block, one per host thread.
-Ctl *host_ctl()
-{
-    thread_local Ctl *p = nullptr;
-    if (!p) {
-        void *q = nullptr;
-        if (hipHostMalloc(&q, sizeof(Ctl), hipHostMallocDefault) != hipSuccess)
-            return nullptr;
-        p = static_cast<Ctl *>(q);
-    }
-    return p;
-}
-
-struct StatusCount {
-    int run = 0, pending = 0, inner_done = 0, outer = 0;
-};
-
-StatusCount count(const Ctl &h, int m)
-{
-    StatusCount c;
-    for (int i = 0; i < m; ++i) {
-        const int32_t st = h.status[i];
-        c.run += st == COL_RUN;
-        c.pending += st == COL_PEND_CHECK || st == COL_PEND_BD;
-        c.inner_done += st == COL_INNER_DONE;
-        c.outer += st == COL_OUTER;
-    }
-    return c;
-}
-
-mrhs_status col_status(int32_t st)
-{
-    switch (st) {
-    case COL_DONE: return MRHS_OK;
-    case COL_BREAKDOWN: return MRHS_EBREAKDOWN;
-    default: return MRHS_ENOCONV;
-    }
-}
-
-} // namespace
-
-size_t solve_workspace_bytes(const mrhs_csr_s &A, int32_t m, uint32_t flags)
-{
-    return layout(A.n, m, flags).total;
-}
-
-mrhs_status block_solve(const mrhs_csr_s &A, const double *B, double *X, const SolveParams &p,
-                        void *ws, size_t ws_bytes, hipStream_t s, mrhs_col_info *info)
-{
-    const int m = p.m;
-    const bool mixed = (p.flags & MRHS_MIXED) != 0;
-    const bool x0 = (p.flags & MRHS_X0_GIVEN) != 0;
-    const bool nullspace = (A.flags & MRHS_CSR_NULLSPACE_CONST) != 0;
-    const Layout L = layout(A.n, m, p.flags);
-    if (ws_bytes < L.total)
-        return set_error(MRHS_EINVAL, "workspace of %zu bytes is smaller than the %zu required", ws_bytes,
-                         L.total);
     static const StepTable tables[kMaxM + 1] = {
         {},
         MakeTable{}.operator()<1>(),  MakeTable{}.operator()<2>(),  MakeTable{}.operator()<3>(),
@@ -300,117 +262,211 @@ mrhs_status block_solve(const mrhs_csr_s &A, const double *B, double *X, const S
         MakeTable{}.operator()<13>(), MakeTable{}.operator()<14>(), MakeTable{}.operator()<15>(),
         MakeTable{}.operator()<16>(),
     };
-    const StepTable &T = tables[m];
+    return tables[m];
+}
 
+} // namespace
+
+mrhs_status column_status(int32_t st)
+{
+    switch (st) {
+    case COL_DONE: return MRHS_OK;
+    case COL_BREAKDOWN: return MRHS_EBREAKDOWN;
+    default: return MRHS_ENOCONV;
+    }
+}
+
+size_t Engine::workspace_bytes(const mrhs_csr_s &A, int32_t m, uint32_t flags)
+{
+    return layout(A.n, m, flags).total;
+}
+
+Engine::Engine(const mrhs_csr_s &A, int m, uint32_t flags, void *ws, const double *B, double *X, hipStream_t s)
+    : A_(A), m_(m), mixed_((flags & MRHS_MIXED) != 0), nullspace_((A.flags & MRHS_CSR_NULLSPACE_CONST) != 0),
+      s_(s), T_(&table(m))
+{
+    const Layout L = layout(A.n, m, flags);
     char *base = static_cast<char *>(ws);
-    Ctx c{};
-    c.A = &A;
-    c.B = B;
-    c.X = X;
-    c.n = A.n;
-    c.s = s;
-    c.ctl = reinterpret_cast<Ctl *>(base + L.ctl);
-    c.kry64 = reinterpret_cast<Kry<double> *>(base + L.kry64);
-    c.kry32 = reinterpret_cast<Kry<float> *>(base + L.kry32);
-    unsigned *tickets = reinterpret_cast<unsigned *>(base + L.tickets);
-    c.rb64 = {reinterpret_cast<double *>(base + L.part), reinterpret_cast<double *>(base + L.gpart), tickets};
-    c.rb32 = {reinterpret_cast<float *>(base + L.part), reinterpret_cast<float *>(base + L.gpart), tickets};
-    if (mixed) {
-        c.r64 = reinterpret_cast<double *>(base + L.r64);
-        for (int i = 0; i < gcr_dirs(); ++i) {
-            c.gcr.z[i] = reinterpret_cast<double *>(base + L.z[i]);
-            c.gcr.w[i] = reinterpret_cast<double *>(base + L.w[i]);
+    c_.A = &A;
+    c_.B = B;
+    c_.X = X;
+    c_.n = A.n;
+    c_.s = s;
+    c_.ctl = reinterpret_cast<Ctl *>(base + L.ctl);
+    c_.kry64 = reinterpret_cast<Kry<double> *>(base + L.kry64);
+    c_.kry32 = reinterpret_cast<Kry<float> *>(base + L.kry32);
+    tickets_ = reinterpret_cast<unsigned *>(base + L.tickets);
+    c_.rb64 = {reinterpret_cast<double *>(base + L.part), reinterpret_cast<double *>(base + L.gpart), tickets_};
+    c_.rb32 = {reinterpret_cast<float *>(base + L.part), reinterpret_cast<float *>(base + L.gpart), tickets_};
+    ndirs_ = gcr_dirs();
+    if (mixed_) {
+        c_.r64 = reinterpret_cast<double *>(base + L.r64);
+        for (int i = 0; i < ndirs_; ++i) {
+            c_.gcr.z[i] = reinterpret_cast<double *>(base + L.z[i]);
+            c_.gcr.w[i] = reinterpret_cast<double *>(base + L.w[i]);
         }
-        float **v32[6] = {&c.r32, &c.rh32, &c.p32, &c.v32, &c.t32, &c.y32};
+        c_.gcr.znew = reinterpret_cast<double *>(base + L.znew);
+        c_.gcr.wnew = reinterpret_cast<double *>(base + L.wnew);
+        c_.gcr.ndirs = ndirs_;
+        c_.gcr.jmax = 0;
+        float **v32[6] = {&c_.r32, &c_.rh32, &c_.p32, &c_.v32, &c_.t32, &c_.y32};
         for (int i = 0; i < 6; ++i)
             *v32[i] = reinterpret_cast<float *>(base + L.v32[i]);
     } else {
-        double **v64[5] = {&c.r, &c.rh, &c.p, &c.v, &c.t};
+        double **v64[5] = {&c_.r, &c_.rh, &c_.p, &c_.v, &c_.t};
         for (int i = 0; i < 5; ++i)
             *v64[i] = reinterpret_cast<double *>(base + L.v64[i]);
     }
+    chunk_ = env_int("MRHS_POLL_ITERS", 16, 1, 1024);
+    tol_in_ = env_double("MRHS_INNER_TOL", 0.1);
+    max_outer_ = env_int("MRHS_MAX_OUTER", 500, 1, 100000);
+}
 
-    Ctl *h = host_ctl();
-    if (!h)
-        return set_error(MRHS_ENOMEM, "pinned host buffer allocation failed");
-    std::memset(h, 0, sizeof(Ctl));
-    for (int i = 0; i < m; ++i) {
-        h->status[i] = COL_RUN;
-        h->tol[i] = p.tol;
-        h->maxit[i] = p.maxit;
-        h->inner_maxit[i] = p.maxit;
+Engine::~Engine()
+{
+    if (host_)
+        (void)hipHostFree(host_);
+}
+
+mrhs_status Engine::reset()
+{
+    if (!host_) {
+        void *q = nullptr;
+        if (hipHostMalloc(&q, sizeof(Ctl), hipHostMallocDefault) != hipSuccess)
+            return set_error(MRHS_ENOMEM, "pinned host buffer allocation failed");
+        host_ = static_cast<Ctl *>(q);
     }
-    h->mode = mixed ? MODE_INNER : MODE_F64;
-    h->tol_in = env_double("MRHS_INNER_TOL", 0.1);
-    h->max_outer = env_int("MRHS_MAX_OUTER", 500, 1, 100000);
-    h->n = A.n;
-    const int chunk = env_int("MRHS_POLL_ITERS", 16, 1, 1024);
-
-    MRHS_HIP(hipMemcpyAsync(c.ctl, h, sizeof(Ctl), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, tickets, kGroups + 1, 0u);
+    std::memset(host_, 0, sizeof(Ctl));
+    gcr_steps_ = 0;
+    c_.gcr.jmax = 0;
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s_, tickets_, kGroups + 1, 0u);
+    hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, s_, c_.ctl, mixed_ ? MODE_INNER : MODE_F64, tol_in_,
+                       max_outer_, A_.n);
     MRHS_HIP(hipGetLastError());
+    return MRHS_OK;
+}
 
-    auto read_status = [&]() -> hipError_t {
-        hipError_t e = hipMemcpyAsync(h->status, c.ctl->status, sizeof(int32_t) * m, hipMemcpyDeviceToHost, s);
-        if (e != hipSuccess)
-            return e;
-        return hipStreamSynchronize(s);
-    };
-
-    if (!mixed) {
-        MRHS_HIP(T.f64_setup(c, x0));
-        MRHS_HIP(read_status());
-        for (;;) {
-            const StatusCount sc = count(*h, m);
-            if (sc.pending) {
-                MRHS_HIP(T.f64_check(c));
-                MRHS_HIP(read_status());
-                continue;
-            }
-            if (!sc.run)
-                break;
-            MRHS_HIP(T.f64_iterate(c, chunk));
-            MRHS_HIP(read_status());
-        }
-    } else {
-        // binary32 inner solves, binary64 refinement steps (all columns in
-        // step: every inner phase runs until no column is iterating)
-        const int ndirs = gcr_dirs();
-        int slot = 0;
-        MRHS_HIP(T.mixed_setup(c, x0));
-        for (;;) {
-            MRHS_HIP(read_status());
-            const StatusCount sc = count(*h, m);
-            if (sc.pending) {
-                MRHS_HIP(T.mixed_check(c));
-                continue;
-            }
-            if (!sc.outer)
-                break;
-            MRHS_HIP(T.mixed_cast(c));
-            for (;;) {
-                MRHS_HIP(read_status());
-                if (!count(*h, m).run)
-                    break;
-                MRHS_HIP(T.inner_iterate(c, chunk));
-            }
-            MRHS_HIP(T.mixed_step(c, slot));
-            slot = (slot + 1) % ndirs;
-        }
+mrhs_status Engine::start(uint32_t cmask, const double *tol, const int32_t *maxit, bool x0)
+{
+    SlotInit si{};
+    for (int c = 0; c < kMaxM; ++c) {
+        si.tol[c] = c < m_ ? tol[c] : 1.0;
+        si.maxit[c] = c < m_ ? maxit[c] : 1;
     }
-    MRHS_HIP(T.finish(c, mixed, nullspace));
-    MRHS_HIP(hipMemcpyAsync(h, c.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-    MRHS_HIP(hipStreamSynchronize(s));
+    cmask &= (1u << m_) - 1u;
+    hipLaunchKernelGGL(k_slot_init, dim3(1), dim3(64), 0, s_, c_.ctl, cmask, si);
+    MRHS_HIP(hipGetLastError());
+    MRHS_HIP(mixed_ ? T_->mixed_start(c_, cmask, x0) : T_->f64_start(c_, cmask, x0));
+    return MRHS_OK;
+}
 
+mrhs_status Engine::read_status()
+{
+    MRHS_HIP(hipMemcpyAsync(host_->status, c_.ctl->status, sizeof(int32_t) * m_, hipMemcpyDeviceToHost, s_));
+    MRHS_HIP(hipStreamSynchronize(s_));
+    return MRHS_OK;
+}
+
+mrhs_status Engine::read_ctl()
+{
+    MRHS_HIP(hipMemcpyAsync(host_, c_.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s_));
+    MRHS_HIP(hipStreamSynchronize(s_));
+    return MRHS_OK;
+}
+
+bool Engine::terminal(int32_t st) { return st == COL_DONE || st == COL_NOCONV || st == COL_BREAKDOWN; }
+
+uint32_t Engine::terminal_mask() const
+{
+    uint32_t mk = 0;
+    for (int c = 0; c < m_; ++c)
+        if (terminal(host_->status[c]))
+            mk |= 1u << c;
+    return mk;
+}
+
+mrhs_status Engine::advance(bool *busy)
+{
+    mrhs_status st = read_status();
+    if (st != MRHS_OK)
+        return st;
+    int run = 0, pend = 0, done_in = 0, outer = 0;
+    for (int c = 0; c < m_; ++c) {
+        const int32_t s = host_->status[c];
+        run += s == COL_RUN;
+        pend += s == COL_PEND_CHECK || s == COL_PEND_BD;
+        done_in += s == COL_INNER_DONE;
+        outer += s == COL_OUTER;
+    }
+    *busy = run || pend || done_in || outer;
+    if (!*busy)
+        return MRHS_OK;
+    if (!mixed_) {
+        if (pend)
+            MRHS_HIP(T_->f64_check(c_));
+        MRHS_HIP(T_->f64_iterate(c_, chunk_));
+        return MRHS_OK;
+    }
+    if (pend)
+        MRHS_HIP(T_->mixed_check(c_));
+    if (done_in) {
+        MRHS_HIP(T_->mixed_step(c_));
+        ++gcr_steps_;
+        c_.gcr.jmax = std::min(gcr_steps_, ndirs_);
+    }
+    MRHS_HIP(T_->mixed_cast(c_));
+    MRHS_HIP(T_->inner_iterate(c_, chunk_));
+    return MRHS_OK;
+}
+
+mrhs_status Engine::finish(uint32_t cmask)
+{
+    MRHS_HIP(T_->finish(c_, cmask, mixed_, nullspace_));
+    return MRHS_OK;
+}
+
+size_t solve_workspace_bytes(const mrhs_csr_s &A, int32_t m, uint32_t flags)
+{
+    return Engine::workspace_bytes(A, m, flags);
+}
+
+mrhs_status block_solve(const mrhs_csr_s &A, const double *B, double *X, const SolveParams &p, void *ws,
+                        size_t ws_bytes, hipStream_t s, mrhs_col_info *info)
+{
+    const int m = p.m;
+    const size_t need = Engine::workspace_bytes(A, m, p.flags);
+    if (ws_bytes < need)
+        return set_error(MRHS_EINVAL, "workspace of %zu bytes is smaller than the %zu required", ws_bytes, need);
+    Engine e(A, m, p.flags, ws, B, X, s);
+    mrhs_status st = e.reset();
+    if (st != MRHS_OK)
+        return st;
+    double tol[kMaxM];
+    int32_t maxit[kMaxM];
+    for (int c = 0; c < kMaxM; ++c) {
+        tol[c] = p.tol;
+        maxit[c] = p.maxit;
+    }
+    const uint32_t all = (1u << m) - 1u;
+    if ((st = e.start(all, tol, maxit, (p.flags & MRHS_X0_GIVEN) != 0)) != MRHS_OK)
+        return st;
+    bool busy = true;
+    while (busy)
+        if ((st = e.advance(&busy)) != MRHS_OK)
+            return st;
+    if ((st = e.finish(all)) != MRHS_OK || (st = e.read_ctl()) != MRHS_OK)
+        return st;
+    const Ctl &h = e.host();
+    const bool mixed = (p.flags & MRHS_MIXED) != 0;
     mrhs_status worst = MRHS_OK;
     for (int i = 0; i < m; ++i) {
-        const mrhs_status cs = col_status(h->status[i]);
+        const mrhs_status cs = column_status(h.status[i]);
         if (info) {
-            info[i].iters = mixed ? h->total_iters[i] : h->iters[i];
-            info[i].restarts = h->restarts[i];
-            info[i].outer = mixed ? h->outer[i] : 0;
+            info[i].iters = mixed ? h.total_iters[i] : h.iters[i];
+            info[i].restarts = h.restarts[i];
+            info[i].outer = mixed ? h.outer[i] : 0;
             info[i].status = cs;
-            info[i].relres = h->relres[i];
+            info[i].relres = h.relres[i];
         }
         if (cs < worst)
             worst = cs;
