@@ -43,9 +43,8 @@ def kernel_bytes(name, n, nnz, m, S):
     table = {
         "gspmv": mat + 2 * blk,        # read X, write Y
         "spmv_sigma": mat + 3 * blk,   # read p (gathered), r^; write v
-        "spmv_omega": mat + 3 * blk,   # read r, v (gathered); write t
-        "xr_update": 8 * blk,          # read y, r, p, v, t, r^; write y, r
-        "p_update": 4 * blk,           # read r, p, v; write p
+        "spmv_omega": mat + 4 * blk,   # read r, v (gathered), r^; write t
+        "xr_update": 9 * blk,          # read y, r, p, v, t, r^; write y, r, p
     }
     return table.get(name)
 

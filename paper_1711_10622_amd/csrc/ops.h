@@ -9,11 +9,18 @@
 // form), without a separate preconditioner pass.  Per iteration, for every
 // running column (van der Vorst 1992, as cited in Section 1):
 //
-//   p   = r + beta (p - omega v)        beta = (rho/rho_old)(alpha/omega)
 //   v   = Ah p;   sigma = (r^, v);      alpha = rho / sigma
 //   s   = r - alpha v                   (never stored: recomputed where used)
 //   t   = Ah s;   omega = (t, s)/(t, t)
 //   y  += alpha p + omega s;   r = s - omega t;   rho = (r^, r)
+//   p   = r + beta (p - omega v)        beta = (rho_next/rho)(alpha/omega)
+//
+// with p = r at a (re)start.  The p update is done in the same pass as the
+// y and r updates, so beta must be known before that pass: it uses the
+// BiCGStab identity (r^, s) = rho - alpha sigma = 0, i.e.
+// rho_next = (r^, s - omega t) = -omega (r^, t), summed in the t = Ah s
+// pass.  rho itself (for alpha) and ||r|| (for the stopping test) are still
+// the directly summed dot products of that update pass.
 //
 // Each column follows its own control flow (Section 2.2: the m realizations
 // are independent systems sharing A):
@@ -93,6 +100,7 @@ struct Kry {
     T alpha[kMaxM];
     T omega[kMaxM];
     T nbi[kMaxM];
+    T beta[kMaxM];  // for the p update of the current iteration
 };
 
 #ifndef MRHS_NT_STORE
@@ -171,6 +179,7 @@ struct OpResid {
     const double *B;
     double *R;
     double *R2;  // optional second copy of R (may be null)
+    double *R3;  // optional third copy of R (may be null)
     Ctl *ctl;
     Kry<double> *kry;
     int32_t kind;
@@ -230,6 +239,8 @@ struct OpResid {
                 put<double, S::VW>(R + o, r);
             if (R2)
                 put<double, S::VW>(R2 + o, r);
+            if (R3)
+                put<double, S::VW>(R3 + o, r);
         } else {
             // only the columns this kind owns are written
 #pragma unroll
@@ -240,6 +251,8 @@ struct OpResid {
                     R[o + v] = r[v];
                 if (R2)
                     R2[o + v] = r[v];
+                if (R3)
+                    R3[o + v] = r[v];
             }
         }
     }
@@ -360,55 +373,6 @@ __device__ __forceinline__ RunLane<T, M> run_lane(const Ctl *ctl, int g)
     return ln;
 }
 
-// p = r + beta (p - omega v), or p = r right after a (re)start.
-template <typename T, int M>
-struct OpPUpdate {
-    static constexpr const char *kName = "p_update";
-    using S = Shape<T, M>;
-    static constexpr int NDOT = 0;
-    T *p;
-    const T *r;
-    const T *v;
-    const Ctl *ctl;
-    const Kry<T> *kry;
-    struct Lane {
-        bool on;
-        bool act[S::VW];
-        bool fresh[S::VW];
-        T beta[S::VW], omega[S::VW];
-    };
-    __device__ Lane lane(int g) const
-    {
-        Lane ln;
-        const RunLane<T, M> rl = run_lane<T, M>(ctl, g);
-        ln.on = rl.on;
-#pragma unroll
-        for (int q = 0; q < S::VW; ++q) {
-            const int c = g * S::VW + q;
-            ln.act[q] = rl.act[q];
-            ln.fresh[q] = ctl->fresh[c] != 0;
-            ln.omega[q] = kry->omega[c];
-            ln.beta[q] = (kry->rho[c] / kry->rho_old[c]) * (kry->alpha[c] / kry->omega[c]);
-        }
-        return ln;
-    }
-    __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, Acc<T, S::VW, NDOT> &) const
-    {
-        const size_t o = static_cast<size_t>(i) * M + g * S::VW;
-        T rr[S::VW], pp[S::VW], vv[S::VW];
-        Vec<T, S::VW>::load(r + o, rr);
-        Vec<T, S::VW>::load(p + o, pp);
-        Vec<T, S::VW>::load(v + o, vv);
-#pragma unroll
-        for (int q = 0; q < S::VW; ++q) {
-            if (ln.act[q])
-                pp[q] = ln.fresh[q] ? rr[q] : rr[q] + ln.beta[q] * (pp[q] - ln.omega[q] * vv[q]);
-        }
-        put<T, S::VW>(p + o, pp);
-    }
-    __device__ void finish(const T *) const {}
-};
-
 // v = Ah p with sigma = (r^, v); the last workgroup forms alpha.
 template <typename T, int M>
 struct OpSpmv1 {
@@ -460,9 +424,10 @@ template <typename T, int M>
 struct OpSpmv2 {
     static constexpr const char *kName = "spmv_omega";
     using S = Shape<T, M>;
-    static constexpr int NDOT = 3;
+    static constexpr int NDOT = 4;
     const T *r;
     const T *v;
+    const T *rh;
     T *t;
     Ctl *ctl;
     Kry<T> *kry;
@@ -497,8 +462,9 @@ struct OpSpmv2 {
                                         Acc<T, S::VW, NDOT> &acc) const
     {
         const size_t o = static_cast<size_t>(i) * M + g * S::VW;
-        T s[S::VW];
+        T s[S::VW], h[S::VW];
         gather(ln, i, g, s);
+        Vec<T, S::VW>::load(rh + o, h);
         put<T, S::VW>(t + o, sum);
 #pragma unroll
         for (int q = 0; q < S::VW; ++q) {
@@ -506,6 +472,7 @@ struct OpSpmv2 {
                 acc.a[0][q] += sum[q] * s[q];
                 acc.a[1][q] += sum[q] * sum[q];
                 acc.a[2][q] += s[q] * s[q];
+                acc.a[3][q] += h[q] * sum[q];
             }
         }
     }
@@ -515,7 +482,7 @@ struct OpSpmv2 {
         if (c >= M || ctl->status[c] != COL_RUN)
             return;
         Ctl &k = *ctl;
-        const T ts = tot[c], tt = tot[M + c], ss = tot[2 * M + c];
+        const T ts = tot[c], tt = tot[M + c], ss = tot[2 * M + c], ht = tot[3 * M + c];
         const double nb = (k.mode == MODE_INNER) ? static_cast<double>(kry->nbi[c]) : k.nb[c];
         const double tol = (k.mode == MODE_INNER) ? k.tol_in : k.tol[c];
         int32_t f = 0;
@@ -523,10 +490,13 @@ struct OpSpmv2 {
             f = F_SCONV;
         } else {
             const T w = ts / tt;
-            if (bad(w))
+            if (bad(w)) {
                 f = F_OMEGA_BAD;
-            else
+            } else {
                 kry->omega[c] = w;
+                // rho_next = -omega (r^, t), so beta = (rho_next/rho)(alpha/omega)
+                kry->beta[c] = ((-w * ht) / kry->rho[c]) * (kry->alpha[c] / w);
+            }
         }
         k.flag[c] = f;
     }
@@ -541,7 +511,7 @@ struct OpXR {
     static constexpr int NDOT = 2;
     T *y;
     T *r;
-    const T *p;
+    T *p;
     const T *v;
     const T *t;
     const T *rh;
@@ -551,7 +521,7 @@ struct OpXR {
         bool on;
         bool act[S::VW];
         bool use_w[S::VW];
-        T alpha[S::VW], omega[S::VW];
+        T alpha[S::VW], omega[S::VW], beta[S::VW];
     };
     __device__ Lane lane(int g) const
     {
@@ -565,6 +535,7 @@ struct OpXR {
             ln.use_w[q] = ctl->flag[c] == 0;
             ln.alpha[q] = kry->alpha[c];
             ln.omega[q] = ln.use_w[q] ? kry->omega[c] : T(0);
+            ln.beta[q] = kry->beta[c];
         }
         return ln;
     }
@@ -585,6 +556,7 @@ struct OpXR {
                 if (ln.use_w[q]) {
                     yy[q] = yy[q] + (ln.alpha[q] * pp[q] + ln.omega[q] * s);
                     rr[q] = s - ln.omega[q] * tt[q];
+                    pp[q] = rr[q] + ln.beta[q] * (pp[q] - ln.omega[q] * vv[q]);
                 } else {
                     yy[q] = yy[q] + ln.alpha[q] * pp[q];
                     rr[q] = s;
@@ -595,6 +567,7 @@ struct OpXR {
         }
         put<T, S::VW>(y + o, yy);
         put<T, S::VW>(r + o, rr);
+        put<T, S::VW>(p + o, pp);
     }
     __device__ void finish(const T *tot) const
     {
@@ -649,6 +622,7 @@ struct OpRestart {
     const T *rt;
     T *r;
     T *rh;
+    T *p;
     const Ctl *ctl;
     struct Lane {
         bool on;
@@ -669,18 +643,21 @@ struct OpRestart {
     __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, Acc<T, S::VW, NDOT> &) const
     {
         const size_t o = static_cast<size_t>(i) * M + g * S::VW;
-        T a[S::VW], b[S::VW], h[S::VW];
+        T a[S::VW], b[S::VW], h[S::VW], pp[S::VW];
         Vec<T, S::VW>::load(rt + o, a);
         Vec<T, S::VW>::load(r + o, b);
         Vec<T, S::VW>::load(rh + o, h);
+        Vec<T, S::VW>::load(p + o, pp);
 #pragma unroll
         for (int q = 0; q < S::VW; ++q)
             if (ln.act[q]) {
                 b[q] = a[q];
                 h[q] = a[q];
+                pp[q] = a[q];
             }
         put<T, S::VW>(r + o, b);
         put<T, S::VW>(rh + o, h);
+        put<T, S::VW>(p + o, pp);
     }
     __device__ void finish(const T *) const {}
 };
@@ -802,6 +779,7 @@ struct OpCast {
     float *r;
     float *rh;
     float *y;
+    float *p;
     Ctl *ctl;
     Kry<float> *kry;
     struct Lane {
@@ -825,16 +803,18 @@ struct OpCast {
     __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, Acc<float, S::VW, NDOT> &acc) const
     {
         const size_t o = static_cast<size_t>(i) * M + g * S::VW;
-        float a[S::VW], h[S::VW], z[S::VW];
+        float a[S::VW], h[S::VW], z[S::VW], pp[S::VW];
         Vec<float, S::VW>::load(r + o, a);
         Vec<float, S::VW>::load(rh + o, h);
         Vec<float, S::VW>::load(y + o, z);
+        Vec<float, S::VW>::load(p + o, pp);
 #pragma unroll
         for (int q = 0; q < S::VW; ++q) {
             if (ln.act[q]) {
                 const float f = static_cast<float>(r64[o + q] / ln.scale[q]);
                 a[q] = f;
                 h[q] = f;
+                pp[q] = f;
                 z[q] = 0.0f;
                 acc.a[0][q] += f * f;
             }
@@ -842,6 +822,7 @@ struct OpCast {
         put<float, S::VW>(r + o, a);
         put<float, S::VW>(rh + o, h);
         put<float, S::VW>(y + o, z);
+        put<float, S::VW>(p + o, pp);
     }
     __device__ void finish(const float *tot) const
     {

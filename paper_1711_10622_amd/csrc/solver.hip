@@ -153,18 +153,16 @@ struct Steps {
         MRHS_TRY((launch_stream<double, M>(
             c.n, OpScale<M>{c.X, c.A->diag, c.A->dinv, c.ctl, x0 ? SC_IN : SC_ZERO, cmask}, c.rb64, c.s)));
         return launch_gspmv<double, M>(view<double>(*c.A, true),
-                                       OpResid<M>{c.X, c.B, c.r, c.rh, c.ctl, c.kry64, RES_SETUP, 0u}, c.rb64,
-                                       c.s);
+                                       OpResid<M>{c.X, c.B, c.r, c.rh, c.p, c.ctl, c.kry64, RES_SETUP, 0u},
+                                       c.rb64, c.s);
     }
     static hipError_t f64_iterate(Ctx &c, int k)
     {
         const CsrView<double> Ah = view<double>(*c.A, true);
         for (int it = 0; it < k; ++it) {
-            MRHS_TRY((launch_stream<double, M>(c.n, OpPUpdate<double, M>{c.p, c.r, c.v, c.ctl, c.kry64},
-                                                c.rb64, c.s)));
             MRHS_TRY((launch_gspmv<double, M>(Ah, OpSpmv1<double, M>{c.p, c.v, c.rh, c.ctl, c.kry64},
                                                c.rb64, c.s)));
-            MRHS_TRY((launch_gspmv<double, M>(Ah, OpSpmv2<double, M>{c.r, c.v, c.t, c.ctl, c.kry64},
+            MRHS_TRY((launch_gspmv<double, M>(Ah, OpSpmv2<double, M>{c.r, c.v, c.rh, c.t, c.ctl, c.kry64},
                                                c.rb64, c.s)));
             MRHS_TRY((launch_stream<double, M>(
                 c.n, OpXR<double, M>{c.X, c.r, c.p, c.v, c.t, c.rh, c.ctl, c.kry64}, c.rb64, c.s)));
@@ -174,9 +172,9 @@ struct Steps {
     static hipError_t f64_check(Ctx &c)
     {
         MRHS_TRY((launch_gspmv<double, M>(view<double>(*c.A, true),
-                                           OpResid<M>{c.X, c.B, c.t, nullptr, c.ctl, c.kry64, RES_CHECK, 0u},
+                                           OpResid<M>{c.X, c.B, c.t, nullptr, nullptr, c.ctl, c.kry64, RES_CHECK, 0u},
                                            c.rb64, c.s)));
-        return launch_stream<double, M>(c.n, OpRestart<double, M>{c.t, c.r, c.rh, c.ctl}, c.rb64, c.s);
+        return launch_stream<double, M>(c.n, OpRestart<double, M>{c.t, c.r, c.rh, c.p, c.ctl}, c.rb64, c.s);
     }
     static hipError_t finish(Ctx &c, uint32_t cmask, bool mixed, bool nullspace)
     {
@@ -188,7 +186,7 @@ struct Steps {
                 c.n, OpScale<M>{c.X, c.A->diag, c.A->dinv, c.ctl, SC_SUB_MEAN, cmask}, c.rb64, c.s)));
         }
         return launch_gspmv<double, M>(view<double>(*c.A, false),
-                                       OpResid<M>{c.X, c.B, nullptr, nullptr, c.ctl, c.kry64, RES_FINAL, cmask},
+                                       OpResid<M>{c.X, c.B, nullptr, nullptr, nullptr, c.ctl, c.kry64, RES_FINAL, cmask},
                                        c.rb64, c.s);
     }
     static hipError_t mixed_start(Ctx &c, uint32_t cmask, bool x0)
@@ -197,7 +195,7 @@ struct Steps {
             MRHS_TRY((launch_stream<double, M>(
                 c.n, OpScale<M>{c.X, c.A->diag, c.A->dinv, c.ctl, SC_ZERO, cmask}, c.rb64, c.s)));
         return launch_gspmv<double, M>(view<double>(*c.A, false),
-                                       OpResid<M>{c.X, c.B, c.r64, nullptr, c.ctl, c.kry64, RES_SETUP, 0u},
+                                       OpResid<M>{c.X, c.B, c.r64, nullptr, nullptr, c.ctl, c.kry64, RES_SETUP, 0u},
                                        c.rb64, c.s);
     }
     // one refinement step for every column whose inner solve ended
@@ -215,24 +213,22 @@ struct Steps {
     static hipError_t mixed_check(Ctx &c)
     {
         return launch_gspmv<double, M>(view<double>(*c.A, false),
-                                       OpResid<M>{c.X, c.B, c.r64, nullptr, c.ctl, c.kry64, RES_MIXCHECK, 0u},
+                                       OpResid<M>{c.X, c.B, c.r64, nullptr, nullptr, c.ctl, c.kry64, RES_MIXCHECK, 0u},
                                        c.rb64, c.s);
     }
     static hipError_t mixed_cast(Ctx &c)
     {
-        return launch_stream<float, M>(c.n, OpCast<M>{c.r64, c.r32, c.rh32, c.y32, c.ctl, c.kry32}, c.rb32,
+        return launch_stream<float, M>(c.n, OpCast<M>{c.r64, c.r32, c.rh32, c.y32, c.p32, c.ctl, c.kry32}, c.rb32,
                                        c.s);
     }
     static hipError_t inner_iterate(Ctx &c, int k)
     {
         const CsrView<float> Ah = view<float>(*c.A, true);
         for (int it = 0; it < k; ++it) {
-            MRHS_TRY((launch_stream<float, M>(
-                c.n, OpPUpdate<float, M>{c.p32, c.r32, c.v32, c.ctl, c.kry32}, c.rb32, c.s)));
             MRHS_TRY((launch_gspmv<float, M>(
                 Ah, OpSpmv1<float, M>{c.p32, c.v32, c.rh32, c.ctl, c.kry32}, c.rb32, c.s)));
             MRHS_TRY((launch_gspmv<float, M>(
-                Ah, OpSpmv2<float, M>{c.r32, c.v32, c.t32, c.ctl, c.kry32}, c.rb32, c.s)));
+                Ah, OpSpmv2<float, M>{c.r32, c.v32, c.rh32, c.t32, c.ctl, c.kry32}, c.rb32, c.s)));
             MRHS_TRY((launch_stream<float, M>(
                 c.n, OpXR<float, M>{c.y32, c.r32, c.p32, c.v32, c.t32, c.rh32, c.ctl, c.kry32}, c.rb32,
                 c.s)));
