@@ -214,16 +214,20 @@ mrhs_status solve_server_stats(mrhs_server S, mrhs_server_stats *out);
 mrhs_status solve_server_destroy(mrhs_server S);
 
 /*
- * Kernel timing.  mrhs_trace_enable(1) clears the statistics and starts
- * bracketing every kernel launch of the library with a pair of HIP events on
- * the launch's own stream; mrhs_trace_enable(0) stops.  mrhs_trace_read
- * waits for the recorded events and writes a NUL-terminated JSON object
- * {"<kernel>/<f64|f32>/m<M>/g<grid>": {"launches", "total_ms", "min_ms",
- * "max_ms"}, ...} into buf (cap bytes); *len receives the length needed
- * (without the NUL).  EINVAL if the text did not fit (it is truncated).
- * Not for use while other threads launch library kernels.
+ * Kernel timing.  mrhs_trace_enable(k), k >= 1, clears the statistics and
+ * starts bracketing every k-th launch of each kernel class (counted per
+ * class, starting with the first) with a pair of HIP events on the launch's
+ * own stream; k = 1 times every launch.  Each event pair adds a few
+ * microseconds of idle time on the stream, which sampling keeps small.
+ * mrhs_trace_enable(0) stops; k < 0 is EINVAL.  mrhs_trace_read waits for the
+ * recorded events and writes a NUL-terminated JSON object
+ * {"<kernel>/<f64|f32>/m<M>/g<grid>": {"seen", "launches", "total_ms",
+ * "min_ms", "max_ms"}, ...} into buf (cap bytes), where "seen" counts all
+ * launches of the class and "launches" the timed ones; *len receives the
+ * length needed (without the NUL).  EINVAL if the text did not fit (it is
+ * truncated).  Not for use while other threads launch library kernels.
  */
-mrhs_status mrhs_trace_enable(int on);
+mrhs_status mrhs_trace_enable(int every);
 mrhs_status mrhs_trace_read(char *buf, size_t cap, size_t *len);
 
 #ifdef __cplusplus

@@ -158,9 +158,10 @@ def block_bicgstab(A: CsrMatrix, B, tol=1e-10, maxit=20000, mixed=False, **kw):
     return A.solve(B, tol=tol, maxit=maxit, mixed=mixed, **kw)
 
 
-def trace_enable(on: bool = True):
-    """Start (clearing old statistics) or stop per-launch kernel timing."""
-    _lib.check(_lib.load().mrhs_trace_enable(1 if on else 0), "mrhs_trace_enable")
+def trace_enable(on=True, every: int = 1):
+    """Start (clearing old statistics) or stop kernel timing; when on, every
+    ``every``-th launch of each kernel class is timed with HIP events."""
+    _lib.check(_lib.load().mrhs_trace_enable(int(every) if on else 0), "mrhs_trace_enable")
 
 
 def trace_read() -> dict:

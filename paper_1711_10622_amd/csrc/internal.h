@@ -83,21 +83,23 @@ __global__ void __launch_bounds__(kBlock) k_stream(int32_t n, Op op, RedBufs<T> 
 }
 
 // ---- optional per-launch timing (mrhs_trace_enable) ---------------------
-// When enabled, every kernel launch is bracketed by a pair of HIP events on
-// its own stream; mrhs_trace_read aggregates the durations per kernel class.
-extern bool g_trace_on;
-int trace_begin(hipStream_t s);
-void trace_end(int slot, hipStream_t s, const char *name, int elem_bytes, int m, int grid);
+// When enabled with period k, every k-th launch of each kernel class is
+// bracketed by a pair of HIP events on its own stream; mrhs_trace_read
+// aggregates the durations per class.  trace_begin returns -1 for launches
+// that are not sampled.
+extern int g_trace_every;
+int trace_begin(hipStream_t s, const char *name, int elem_bytes, int m, int grid);
+void trace_end(int slot, hipStream_t s);
 
 template <typename T, int M, class Op>
 inline hipError_t launch_gspmv(const CsrView<T> &A, const Op &op, const RedBufs<T> &rb, hipStream_t s)
 {
     const void *fn = reinterpret_cast<const void *>(&k_gspmv<T, M, Op>);
     const int grid = grid_for(fn, A.n);
-    const int slot = g_trace_on ? trace_begin(s) : -1;
+    const int slot = g_trace_every ? trace_begin(s, Op::kName, static_cast<int>(sizeof(T)), M, grid) : -1;
     hipLaunchKernelGGL((k_gspmv<T, M, Op>), dim3(grid), dim3(kBlock), 0, s, A, op, rb);
     if (slot >= 0)
-        trace_end(slot, s, Op::kName, static_cast<int>(sizeof(T)), M, grid);
+        trace_end(slot, s);
     return hipGetLastError();
 }
 
@@ -106,10 +108,10 @@ inline hipError_t launch_stream(int32_t n, const Op &op, const RedBufs<T> &rb, h
 {
     const void *fn = reinterpret_cast<const void *>(&k_stream<T, M, Op>);
     const int grid = grid_for(fn, n);
-    const int slot = g_trace_on ? trace_begin(s) : -1;
+    const int slot = g_trace_every ? trace_begin(s, Op::kName, static_cast<int>(sizeof(T)), M, grid) : -1;
     hipLaunchKernelGGL((k_stream<T, M, Op>), dim3(grid), dim3(kBlock), 0, s, n, op, rb);
     if (slot >= 0)
-        trace_end(slot, s, Op::kName, static_cast<int>(sizeof(T)), M, grid);
+        trace_end(slot, s);
     return hipGetLastError();
 }
 

@@ -86,7 +86,7 @@ int grid_for(const void *kernel, int64_t n)
 }
 
 // ---- launch tracing ---------------------------------------------------------
-bool g_trace_on = false;
+int g_trace_every = 0;
 
 namespace {
 
@@ -97,7 +97,8 @@ struct TraceRec {
 };
 
 struct TraceStat {
-    int64_t launches = 0;
+    int64_t seen = 0;      // launches of the class since tracing started
+    int64_t launches = 0;  // launches timed (every g_trace_every-th)
     double total_ms = 0.0, min_ms = 1e300, max_ms = 0.0;
 };
 
@@ -140,9 +141,15 @@ void trace_drain_locked()
 
 } // namespace
 
-int trace_begin(hipStream_t s)
+int trace_begin(hipStream_t s, const char *name, int elem_bytes, int m, int grid)
 {
     std::lock_guard<std::mutex> lk(g_trace_mu);
+    char key[128];
+    std::snprintf(key, sizeof(key), "%s/%s/m%d/g%d", name, elem_bytes == 8 ? "f64" : "f32", m, grid);
+    TraceStat &st = trace_stat(key);
+    const int64_t seen = st.seen++;
+    if (g_trace_every <= 0 || seen % g_trace_every != 0)
+        return -1;
     TraceRec r;
     if (!g_trace_pool.empty()) {
         r.a = g_trace_pool.back().first;
@@ -152,6 +159,7 @@ int trace_begin(hipStream_t s)
         return -1;
     }
     r.open = true;
+    r.key = key;
     (void)hipEventRecord(r.a, s);
     const int slot = g_trace_next;
     g_trace_next = (g_trace_next + 1) & 0x3fffffff;
@@ -159,7 +167,7 @@ int trace_begin(hipStream_t s)
     return slot;
 }
 
-void trace_end(int slot, hipStream_t s, const char *name, int elem_bytes, int m, int grid)
+void trace_end(int slot, hipStream_t s)
 {
     std::lock_guard<std::mutex> lk(g_trace_mu);
     auto it = g_trace_recs.find(slot);
@@ -167,9 +175,6 @@ void trace_end(int slot, hipStream_t s, const char *name, int elem_bytes, int m,
         return;
     TraceRec &r = it->second;
     (void)hipEventRecord(r.b, s);
-    char key[128];
-    std::snprintf(key, sizeof(key), "%s/%s/m%d/g%d", name, elem_bytes == 8 ? "f64" : "f32", m, grid);
-    r.key = key;
     r.open = false;
     if (g_trace_recs.size() >= 4096)
         trace_drain_locked();
@@ -472,14 +477,16 @@ MRHS_API mrhs_status block_bicgstab(mrhs_csr A, const double *B, double *X, int3
     return block_bicgstab_ex(A, B, X, m, tol, maxit, 0u, nullptr, 0, nullptr, nullptr);
 }
 
-MRHS_API mrhs_status mrhs_trace_enable(int on)
+MRHS_API mrhs_status mrhs_trace_enable(int every)
 {
     clear_error();
+    if (every < 0)
+        return set_error(MRHS_EINVAL, "trace period must be >= 0, got %d", every);
     std::lock_guard<std::mutex> lk(g_trace_mu);
     trace_drain_locked();
-    if (on)
+    if (every)
         g_trace_stats.clear();
-    g_trace_on = on != 0;
+    g_trace_every = every;
     return MRHS_OK;
 }
 
@@ -492,9 +499,12 @@ MRHS_API mrhs_status mrhs_trace_read(char *buf, size_t cap, size_t *len)
     bool first = true;
     for (const auto &kv : g_trace_stats) {
         char item[320];
-        std::snprintf(item, sizeof(item), "%s\"%s\": {\"launches\": %lld, \"total_ms\": %.6f, \"min_ms\": %.6f, \"max_ms\": %.6f}",
-                      first ? "" : ", ", kv.first.c_str(), static_cast<long long>(kv.second.launches),
-                      kv.second.total_ms, kv.second.min_ms, kv.second.max_ms);
+        std::snprintf(item, sizeof(item),
+                      "%s\"%s\": {\"seen\": %lld, \"launches\": %lld, \"total_ms\": %.6f, \"min_ms\": %.6f, "
+                      "\"max_ms\": %.6f}",
+                      first ? "" : ", ", kv.first.c_str(), static_cast<long long>(kv.second.seen),
+                      static_cast<long long>(kv.second.launches), kv.second.total_ms, kv.second.min_ms,
+                      kv.second.max_ms);
         out += item;
         first = false;
     }

@@ -156,6 +156,26 @@ def test_argument_errors(torch_cuda, mrhs):
     E.close()
 
 
+def test_sampled_trace(torch_cuda, mrhs):
+    """mrhs_trace_enable(k) times launches 0, k, 2k, ... of each kernel class."""
+    A = grids.dirichlet7(6)
+    M = mrhs.CsrMatrix.from_csr(A)
+    X = torch_cuda.ones((A.n, 4), dtype=torch_cuda.float64, device="cuda")
+    Y = torch_cuda.empty_like(X)
+    mrhs.trace_enable(True, every=3)
+    for _ in range(7):
+        M.gspmv(X, out=Y)
+    M.gspmv(X[:, :2].contiguous())
+    tr = mrhs.trace_read()
+    mrhs.trace_enable(False)
+    M.close()
+    keys = sorted(tr)
+    assert len(keys) == 2 and keys[0].startswith("gspmv/f64/m2/") and keys[1].startswith("gspmv/f64/m4/")
+    assert tr[keys[1]]["seen"] == 7 and tr[keys[1]]["launches"] == 3
+    assert tr[keys[0]]["seen"] == 1 and tr[keys[0]]["launches"] == 1
+    assert 0 < tr[keys[1]]["min_ms"] <= tr[keys[1]]["max_ms"] < 1e3
+
+
 @pytest.mark.parametrize("m", [1, 8, 16])
 def test_full_size_channel_f64(torch_cuda, mrhs, m):
     """The 128x64x64 stretched channel at full size, every row checked."""
