@@ -8,6 +8,13 @@
 // streams one contiguous stretch of rows and its L2 holds the neighbours'
 // block rows that the gather needs.
 //
+// Products over matrices with a long, regular forward reach (a grid operator
+// in natural order, whose farthest neighbour is a plane of P tiles away) use
+// a plane-interleaved schedule instead: the rows are seen as planes of P
+// tiles, group x owns the x-th eighth of every plane and walks the planes in
+// order, so the rows a tile gathers from the planes before and after it were
+// fetched into the same XCD's L2 by the tiles just before and just after it.
+//
 // Lane layout for an n x M row-interleaved block.  Each lane handles VW
 // consecutive columns of one row (VW elements = one 8- or 16-byte access), a
 // row takes G = M/VW lanes padded to L = next power of two, and a wave holds
@@ -44,8 +51,7 @@ namespace mrhs {
 #endif
 
 constexpr int kBlock = 256;
-constexpr int kTileRows = MRHS_TILE_ROWS;
-constexpr int kNzCap = MRHS_TILE_ROWS * MRHS_NZ_PER_ROW;  // staged nonzeros per tile
+constexpr int kTileRows = MRHS_TILE_ROWS;  // rows per tile (at least one pass)
 constexpr int kGroups = 8;
 constexpr int kMaxM = 16;
 constexpr int kMaxDots = 8;  // largest NDOT of any reduction (GCR projections)
@@ -69,9 +75,11 @@ struct Shape {
     static constexpr int G = M / VW;       // lanes that hold data in a row
     static constexpr int L = next_pow2(G); // lanes per row
     static constexpr int RPP = kBlock / L; // rows per pass of the workgroup
-    static constexpr int PASSES = kTileRows / RPP;
+    static constexpr int TR = RPP > kTileRows ? RPP : kTileRows;  // rows per tile
+    static constexpr int NZCAP = TR * MRHS_NZ_PER_ROW;            // staged nonzeros per tile
+    static constexpr int PASSES = TR / RPP;
     static_assert(G * VW == M, "lane width must divide M");
-    static_assert(PASSES >= 1 && PASSES * RPP == kTileRows, "a tile must hold whole passes");
+    static_assert(PASSES >= 1 && PASSES * RPP == TR, "a tile must hold whole passes");
     static_assert(L <= 64, "a row must fit one wave");
 };
 
@@ -82,6 +90,7 @@ struct Vec;
 template <typename T>
 struct Vec<T, 1> {
     static __device__ __forceinline__ void load(const T *p, T *v) { v[0] = *p; }
+    static __device__ __forceinline__ void load_nt(const T *p, T *v) { v[0] = __builtin_nontemporal_load(p); }
     static __device__ __forceinline__ void store(T *p, const T *v) { *p = v[0]; }
     static __device__ __forceinline__ void store_nt(T *p, const T *v) { __builtin_nontemporal_store(v[0], p); }
 };
@@ -92,6 +101,12 @@ struct Vec<double, 2> {
     static __device__ __forceinline__ void load(const double *p, double *v)
     {
         v2 t = *reinterpret_cast<const v2 *>(p);
+        v[0] = t.x;
+        v[1] = t.y;
+    }
+    static __device__ __forceinline__ void load_nt(const double *p, double *v)
+    {
+        v2 t = __builtin_nontemporal_load(reinterpret_cast<const v2 *>(p));
         v[0] = t.x;
         v[1] = t.y;
     }
@@ -117,6 +132,12 @@ struct Vec<float, 2> {
     static __device__ __forceinline__ void load(const float *p, float *v)
     {
         v2 t = *reinterpret_cast<const v2 *>(p);
+        v[0] = t.x;
+        v[1] = t.y;
+    }
+    static __device__ __forceinline__ void load_nt(const float *p, float *v)
+    {
+        v2 t = __builtin_nontemporal_load(reinterpret_cast<const v2 *>(p));
         v[0] = t.x;
         v[1] = t.y;
     }
@@ -147,6 +168,14 @@ struct Vec<float, 4> {
         v[2] = t.z;
         v[3] = t.w;
     }
+    static __device__ __forceinline__ void load_nt(const float *p, float *v)
+    {
+        v4 t = __builtin_nontemporal_load(reinterpret_cast<const v4 *>(p));
+        v[0] = t.x;
+        v[1] = t.y;
+        v[2] = t.z;
+        v[3] = t.w;
+    }
     static __device__ __forceinline__ void store(float *p, const float *v)
     {
         v4 t;
@@ -167,19 +196,11 @@ struct Vec<float, 4> {
     }
 };
 
-// Address of element (row, col0) of an n x M row-interleaved block.  With
-// MRHS_OFF32 the byte offset is formed in 32 bits (blocks under 4 GiB), which
-// lets the compiler address with a scalar base and one offset register.
+// Address of element (row, col0) of an n x M row-interleaved block.
 template <typename T, int M>
 __device__ __forceinline__ const T *blk(const T *base, int32_t row, int col0)
 {
-#ifdef MRHS_OFF32
-    const uint32_t off = static_cast<uint32_t>(row) * static_cast<uint32_t>(M * sizeof(T)) +
-                         static_cast<uint32_t>(col0 * sizeof(T));
-    return reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + off);
-#else
     return base + static_cast<size_t>(row) * M + col0;
-#endif
 }
 
 template <typename T, int M>
@@ -195,6 +216,11 @@ struct Vec<double, 4> {
     {
         Vec<double, 2>::load(p, v);
         Vec<double, 2>::load(p + 2, v + 2);
+    }
+    static __device__ __forceinline__ void load_nt(const double *p, double *v)
+    {
+        Vec<double, 2>::load_nt(p, v);
+        Vec<double, 2>::load_nt(p + 2, v + 2);
     }
     static __device__ __forceinline__ void store(double *p, const double *v)
     {
@@ -215,6 +241,11 @@ struct Vec<float, 8> {
         Vec<float, 4>::load(p, v);
         Vec<float, 4>::load(p + 4, v + 4);
     }
+    static __device__ __forceinline__ void load_nt(const float *p, float *v)
+    {
+        Vec<float, 4>::load_nt(p, v);
+        Vec<float, 4>::load_nt(p + 4, v + 4);
+    }
     static __device__ __forceinline__ void store(float *p, const float *v)
     {
         Vec<float, 4>::store(p, v);
@@ -228,22 +259,45 @@ struct Vec<float, 8> {
 };
 
 // ---- tile schedule ------------------------------------------------------------
+// Steps s = first, first + stride, ... < end of this workgroup; step s is
+// tile s (contiguous mode, P = 0) or, in plane mode, tile
+// (s / cg) * P + lo + s % cg, which may fall past the last tile in the
+// final, partial plane (then it is skipped).
 struct TileRange {
-    int64_t first, end, stride;
+    int32_t first, end, stride;
+    int32_t P, lo, cg;
+    __device__ __forceinline__ int32_t tile(int32_t s) const { return P ? (s / cg) * P + lo + s % cg : s; }
 };
 
-__device__ __forceinline__ TileRange tile_range(int64_t ntiles)
+__device__ __forceinline__ TileRange tile_range(int32_t ntiles, int32_t P = 0)
 {
 #if !MRHS_XCD_GROUPS
-    return {blockIdx.x, ntiles, gridDim.x};
+    return {static_cast<int32_t>(blockIdx.x), ntiles, static_cast<int32_t>(gridDim.x), 0, 0, 1};
 #endif
     const int b = blockIdx.x;
     const int grp = b % kGroups;
     const int q = b / kGroups;
     const int gx = gridDim.x / kGroups;
-    const int64_t lo = ntiles * grp / kGroups;
-    const int64_t hi = ntiles * (grp + 1) / kGroups;
-    return {lo + q, hi, gx};
+    if (P) {
+        const int32_t lo = P * grp / kGroups;
+        const int32_t cg = P * (grp + 1) / kGroups - lo;
+        const int32_t planes = (ntiles + P - 1) / P;
+        return {q, planes * cg, gx, P, lo, cg};
+    }
+    const int32_t lo = static_cast<int32_t>(static_cast<int64_t>(ntiles) * grp / kGroups);
+    const int32_t hi = static_cast<int32_t>(static_cast<int64_t>(ntiles) * (grp + 1) / kGroups);
+    return {lo + q, hi, gx, 0, 0, 1};
+}
+
+// Tiles per plane for the plane-interleaved schedule of a product, or 0 for
+// the contiguous one: the matrix's typical forward reach (median over rows of
+// the largest column - row offset) rounded to whole tiles, used when every
+// group gets at least two tiles of each plane and there are at least four
+// planes.
+__device__ __forceinline__ int32_t plane_tiles(int32_t reach, int32_t tile_rows, int32_t ntiles)
+{
+    const int32_t P = (reach + tile_rows / 2) / tile_rows;
+    return (P >= 2 * kGroups && ntiles >= 4 * P) ? P : 0;
 }
 
 // ---- matrix view ----------------------------------------------------------------
@@ -253,6 +307,7 @@ struct CsrView {
     const int32_t *__restrict__ ci;
     const T *__restrict__ va;
     int32_t n;
+    int32_t reach;  // median over rows of the largest forward column offset
 };
 
 // One row of the product: sum over the row's entries in storage order of
@@ -273,11 +328,7 @@ __device__ __forceinline__ void row_product(PI cis, PV vas, int j0, int j1, int 
         for (int k = 0; k < NB; ++k) {
             ok[k] = j + k < j1;
             const int jj = ok[k] ? j + k : j1 - 1;
-#ifdef MRHS_DIAG_LOCAL
-            c[k] = cis[j0 + (j1 - j0) / 2];
-#else
             c[k] = cis[jj];
-#endif
             a[k] = vas[jj];
         }
 #pragma unroll
@@ -310,25 +361,28 @@ struct Acc {
 // tile's row offsets, column indices and values are first staged in LDS with
 // coalesced streaming loads (one pass over HBM, no reuse in cache needed), then
 // every lane walks its rows out of LDS and gathers block rows of X through the
-// cache hierarchy.  A tile whose nonzeros exceed kNzCap reads them directly.
+// cache hierarchy.  A tile whose nonzeros exceed S::NZCAP reads them directly.
 template <typename T, int M, class Op>
 __device__ __forceinline__ void gspmv_tiles(const CsrView<T> &A, const Op &op,
                                             Acc<T, Shape<T, M>::VW, Op::NDOT> &acc)
 {
     using S = Shape<T, M>;
-    __shared__ int32_t s_rp[kTileRows + 1];
-    __shared__ __align__(16) int32_t s_ci[kNzCap + 4];
-    __shared__ __align__(16) T s_va[kNzCap + 4];
+    __shared__ int32_t s_rp[S::TR + 1];
+    __shared__ __align__(16) int32_t s_ci[S::NZCAP + 4];
+    __shared__ __align__(16) T s_va[S::NZCAP + 4];
     const int tid = threadIdx.x;
     const int g = tid % S::L;
     const int rl = tid / S::L;
     const typename Op::Lane ln = op.lane(g < S::G ? g : 0);
     const bool lane_on = g < S::G && ln.on;
-    const int64_t ntiles = (static_cast<int64_t>(A.n) + kTileRows - 1) / kTileRows;
-    const TileRange tr = tile_range(ntiles);
-    for (int64_t tile = tr.first; tile < tr.end; tile += tr.stride) {
-        const int32_t r0 = static_cast<int32_t>(tile * kTileRows);
-        const int nr = min(kTileRows, A.n - r0);
+    const int32_t ntiles = static_cast<int32_t>((static_cast<int64_t>(A.n) + S::TR - 1) / S::TR);
+    const TileRange tr = tile_range(ntiles, plane_tiles(A.reach, S::TR, ntiles));
+    for (int32_t step = tr.first; step < tr.end; step += tr.stride) {
+        const int32_t tile = tr.tile(step);
+        if (tile >= ntiles)  // past the end of the last, partial plane
+            continue;
+        const int32_t r0 = tile * S::TR;
+        const int nr = min(S::TR, A.n - r0);
         for (int k = tid; k <= nr; k += kBlock)
             s_rp[k] = A.rp[r0 + k];
         __syncthreads();
@@ -339,13 +393,13 @@ __device__ __forceinline__ void gspmv_tiles(const CsrView<T> &A, const Op &op,
         // thread issues all of its loads before writing any of them to LDS
         const int32_t zb = z0 & ~3;
         const int lead = z0 - zb;
-        const bool staged = cnt + lead <= kNzCap;
+        const bool staged = cnt + lead <= S::NZCAP;
         if (staged) {
             using I4 = int __attribute__((ext_vector_type(4)));
             constexpr int VV = 16 / static_cast<int>(sizeof(T));
             using TV = T __attribute__((ext_vector_type(VV)));
-            constexpr int CI_PT = ((kNzCap + 4) / 4 + kBlock - 1) / kBlock;
-            constexpr int VA_PT = ((kNzCap + 4) / VV + kBlock - 1) / kBlock;
+            constexpr int CI_PT = ((S::NZCAP + 4) / 4 + kBlock - 1) / kBlock;
+            constexpr int VA_PT = ((S::NZCAP + 4) / VV + kBlock - 1) / kBlock;
             const int nci = (cnt + lead + 3) / 4;
             const int nva = (cnt + lead + VV - 1) / VV;
             const I4 *gci = reinterpret_cast<const I4 *>(A.ci + zb);
@@ -380,62 +434,6 @@ __device__ __forceinline__ void gspmv_tiles(const CsrView<T> &A, const Op &op,
         __syncthreads();
         const int32_t *lci = s_ci + lead;
         const T *lva = s_va + lead;
-#ifdef MRHS_PIPE2
-        if (staged) {  // uniform over the workgroup: one barrier on every path
-          if (lane_on) {
-            // two passes in flight: the gathers of pass p+1 are issued before
-            // pass p is consumed; rows longer than NB finish in row_product
-            constexpr int NB = MRHS_GATHER_BATCH;
-            int32_t cc[2][NB];
-            T aa[2][NB], xx[2][NB][S::VW];
-            int jj0[2], jj1[2];
-            auto issue = [&](int slot, int p) {
-                const int row_l = p * S::RPP + rl;
-                const bool live = row_l < nr;
-                const int j0 = live ? s_rp[row_l] - z0 : 0;
-                const int j1 = live ? s_rp[row_l + 1] - z0 : 0;
-                jj0[slot] = j0;
-                jj1[slot] = j1;
-#pragma unroll
-                for (int k = 0; k < NB; ++k) {
-                    const bool ok = j0 + k < j1;
-                    const int j = ok ? j0 + k : (j1 > j0 ? j1 - 1 : -1);
-                    cc[slot][k] = j >= 0 ? lci[j] : -1;
-                    aa[slot][k] = (ok && j >= 0) ? lva[j] : T(0);
-                }
-#pragma unroll
-                for (int k = 0; k < NB; ++k)
-                    if (cc[slot][k] >= 0)
-                        op.gather(ln, cc[slot][k], g, xx[slot][k]);
-            };
-            issue(0, 0);
-#pragma unroll
-            for (int p = 0; p < S::PASSES; ++p) {
-                const int cur = p & 1;
-                if (p + 1 < S::PASSES)
-                    issue(cur ^ 1, p + 1);
-                const int row_l = p * S::RPP + rl;
-                if (row_l < nr) {
-                    T sum[S::VW];
-#pragma unroll
-                    for (int v = 0; v < S::VW; ++v)
-                        sum[v] = T(0);
-#pragma unroll
-                    for (int k = 0; k < NB; ++k)
-#pragma unroll
-                        for (int v = 0; v < S::VW; ++v)
-                            if (jj0[cur] + k < jj1[cur])
-                                sum[v] += aa[cur][k] * xx[cur][k][v];
-                    if (jj1[cur] - jj0[cur] > NB)
-                        row_product<T, S::VW>(lci, lva, jj0[cur] + NB, jj1[cur], g, op, ln, sum);
-                    op.row(ln, r0 + row_l, g, sum, acc);
-                }
-            }
-          }
-          __syncthreads();
-          continue;
-        }
-#endif
 #pragma unroll 1
         for (int p = 0; p < S::PASSES; ++p) {
             const int row_l = p * S::RPP + rl;
@@ -471,11 +469,11 @@ __device__ __forceinline__ void stream_tiles(int32_t n, const Op &op,
     const typename Op::Lane ln = op.lane(g);
     if (!ln.on)
         return;
-    const int64_t ntiles = (static_cast<int64_t>(n) + kTileRows - 1) / kTileRows;
+    const int32_t ntiles = static_cast<int32_t>((static_cast<int64_t>(n) + S::TR - 1) / S::TR);
     const TileRange tr = tile_range(ntiles);
-    for (int64_t tile = tr.first; tile < tr.end; tile += tr.stride) {
-        const int32_t r0 = static_cast<int32_t>(tile * kTileRows);
-        const int nr = min(kTileRows, n - r0);
+    for (int32_t tile = tr.first; tile < tr.end; tile += tr.stride) {
+        const int32_t r0 = tile * S::TR;
+        const int nr = min(S::TR, n - r0);
 #pragma unroll 2
         for (int p = 0; p < S::PASSES; ++p) {
             const int row_l = p * S::RPP + rl;

@@ -25,6 +25,7 @@ struct mrhs_csr_s {
     float *valh32 = nullptr;  // [nnz] RN32(A D^-1)
     double *diag = nullptr;   // [n]
     double *dinv = nullptr;   // [n]
+    int32_t reach = 0;        // median over rows of max(col - row), >= 0
     size_t bytes = 0;
 };
 
@@ -44,7 +45,7 @@ void clear_error();
 // Number of workgroups for a tile-looping kernel over n rows: enough to keep
 // every CU at its occupancy limit, never more than there are tiles, rounded
 // up to a multiple of kGroups.
-int grid_for(const void *kernel, int64_t n);
+int grid_for(const void *kernel, int64_t n, int tile_rows);
 int max_grid();  // upper bound of grid_for over all kernels (for buffer sizing)
 
 template <typename T>
@@ -53,13 +54,13 @@ inline CsrView<T> view(const mrhs_csr_s &A, bool scaled);
 template <>
 inline CsrView<double> view<double>(const mrhs_csr_s &A, bool scaled)
 {
-    return {A.rp, A.ci, scaled ? A.valh : A.val, A.n};
+    return {A.rp, A.ci, scaled ? A.valh : A.val, A.n, A.reach};
 }
 
 template <>
 inline CsrView<float> view<float>(const mrhs_csr_s &A, bool scaled)
 {
-    return {A.rp, A.ci, scaled ? A.valh32 : A.val32, A.n};
+    return {A.rp, A.ci, scaled ? A.valh32 : A.val32, A.n, A.reach};
 }
 
 template <typename T, int M, class Op>
@@ -95,7 +96,7 @@ template <typename T, int M, class Op>
 inline hipError_t launch_gspmv(const CsrView<T> &A, const Op &op, const RedBufs<T> &rb, hipStream_t s)
 {
     const void *fn = reinterpret_cast<const void *>(&k_gspmv<T, M, Op>);
-    const int grid = grid_for(fn, A.n);
+    const int grid = grid_for(fn, A.n, Shape<T, M>::TR);
     const int slot = g_trace_every ? trace_begin(s, Op::kName, static_cast<int>(sizeof(T)), M, grid) : -1;
     hipLaunchKernelGGL((k_gspmv<T, M, Op>), dim3(grid), dim3(kBlock), 0, s, A, op, rb);
     if (slot >= 0)
@@ -107,7 +108,7 @@ template <typename T, int M, class Op>
 inline hipError_t launch_stream(int32_t n, const Op &op, const RedBufs<T> &rb, hipStream_t s)
 {
     const void *fn = reinterpret_cast<const void *>(&k_stream<T, M, Op>);
-    const int grid = grid_for(fn, n);
+    const int grid = grid_for(fn, n, Shape<T, M>::TR);
     const int slot = g_trace_every ? trace_begin(s, Op::kName, static_cast<int>(sizeof(T)), M, grid) : -1;
     hipLaunchKernelGGL((k_stream<T, M, Op>), dim3(grid), dim3(kBlock), 0, s, n, op, rb);
     if (slot >= 0)

@@ -1,4 +1,5 @@
 // C ABI of libmrhs: matrix handles, the generalized SpMV and the block solve.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -58,7 +59,7 @@ int max_grid()
     return (g + kGroups - 1) / kGroups * kGroups;
 }
 
-int grid_for(const void *kernel, int64_t n)
+int grid_for(const void *kernel, int64_t n, int tile_rows)
 {
     int per_cu = 1, cus = 0;
     {
@@ -74,12 +75,8 @@ int grid_for(const void *kernel, int64_t n)
         }
         per_cu = it->second;
     }
-    const int64_t ntiles = (n + kTileRows - 1) / kTileRows;
-#ifdef MRHS_GRID_ALL_TILES  // tuning experiments of the reduction-free product only
-    int64_t g = ntiles;
-#else
+    const int64_t ntiles = (n + tile_rows - 1) / tile_rows;
     int64_t g = std::min<int64_t>(ntiles, static_cast<int64_t>(per_cu) * cus);
-#endif
     g = std::max<int64_t>(g, 1);
     g = (g + kGroups - 1) / kGroups * kGroups;
     return static_cast<int>(g);
@@ -275,6 +272,7 @@ MRHS_API mrhs_status csr_create(int32_t n, int64_t nnz, const int32_t *row_ptr, 
     if (nnz > 0 && (!col_idx || !val))
         return set_error(MRHS_EINVAL, "col_idx or val is NULL");
     std::vector<double> diag(static_cast<size_t>(n), 0.0);
+    std::vector<int32_t> reach(static_cast<size_t>(n), 0);
     if (n > 0) {
         if (row_ptr[0] != 0)
             return set_error(MRHS_EINVAL, "row_ptr[0] = %d, must be 0", row_ptr[0]);
@@ -292,6 +290,7 @@ MRHS_API mrhs_status csr_create(int32_t n, int64_t nnz, const int32_t *row_ptr, 
                     return set_error(MRHS_EINVAL, "val[%d] is not finite", j);
                 if (c == i)
                     diag[i] += val[j];
+                reach[i] = std::max(reach[i], c - i);
             }
         }
         if (row_ptr[n] != nnz)
@@ -311,6 +310,10 @@ MRHS_API mrhs_status csr_create(int32_t n, int64_t nnz, const int32_t *row_ptr, 
     for (int32_t i = 0; i < n; ++i)
         if (diag[i] == 0.0)
             A->zero_diag = true;
+    if (n > 0) {  // the tile schedule of the products uses the median reach
+        std::nth_element(reach.begin(), reach.begin() + n / 2, reach.end());
+        A->reach = reach[n / 2];
+    }
     if (n == 0) {
         *out = A;
         return MRHS_OK;

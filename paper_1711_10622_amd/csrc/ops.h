@@ -120,6 +120,23 @@ __device__ __forceinline__ void put(T *p, const T *v)
 #endif
 }
 
+#ifndef MRHS_NT_LOAD
+#define MRHS_NT_LOAD 0
+#endif
+
+// Row-aligned block operands that are read once (not gathered through the
+// matrix) are loaded with streaming loads, so they do not displace gathered
+// rows from L2.
+template <typename T, int VW>
+__device__ __forceinline__ void get(const T *p, T *v)
+{
+#if MRHS_NT_LOAD
+    Vec<T, VW>::load_nt(p, v);
+#else
+    Vec<T, VW>::load(p, v);
+#endif
+}
+
 template <typename T>
 __device__ __forceinline__ bool bad(T v)
 {
@@ -148,12 +165,7 @@ struct OpStore {
     __device__ __forceinline__ void row(const Lane &, int32_t i, int g, const T *sum,
                                         Acc<T, S::VW, NDOT> &) const
     {
-#ifdef MRHS_DIAG_NOSTORE
-        if (sum[0] == T(123456.789))
-            put<T, S::VW>(blk<T, M>(Y, i, g * S::VW), sum);
-#else
         put<T, S::VW>(blk<T, M>(Y, i, g * S::VW), sum);
-#endif
     }
     __device__ void finish(const T *) const {}
 };
@@ -221,7 +233,7 @@ struct OpResid {
     {
         const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         double b[S::VW], r[S::VW];
-        Vec<double, S::VW>::load(B + o, b);
+        get<double, S::VW>(B + o, b);
 #pragma unroll
         for (int v = 0; v < S::VW; ++v) {
             r[v] = b[v] - sum[v];
@@ -395,7 +407,7 @@ struct OpSpmv1 {
     {
         const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         T h[S::VW];
-        Vec<T, S::VW>::load(rh + o, h);
+        get<T, S::VW>(rh + o, h);
         put<T, S::VW>(v + o, sum);
 #pragma unroll
         for (int q = 0; q < S::VW; ++q)
@@ -464,7 +476,7 @@ struct OpSpmv2 {
         const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         T s[S::VW], h[S::VW];
         gather(ln, i, g, s);
-        Vec<T, S::VW>::load(rh + o, h);
+        get<T, S::VW>(rh + o, h);
         put<T, S::VW>(t + o, sum);
 #pragma unroll
         for (int q = 0; q < S::VW; ++q) {
@@ -543,12 +555,12 @@ struct OpXR {
     {
         const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         T yy[S::VW], rr[S::VW], pp[S::VW], vv[S::VW], tt[S::VW], hh[S::VW];
-        Vec<T, S::VW>::load(y + o, yy);
-        Vec<T, S::VW>::load(r + o, rr);
-        Vec<T, S::VW>::load(p + o, pp);
-        Vec<T, S::VW>::load(v + o, vv);
-        Vec<T, S::VW>::load(t + o, tt);
-        Vec<T, S::VW>::load(rh + o, hh);
+        get<T, S::VW>(y + o, yy);
+        get<T, S::VW>(r + o, rr);
+        get<T, S::VW>(p + o, pp);
+        get<T, S::VW>(v + o, vv);
+        get<T, S::VW>(t + o, tt);
+        get<T, S::VW>(rh + o, hh);
 #pragma unroll
         for (int q = 0; q < S::VW; ++q) {
             if (ln.act[q]) {
@@ -644,10 +656,10 @@ struct OpRestart {
     {
         const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         T a[S::VW], b[S::VW], h[S::VW], pp[S::VW];
-        Vec<T, S::VW>::load(rt + o, a);
-        Vec<T, S::VW>::load(r + o, b);
-        Vec<T, S::VW>::load(rh + o, h);
-        Vec<T, S::VW>::load(p + o, pp);
+        get<T, S::VW>(rt + o, a);
+        get<T, S::VW>(r + o, b);
+        get<T, S::VW>(rh + o, h);
+        get<T, S::VW>(p + o, pp);
 #pragma unroll
         for (int q = 0; q < S::VW; ++q)
             if (ln.act[q]) {
@@ -707,7 +719,7 @@ struct OpScale {
     {
         const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         double a[S::VW];
-        Vec<double, S::VW>::load(x + o, a);
+        get<double, S::VW>(x + o, a);
         const double di = (kind == SC_IN) ? diag[i] : (kind == SC_OUT ? dinv[i] : 1.0);
 #pragma unroll
         for (int q = 0; q < S::VW; ++q) {
@@ -754,7 +766,7 @@ struct OpColSum {
     __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, Acc<double, S::VW, NDOT> &acc) const
     {
         double a[S::VW];
-        Vec<double, S::VW>::load(x + static_cast<size_t>(i) * M + g * S::VW, a);
+        get<double, S::VW>(x + static_cast<size_t>(i) * M + g * S::VW, a);
 #pragma unroll
         for (int q = 0; q < S::VW; ++q)
             if (ln.act[q])
@@ -804,10 +816,10 @@ struct OpCast {
     {
         const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         float a[S::VW], h[S::VW], z[S::VW], pp[S::VW];
-        Vec<float, S::VW>::load(r + o, a);
-        Vec<float, S::VW>::load(rh + o, h);
-        Vec<float, S::VW>::load(y + o, z);
-        Vec<float, S::VW>::load(p + o, pp);
+        get<float, S::VW>(r + o, a);
+        get<float, S::VW>(rh + o, h);
+        get<float, S::VW>(y + o, z);
+        get<float, S::VW>(p + o, pp);
 #pragma unroll
         for (int q = 0; q < S::VW; ++q) {
             if (ln.act[q]) {
@@ -934,13 +946,13 @@ struct OpGcrDots {
     {
         const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         double wn[S::VW];
-        Vec<double, S::VW>::load(b.wnew + o, wn);
+        get<double, S::VW>(b.wnew + o, wn);
 #pragma unroll
         for (int j = 0; j < kGcrMax; ++j) {
             if (j >= b.jmax)
                 break;
             double wj[S::VW];
-            Vec<double, S::VW>::load(b.w[j] + o, wj);
+            get<double, S::VW>(b.w[j] + o, wj);
 #pragma unroll
             for (int q = 0; q < S::VW; ++q)
                 if (ln.act[q])
@@ -995,16 +1007,16 @@ struct OpGcrOrth {
     {
         const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         double wn[S::VW], zn[S::VW], rr[S::VW];
-        Vec<double, S::VW>::load(b.wnew + o, wn);
-        Vec<double, S::VW>::load(b.znew + o, zn);
-        Vec<double, S::VW>::load(r + o, rr);
+        get<double, S::VW>(b.wnew + o, wn);
+        get<double, S::VW>(b.znew + o, zn);
+        get<double, S::VW>(r + o, rr);
 #pragma unroll
         for (int j = 0; j < kGcrMax; ++j) {
             if (j >= b.jmax)
                 break;
             double wj[S::VW], zj[S::VW];
-            Vec<double, S::VW>::load(b.w[j] + o, wj);
-            Vec<double, S::VW>::load(b.z[j] + o, zj);
+            get<double, S::VW>(b.w[j] + o, wj);
+            get<double, S::VW>(b.z[j] + o, zj);
 #pragma unroll
             for (int q = 0; q < S::VW; ++q) {
                 if (ln.act[q] && ln.beta[j][q] != 0.0) {
@@ -1075,10 +1087,10 @@ struct OpGcrUpdate {
     {
         const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         double xx[S::VW], rr[S::VW], zz[S::VW], ww[S::VW];
-        Vec<double, S::VW>::load(x + o, xx);
-        Vec<double, S::VW>::load(r + o, rr);
-        Vec<double, S::VW>::load(b.znew + o, zz);
-        Vec<double, S::VW>::load(b.wnew + o, ww);
+        get<double, S::VW>(x + o, xx);
+        get<double, S::VW>(r + o, rr);
+        get<double, S::VW>(b.znew + o, zz);
+        get<double, S::VW>(b.wnew + o, ww);
 #pragma unroll
         for (int q = 0; q < S::VW; ++q) {
             if (ln.act[q]) {
