@@ -136,7 +136,18 @@ mrhs_status gspmv_ex(mrhs_csr A, int32_t dtype, const void *X, void *Y,
  * matrix read.  Column l stops when ||b_l - A x_l|| <= tol ||b_l|| holds for
  * the recomputed true residual.  Uses the null stream and blocks until done.
  * Returns OK only if every column converged, else the worst column status.
+ *
+ * The shadow residual r^ of the binary64 iteration (any vector not orthogonal
+ * to the initial residual serves) is the same for every column and every
+ * restart: row i holds
+ * 2 u_i 2^-53 - 1 with u_i the top 53 bits of output number i (counting from
+ * 0) of the SplitMix64 generator seeded with MRHS_SHADOW_SEED, i.e. of
+ * mix(MRHS_SHADOW_SEED + (i + 1) * 0x9E3779B97F4A7C15).  It is generated
+ * where it is used and never stored.  The binary32 inner solves of MRHS_MIXED
+ * (short solves restarted at every refinement step) take r^ = their own
+ * initial residual.
  */
+#define MRHS_SHADOW_SEED 17110622ull
 mrhs_status block_bicgstab(mrhs_csr A, const double *B, double *X, int32_t m,
                            double tol, int32_t maxit);
 

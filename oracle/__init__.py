@@ -30,7 +30,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 OK, EINVAL, ENOMEM, ENOCONV, EBREAKDOWN = 0, -1, -2, -4, -5
-X0_GIVEN, NULLSPACE_CONST = 1, 2
+X0_GIVEN, NULLSPACE_CONST, SHADOW_RANDOM = 1, 2, 4
 
 _lock = threading.Lock()
 _lib = None
@@ -67,9 +67,11 @@ def _load():
                 f.argtypes = [i32, i32p, i32p, f64p, i32, f64p, f64p]
                 f.restype = None
             lib.oracle_bicgstab.argtypes = [i32, i32p, i32p, f64p, f64p, f64p, ctypes.c_double,
-                                            i32, ctypes.c_uint32, ctypes.POINTER(OracleInfo),
-                                            f64p, i32]
+                                            i32, ctypes.c_uint32, ctypes.c_uint64,
+                                            ctypes.POINTER(OracleInfo), f64p, i32]
             lib.oracle_bicgstab.restype = ctypes.c_int
+            lib.oracle_shadow.argtypes = [i32, ctypes.c_uint64, f64p]
+            lib.oracle_shadow.restype = None
             _lib = lib
     return _lib
 
@@ -145,8 +147,12 @@ def gspmv_rows(A, X, rows, dot2=False):
 
 
 def bicgstab(A, B, tol=1e-10, maxit=10000, nullspace_const=None, X0=None,
-             hist_len=0, threads=1):
+             hist_len=0, threads=1, shadow_seed=None):
     """Solve A x_l = b_l for every column l of B independently.
+
+    ``shadow_seed`` None takes the shadow residual r^ = r0 (renewed at every
+    restart); an integer takes the fixed vector of SplitMix64 values of that
+    seed mapped to [-1, 1), the same for every column.
 
     Returns ``(X, infos, hists)``: the (n, m) solution block, a list of
     per-column info dicts and, if ``hist_len`` > 0, an (m, hist_len) array of
@@ -161,6 +167,8 @@ def bicgstab(A, B, tol=1e-10, maxit=10000, nullspace_const=None, X0=None,
     if nullspace_const is None:
         nullspace_const = bool(getattr(A, "nullspace_const", False))
     flags = (NULLSPACE_CONST if nullspace_const else 0) | (X0_GIVEN if X0 is not None else 0)
+    if shadow_seed is not None:
+        flags |= SHADOW_RANDOM
     rp, ci, va = _csr(A)
     X = np.zeros((n, m)) if X0 is None else np.array(X0, dtype=np.float64).reshape(n, m)
     hists = np.full((m, max(hist_len, 1)), np.nan)
@@ -174,7 +182,7 @@ def bicgstab(A, B, tol=1e-10, maxit=10000, nullspace_const=None, X0=None,
         lib.oracle_bicgstab(n, _p(rp, ctypes.c_int32), _p(ci, ctypes.c_int32),
                             _p(va, ctypes.c_double), _p(b, ctypes.c_double),
                             _p(x, ctypes.c_double), float(tol), int(maxit), flags,
-                            ctypes.byref(infos[l]),
+                            int(shadow_seed or 0), ctypes.byref(infos[l]),
                             _p(h, ctypes.c_double) if hist_len > 0 else None, int(hist_len))
         cols_out[l] = x
         hists[l] = h
@@ -187,3 +195,10 @@ def bicgstab(A, B, tol=1e-10, maxit=10000, nullspace_const=None, X0=None,
             run(l)
     Xo = np.stack(cols_out, axis=1) if m else np.zeros((n, 0))
     return Xo, [i.as_dict() for i in infos], (hists if hist_len > 0 else None)
+
+
+def shadow(n, seed):
+    """The shadow residual vector of the random-shadow mode."""
+    out = np.empty(n, dtype=np.float64)
+    _load().oracle_shadow(int(n), int(seed), _p(out, ctypes.c_double))
+    return out

@@ -28,7 +28,10 @@
  *   - row_ptr[0] must be 0; duplicate column entries add (the Figure 1 loop
  *     sums them); an empty row gives 0.
  *   - BiCGStab: right preconditioning M = diag(A), shadow residual
- *     r^ = r0, x0 = 0 unless given, stop when ||r||_2 <= tol * ||b||_2 and
+ *     r^ = r0 (reset to the new residual at every restart) or, with
+ *     ORACLE_SHADOW_RANDOM, the fixed vector whose entry i is value number i
+ *     of the SplitMix64 stream of a given seed mapped to [-1, 1) (kept over
+ *     restarts), x0 = 0 unless given, stop when ||r||_2 <= tol * ||b||_2 and
  *     the recomputed true residual confirms it; otherwise restart from the
  *     true residual.  Breakdown = rho, sigma or omega exactly zero or not
  *     finite; it restarts from the true residual, and the fourth breakdown
@@ -54,6 +57,7 @@
 
 #define ORACLE_X0_GIVEN 1u
 #define ORACLE_NULLSPACE_CONST 2u
+#define ORACLE_SHADOW_RANDOM 4u
 
 #define ORACLE_MAX_BREAKDOWN_RESTARTS 3
 
@@ -157,10 +161,39 @@ static int bad(double v)
 }
 
 /*
+ * SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): output number k (from 0)
+ * of the generator whose state starts at seed and advances by the golden
+ * gamma 0x9E3779B97F4A7C15 before each output.
+ */
+static uint64_t splitmix64_output(uint64_t seed, uint64_t k)
+{
+    uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* rh[i] = uniform [-1, 1) from the top 53 bits of output i (exact). */
+static void random_shadow(int32_t n, uint64_t seed, double *rh)
+{
+    for (int32_t i = 0; i < n; ++i) {
+        const double u = (double)(splitmix64_output(seed, (uint64_t)i) >> 11) / 9007199254740992.0;
+        rh[i] = 2.0 * u - 1.0;
+    }
+}
+
+/* The shadow vector of ORACLE_SHADOW_RANDOM, for the test suite's pin. */
+void oracle_shadow(int32_t n, uint64_t seed, double *out)
+{
+    random_shadow(n, seed, out);
+}
+
+/*
  * Right-Jacobi-preconditioned BiCGStab for one right-hand side.
  *
  *   b      [n]   right-hand side
  *   x      [n]   out: solution; in: initial guess when ORACLE_X0_GIVEN
+ *   shadow_seed  seed of the shadow residual with ORACLE_SHADOW_RANDOM
  *   hist   [hist_len] optional (may be NULL): hist[k] = ||r_k||/||b|| at the
  *          top of the loop after k iterations (recurrence residual, or the
  *          true one right after a restart); unused slots are left alone.
@@ -169,8 +202,8 @@ static int bad(double v)
  */
 int oracle_bicgstab(int32_t n, const int32_t *rp, const int32_t *ci,
                     const double *va, const double *b, double *x, double tol,
-                    int32_t maxit, uint32_t flags, oracle_info *info,
-                    double *hist, int32_t hist_len)
+                    int32_t maxit, uint32_t flags, uint64_t shadow_seed,
+                    oracle_info *info, double *hist, int32_t hist_len)
 {
     memset(info, 0, sizeof(*info));
     if (n < 0 || tol <= 0.0 || maxit < 1) {
@@ -234,9 +267,13 @@ int oracle_bicgstab(int32_t n, const int32_t *rp, const int32_t *ci,
     int fresh = 1;
     int from_recurrence = 0;
 
-    /* (re)start: r = b - A x, r^ = r */
+    /* start: r = b - A x, r^ = r or the random shadow vector */
+    const int shadow_random = (flags & ORACLE_SHADOW_RANDOM) != 0;
     true_residual(n, rp, ci, va, b, x, r);
-    memcpy(rh, r, sizeof(double) * (size_t)n);
+    if (shadow_random)
+        random_shadow(n, shadow_seed, rh);
+    else
+        memcpy(rh, r, sizeof(double) * (size_t)n);
     rho = dot(n, rh, r);
 
     for (;;) {
@@ -321,7 +358,8 @@ int oracle_bicgstab(int32_t n, const int32_t *rp, const int32_t *ci,
         true_residual(n, rp, ci, va, b, x, r);
 
     restart:
-        memcpy(rh, r, sizeof(double) * (size_t)n);
+        if (!shadow_random)
+            memcpy(rh, r, sizeof(double) * (size_t)n);
         rho = dot(n, rh, r);
         rho_old = alpha = omega = 1.0;
         fresh = 1;

@@ -7,5 +7,5 @@ iterations built on the generalized sparse matrix-vector product Y = A X
 (Section 2.3, Figure 1).  The compute path is libmrhs.so (HIP kernels behind a
 C ABI, include/mrhs.h); this package only marshals arguments.
 """
-from ._lib import MrhsError, load  # noqa: F401
+from ._lib import SHADOW_SEED, MrhsError, load  # noqa: F401
 from .api import CsrMatrix, SolveServer, block_bicgstab, gspmv, trace_enable, trace_read  # noqa: F401

@@ -20,6 +20,7 @@ F64, F32 = 0, 1
 CSR_NULLSPACE_CONST = 1
 X0_GIVEN, MIXED = 1, 2
 SERVER_MIXED = 1
+SHADOW_SEED = 17110622  # MRHS_SHADOW_SEED: seed of the BiCGStab shadow residual
 
 # every symbol include/mrhs.h declares
 EXPORTS = (

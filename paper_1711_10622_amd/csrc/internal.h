@@ -152,10 +152,11 @@ struct Ctx {
     Kry<float> *kry32;
     RedBufs<double> rb64;
     RedBufs<float> rb32;
-    double *r, *rh, *p, *v, *t;
+    double *r, *p, *v, *t;
     double *r64;
     GcrBlocks gcr;
-    float *r32, *rh32, *p32, *v32, *t32, *y32;
+    float *r32, *p32, *v32, *t32, *y32;
+    uint8_t *sgn32;
 };
 
 struct StepTable {

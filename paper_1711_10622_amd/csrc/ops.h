@@ -37,6 +37,7 @@
 #pragma once
 
 #include "core.h"
+#include "mrhs.h"
 
 namespace mrhs {
 
@@ -145,6 +146,62 @@ __device__ __forceinline__ bool bad(T v)
 
 __device__ __forceinline__ bool pending(int32_t s) { return s == COL_PEND_CHECK || s == COL_PEND_BD; }
 
+// The shadow residual r^ of the binary64 BiCGStab: one vector shared by every
+// column, row i holding value number i of the SplitMix64 stream of seed
+// MRHS_SHADOW_SEED (Steele, Lea and Flood, OOPSLA 2014) mapped to [-1, 1).
+// It is generated where a dot product needs it, never stored, which takes one
+// block read out of each of the three passes of an iteration.  The binary32
+// inner solves of mixed precision restart at every refinement step, and over
+// such short solves a random r^ converges far worse; they take r^ = sign(r0)
+// of their own initial residual r0 (entries +-1, +1 for a zero), stored as
+// one bit per element: lane g of a row keeps the bits of its VW columns in
+// byte i * L + g of the sign array.
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t k)
+{
+    uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+template <typename T>
+__device__ __forceinline__ T shadow(int32_t i);
+
+template <>
+__device__ __forceinline__ double shadow<double>(int32_t i)
+{
+    // top 53 bits scaled to [0, 2) then shifted: exact in binary64
+    return static_cast<double>(splitmix64_at(MRHS_SHADOW_SEED, static_cast<uint64_t>(i)) >> 11) * 0x1p-52 - 1.0;
+}
+
+template <>
+__device__ __forceinline__ float shadow<float>(int32_t i)
+{
+    // top 24 bits: exact in binary32
+    const uint32_t u = static_cast<uint32_t>(splitmix64_at(MRHS_SHADOW_SEED, static_cast<uint64_t>(i)) >> 40);
+    return static_cast<float>(u) * 0x1p-23f - 1.0f;
+}
+
+// The shadow values of this lane's VW columns of row i: from the sign bits,
+// or the generated vector when sgn is null.
+template <typename T, int M>
+__device__ __forceinline__ void shadow_row(const uint8_t *sgn, int32_t i, int g, T *h)
+{
+    using S = Shape<T, M>;
+    static_assert(S::L <= kMaxM && S::VW <= 8, "a lane's sign bits fit one byte of a row's kMaxM");
+    if (sgn) {
+        const uint32_t b = sgn[static_cast<size_t>(i) * S::L + g];
+#pragma unroll
+        for (int q = 0; q < S::VW; ++q)
+            h[q] = ((b >> q) & 1u) ? T(-1) : T(1);
+    } else {
+        const T s = shadow<T>(i);
+#pragma unroll
+        for (int q = 0; q < S::VW; ++q)
+            h[q] = s;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Plain product Y = A X.
 template <typename T, int M>
@@ -186,7 +243,7 @@ struct OpResid {
     static constexpr const char *kName = "resid";
     using T = double;
     using S = Shape<double, M>;
-    static constexpr int NDOT = 2;
+    static constexpr int NDOT = 3;
     const double *X;
     const double *B;
     double *R;
@@ -234,12 +291,15 @@ struct OpResid {
         const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         double b[S::VW], r[S::VW];
         get<double, S::VW>(B + o, b);
+        const bool restart = kind == RES_SETUP || kind == RES_CHECK;
+        const double h = restart ? shadow<double>(i) : 0.0;
 #pragma unroll
         for (int v = 0; v < S::VW; ++v) {
             r[v] = b[v] - sum[v];
             if (ln.act[v]) {
                 acc.a[0][v] += r[v] * r[v];
                 acc.a[1][v] += b[v] * b[v];
+                acc.a[2][v] += h * r[v];
             }
         }
         bool all = true;
@@ -275,6 +335,7 @@ struct OpResid {
             return;
         const double rr = tot[c];
         const double bb = tot[M + c];
+        const double hr = tot[2 * M + c];  // (r^, r) of the setup / restart residual
         Ctl &k = *ctl;
         switch (kind) {
         case RES_SETUP: {
@@ -282,7 +343,7 @@ struct OpResid {
             k.nb[c] = nb;
             k.fresh[c] = 1;
             k.flag[c] = 0;
-            kry->rho[c] = rr;
+            kry->rho[c] = hr;
             kry->rho_old[c] = kry->alpha[c] = kry->omega[c] = 1.0;
             if (!isfinite(nb)) {
                 k.status[c] = COL_BREAKDOWN;
@@ -300,6 +361,8 @@ struct OpResid {
                     k.status[c] = COL_DONE;
                 else if (bad(rr))
                     k.status[c] = mixed ? COL_BREAKDOWN : COL_PEND_BD;
+                else if (!mixed && bad(hr))
+                    k.status[c] = COL_PEND_BD;
                 else if (k.iters[c] >= k.maxit[c])
                     k.status[c] = COL_NOCONV;
                 else
@@ -328,8 +391,8 @@ struct OpResid {
             }
             if (st == COL_PEND_CHECK)
                 k.restarts[c] += 1;
-            // restart from the true residual: r = r^ = b - A x
-            kry->rho[c] = rr;
+            // restart from the true residual: r = p = b - A x
+            kry->rho[c] = hr;
             kry->rho_old[c] = kry->alpha[c] = kry->omega[c] = 1.0;
             k.fresh[c] = 1;
             k.flag[c] = F_RESTART;
@@ -393,7 +456,7 @@ struct OpSpmv1 {
     static constexpr int NDOT = 1;
     const T *p;
     T *v;
-    const T *rh;
+    const uint8_t *sgn;  // sign bits of the shadow residual, or null: generated
     Ctl *ctl;
     Kry<T> *kry;
     using Lane = RunLane<T, M>;
@@ -407,7 +470,7 @@ struct OpSpmv1 {
     {
         const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         T h[S::VW];
-        get<T, S::VW>(rh + o, h);
+        shadow_row<T, M>(sgn, i, g, h);
         put<T, S::VW>(v + o, sum);
 #pragma unroll
         for (int q = 0; q < S::VW; ++q)
@@ -439,7 +502,7 @@ struct OpSpmv2 {
     static constexpr int NDOT = 4;
     const T *r;
     const T *v;
-    const T *rh;
+    const uint8_t *sgn;  // sign bits of the shadow residual, or null: generated
     T *t;
     Ctl *ctl;
     Kry<T> *kry;
@@ -476,7 +539,7 @@ struct OpSpmv2 {
         const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         T s[S::VW], h[S::VW];
         gather(ln, i, g, s);
-        get<T, S::VW>(rh + o, h);
+        shadow_row<T, M>(sgn, i, g, h);
         put<T, S::VW>(t + o, sum);
 #pragma unroll
         for (int q = 0; q < S::VW; ++q) {
@@ -526,7 +589,7 @@ struct OpXR {
     T *p;
     const T *v;
     const T *t;
-    const T *rh;
+    const uint8_t *sgn;  // sign bits of the shadow residual, or null: generated
     Ctl *ctl;
     Kry<T> *kry;
     struct Lane {
@@ -554,13 +617,14 @@ struct OpXR {
     __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, Acc<T, S::VW, NDOT> &acc) const
     {
         const size_t o = static_cast<size_t>(i) * M + g * S::VW;
-        T yy[S::VW], rr[S::VW], pp[S::VW], vv[S::VW], tt[S::VW], hh[S::VW];
+        T yy[S::VW], rr[S::VW], pp[S::VW], vv[S::VW], tt[S::VW];
         get<T, S::VW>(y + o, yy);
         get<T, S::VW>(r + o, rr);
         get<T, S::VW>(p + o, pp);
         get<T, S::VW>(v + o, vv);
         get<T, S::VW>(t + o, tt);
-        get<T, S::VW>(rh + o, hh);
+        T hh[S::VW];
+        shadow_row<T, M>(sgn, i, g, hh);
 #pragma unroll
         for (int q = 0; q < S::VW; ++q) {
             if (ln.act[q]) {
@@ -633,7 +697,6 @@ struct OpRestart {
     static constexpr int NDOT = 0;
     const T *rt;
     T *r;
-    T *rh;
     T *p;
     const Ctl *ctl;
     struct Lane {
@@ -655,20 +718,17 @@ struct OpRestart {
     __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, Acc<T, S::VW, NDOT> &) const
     {
         const size_t o = static_cast<size_t>(i) * M + g * S::VW;
-        T a[S::VW], b[S::VW], h[S::VW], pp[S::VW];
+        T a[S::VW], b[S::VW], pp[S::VW];
         get<T, S::VW>(rt + o, a);
         get<T, S::VW>(r + o, b);
-        get<T, S::VW>(rh + o, h);
         get<T, S::VW>(p + o, pp);
 #pragma unroll
         for (int q = 0; q < S::VW; ++q)
             if (ln.act[q]) {
                 b[q] = a[q];
-                h[q] = a[q];
                 pp[q] = a[q];
             }
         put<T, S::VW>(r + o, b);
-        put<T, S::VW>(rh + o, h);
         put<T, S::VW>(p + o, pp);
     }
     __device__ void finish(const T *) const {}
@@ -781,15 +841,17 @@ struct OpColSum {
 };
 
 // Mixed precision: start an inner solve for each COL_RUN column:
-// r32 = r^32 = RN32(r64 / ||r64||), y32 = 0; sums (r32, r32) in binary32.
+// r32 = p32 = RN32(r64 / ||r64||), r^ = sign(r32) (bits), y32 = 0; sums
+// (r32, r32) = (r^, r32)... in binary32: (r32, r32) for the norm and
+// (r^, r32) = ||r32||_1 for rho.
 template <int M>
 struct OpCast {
     static constexpr const char *kName = "cast32";
     using S = Shape<float, M>;
-    static constexpr int NDOT = 1;
+    static constexpr int NDOT = 2;
     const double *r64;
     float *r;
-    float *rh;
+    uint8_t *sgn;
     float *y;
     float *p;
     Ctl *ctl;
@@ -815,26 +877,28 @@ struct OpCast {
     __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, Acc<float, S::VW, NDOT> &acc) const
     {
         const size_t o = static_cast<size_t>(i) * M + g * S::VW;
-        float a[S::VW], h[S::VW], z[S::VW], pp[S::VW];
+        float a[S::VW], z[S::VW], pp[S::VW];
         get<float, S::VW>(r + o, a);
-        get<float, S::VW>(rh + o, h);
         get<float, S::VW>(y + o, z);
         get<float, S::VW>(p + o, pp);
+        uint8_t *sb = sgn + static_cast<size_t>(i) * S::L + g;
+        uint32_t bits = *sb;
 #pragma unroll
         for (int q = 0; q < S::VW; ++q) {
             if (ln.act[q]) {
                 const float f = static_cast<float>(r64[o + q] / ln.scale[q]);
                 a[q] = f;
-                h[q] = f;
                 pp[q] = f;
                 z[q] = 0.0f;
                 acc.a[0][q] += f * f;
+                acc.a[1][q] += fabsf(f);
+                bits = (f < 0.0f) ? (bits | (1u << q)) : (bits & ~(1u << q));
             }
         }
         put<float, S::VW>(r + o, a);
-        put<float, S::VW>(rh + o, h);
         put<float, S::VW>(y + o, z);
         put<float, S::VW>(p + o, pp);
+        *sb = static_cast<uint8_t>(bits);
     }
     __device__ void finish(const float *tot) const
     {
@@ -845,7 +909,7 @@ struct OpCast {
         k.status[c] = COL_RUN;
         k.inner_maxit[c] = k.maxit[c] - k.total_iters[c];
         const float rr = tot[c];
-        kry->rho[c] = rr;
+        kry->rho[c] = tot[M + c];  // (r^, r32) = ||r32||_1
         kry->nbi[c] = sqrtf(rr);
         kry->rho_old[c] = kry->alpha[c] = kry->omega[c] = 1.0f;
         k.fresh[c] = 1;

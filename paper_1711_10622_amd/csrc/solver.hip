@@ -39,12 +39,13 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
     size_t ctl, kry64, kry32, tickets, part, gpart;
-    size_t v64[5];      // r, r^, p, v, t                  (binary64 solve)
+    size_t v64[4];      // r, p, v, t                      (binary64 solve)
     size_t r64;         // refinement residual             (mixed)
     size_t z[kGcrMax];  // stored directions z_j           (mixed)
     size_t w[kGcrMax];  // and w_j = A z_j                 (mixed)
     size_t znew, wnew;  // the direction being formed      (mixed)
-    size_t v32[6];      // r, r^, p, v, t, y               (mixed, binary32)
+    size_t v32[5];      // r, p, v, t, y                   (mixed, binary32)
+    size_t sgn32;       // sign bits of the inner shadow residual (mixed)
     size_t total;
 };
 
@@ -74,10 +75,11 @@ Layout layout(int32_t n, int32_t m, uint32_t flags)
         }
         L.znew = take(blk64);
         L.wnew = take(blk64);
-        for (int i = 0; i < 6; ++i)
-            L.v32[i] = take(blk32);
-    } else {
         for (int i = 0; i < 5; ++i)
+            L.v32[i] = take(blk32);
+        L.sgn32 = take(static_cast<size_t>(n) * kMaxM);  // n x (lanes per row <= 16) bytes
+    } else {
+        for (int i = 0; i < 4; ++i)
             L.v64[i] = take(blk64);
     }
     L.total = off;
@@ -153,19 +155,19 @@ struct Steps {
         MRHS_TRY((launch_stream<double, M>(
             c.n, OpScale<M>{c.X, c.A->diag, c.A->dinv, c.ctl, x0 ? SC_IN : SC_ZERO, cmask}, c.rb64, c.s)));
         return launch_gspmv<double, M>(view<double>(*c.A, true),
-                                       OpResid<M>{c.X, c.B, c.r, c.rh, c.p, c.ctl, c.kry64, RES_SETUP, 0u},
+                                       OpResid<M>{c.X, c.B, c.r, c.p, nullptr, c.ctl, c.kry64, RES_SETUP, 0u},
                                        c.rb64, c.s);
     }
     static hipError_t f64_iterate(Ctx &c, int k)
     {
         const CsrView<double> Ah = view<double>(*c.A, true);
         for (int it = 0; it < k; ++it) {
-            MRHS_TRY((launch_gspmv<double, M>(Ah, OpSpmv1<double, M>{c.p, c.v, c.rh, c.ctl, c.kry64},
+            MRHS_TRY((launch_gspmv<double, M>(Ah, OpSpmv1<double, M>{c.p, c.v, nullptr, c.ctl, c.kry64},
                                                c.rb64, c.s)));
-            MRHS_TRY((launch_gspmv<double, M>(Ah, OpSpmv2<double, M>{c.r, c.v, c.rh, c.t, c.ctl, c.kry64},
+            MRHS_TRY((launch_gspmv<double, M>(Ah, OpSpmv2<double, M>{c.r, c.v, nullptr, c.t, c.ctl, c.kry64},
                                                c.rb64, c.s)));
             MRHS_TRY((launch_stream<double, M>(
-                c.n, OpXR<double, M>{c.X, c.r, c.p, c.v, c.t, c.rh, c.ctl, c.kry64}, c.rb64, c.s)));
+                c.n, OpXR<double, M>{c.X, c.r, c.p, c.v, c.t, nullptr, c.ctl, c.kry64}, c.rb64, c.s)));
         }
         return hipSuccess;
     }
@@ -174,7 +176,7 @@ struct Steps {
         MRHS_TRY((launch_gspmv<double, M>(view<double>(*c.A, true),
                                            OpResid<M>{c.X, c.B, c.t, nullptr, nullptr, c.ctl, c.kry64, RES_CHECK, 0u},
                                            c.rb64, c.s)));
-        return launch_stream<double, M>(c.n, OpRestart<double, M>{c.t, c.r, c.rh, c.p, c.ctl}, c.rb64, c.s);
+        return launch_stream<double, M>(c.n, OpRestart<double, M>{c.t, c.r, c.p, c.ctl}, c.rb64, c.s);
     }
     static hipError_t finish(Ctx &c, uint32_t cmask, bool mixed, bool nullspace)
     {
@@ -218,7 +220,7 @@ struct Steps {
     }
     static hipError_t mixed_cast(Ctx &c)
     {
-        return launch_stream<float, M>(c.n, OpCast<M>{c.r64, c.r32, c.rh32, c.y32, c.p32, c.ctl, c.kry32}, c.rb32,
+        return launch_stream<float, M>(c.n, OpCast<M>{c.r64, c.r32, c.sgn32, c.y32, c.p32, c.ctl, c.kry32}, c.rb32,
                                        c.s);
     }
     static hipError_t inner_iterate(Ctx &c, int k)
@@ -226,11 +228,11 @@ struct Steps {
         const CsrView<float> Ah = view<float>(*c.A, true);
         for (int it = 0; it < k; ++it) {
             MRHS_TRY((launch_gspmv<float, M>(
-                Ah, OpSpmv1<float, M>{c.p32, c.v32, c.rh32, c.ctl, c.kry32}, c.rb32, c.s)));
+                Ah, OpSpmv1<float, M>{c.p32, c.v32, c.sgn32, c.ctl, c.kry32}, c.rb32, c.s)));
             MRHS_TRY((launch_gspmv<float, M>(
-                Ah, OpSpmv2<float, M>{c.r32, c.v32, c.rh32, c.t32, c.ctl, c.kry32}, c.rb32, c.s)));
+                Ah, OpSpmv2<float, M>{c.r32, c.v32, c.sgn32, c.t32, c.ctl, c.kry32}, c.rb32, c.s)));
             MRHS_TRY((launch_stream<float, M>(
-                c.n, OpXR<float, M>{c.y32, c.r32, c.p32, c.v32, c.t32, c.rh32, c.ctl, c.kry32}, c.rb32,
+                c.n, OpXR<float, M>{c.y32, c.r32, c.p32, c.v32, c.t32, c.sgn32, c.ctl, c.kry32}, c.rb32,
                 c.s)));
         }
         return hipSuccess;
@@ -305,12 +307,13 @@ Engine::Engine(const mrhs_csr_s &A, int m, uint32_t flags, void *ws, const doubl
         c_.gcr.wnew = reinterpret_cast<double *>(base + L.wnew);
         c_.gcr.ndirs = ndirs_;
         c_.gcr.jmax = 0;
-        float **v32[6] = {&c_.r32, &c_.rh32, &c_.p32, &c_.v32, &c_.t32, &c_.y32};
-        for (int i = 0; i < 6; ++i)
-            *v32[i] = reinterpret_cast<float *>(base + L.v32[i]);
-    } else {
-        double **v64[5] = {&c_.r, &c_.rh, &c_.p, &c_.v, &c_.t};
+        float **v32[5] = {&c_.r32, &c_.p32, &c_.v32, &c_.t32, &c_.y32};
         for (int i = 0; i < 5; ++i)
+            *v32[i] = reinterpret_cast<float *>(base + L.v32[i]);
+        c_.sgn32 = reinterpret_cast<uint8_t *>(base + L.sgn32);
+    } else {
+        double **v64[4] = {&c_.r, &c_.p, &c_.v, &c_.t};
+        for (int i = 0; i < 4; ++i)
             *v64[i] = reinterpret_cast<double *>(base + L.v64[i]);
     }
     chunk_ = env_int("MRHS_POLL_ITERS", 16, 1, 1024);

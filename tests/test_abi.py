@@ -68,3 +68,9 @@ def test_invalid_arguments_without_device():
     assert lib.block_bicgstab_workspace_size(None, 4, 0, ctypes.byref(b)) == _lib.EINVAL
     assert lib.mrhs_trace_enable(-1) == _lib.EINVAL
     assert lib.mrhs_trace_enable(0) == _lib.OK
+
+
+def test_shadow_seed_matches_header():
+    text = open(os.path.join(ROOT, "include", "mrhs.h")).read()
+    mo = re.search(r"#define MRHS_SHADOW_SEED (\d+)ull", text)
+    assert mo and int(mo.group(1)) == _lib.SHADOW_SEED

