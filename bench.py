@@ -61,13 +61,20 @@ def kernel_bytes(name, n, nnz, m, S):
     the matrix (int32 row offsets and columns, S-byte values) read once."""
     mat = 4 * (n + 1) + (4 + S) * nnz
     blk = S * m * n
+    # the binary64 shadow residual is generated in the kernels; binary32
+    # inner solves read its sign bits, one byte per lane of a row
+    sgn = 0 if S == 8 else n * next_pow2(m // (4 if m % 4 == 0 else 2 if m % 2 == 0 else 1))
     table = {
-        "gspmv": mat + 2 * blk,        # read X, write Y
-        "spmv_sigma": mat + 3 * blk,   # read p (gathered), r^; write v
-        "spmv_omega": mat + 4 * blk,   # read r, v (gathered), r^; write t
-        "xr_update": 9 * blk,          # read y, r, p, v, t, r^; write y, r, p
+        "gspmv": mat + 2 * blk,             # read X, write Y
+        "spmv_sigma": mat + 2 * blk + sgn,  # read p (gathered); write v
+        "spmv_omega": mat + 3 * blk + sgn,  # read r, v (gathered); write t
+        "xr_update": 8 * blk + sgn,         # read y, r, p, v, t; write y, r, p
     }
     return table.get(name)
+
+
+def next_pow2(x):
+    return 1 if x <= 1 else 2 * next_pow2((x + 1) // 2)
 
 
 def kernel_sources_digest():

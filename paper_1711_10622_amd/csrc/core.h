@@ -44,7 +44,7 @@ namespace mrhs {
 #define MRHS_NZ_PER_ROW 8
 #endif
 #ifndef MRHS_GATHER_BATCH
-#define MRHS_GATHER_BATCH 8
+#define MRHS_GATHER_BATCH 7  // one batch covers a 7-point stencil row
 #endif
 #ifndef MRHS_XCD_GROUPS
 #define MRHS_XCD_GROUPS 1
