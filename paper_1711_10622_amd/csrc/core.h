@@ -16,10 +16,12 @@
 // fetched into the same XCD's L2 by the tiles just before and just after it.
 //
 // Lane layout for an n x M row-interleaved block.  Each lane handles VW
-// consecutive columns of one row (VW elements = one 8- or 16-byte access), a
-// row takes G = M/VW lanes padded to L = next power of two, and a wave holds
-// 64/L rows.  A wave-wide access of a block therefore covers 64/L whole rows,
-// i.e. contiguous memory.
+// consecutive columns of one row (VW elements = one 16-byte access when M is
+// wide enough), a row takes G = ceil(M/VW) lanes padded to L = next power of
+// two, and a wave holds 64/L rows.  A wave-wide access of a block therefore
+// covers 64/L whole rows, i.e. contiguous memory.  When VW does not divide M
+// the row's last lane holds the remaining TAIL columns and accesses them
+// element by element, and the other lanes' vectors are only element-aligned.
 //
 // Reductions (per-column dot products) are deterministic: lanes of one column
 // are combined by a fixed xor butterfly inside the wave, waves in fixed order
@@ -58,27 +60,20 @@ constexpr int kMaxDots = 8;  // largest NDOT of any reduction (GCR projections)
 
 constexpr int next_pow2(int x) { return x <= 1 ? 1 : 2 * next_pow2((x + 1) / 2); }
 
-#ifndef MRHS_WIDE
-#define MRHS_WIDE 0
-#endif
-
 template <typename T, int M>
 struct Shape {
-#if MRHS_WIDE
-    static constexpr int VW = std::is_same<T, double>::value
-                                  ? (M % 4 == 0 ? 4 : (M % 2 == 0 ? 2 : 1))
-                                  : (M % 8 == 0 ? 8 : (M % 4 == 0 ? 4 : (M % 2 == 0 ? 2 : 1)));
-#else
+    // columns per lane: the widest 8- or 16-byte access that divides the row
+    // (a row-end lane holding fewer columns, with element-aligned 16-byte
+    // accesses for the others, measured 20 % slower for odd M in binary64)
     static constexpr int VW = std::is_same<T, double>::value ? (M % 2 == 0 ? 2 : 1)
                                                              : (M % 4 == 0 ? 4 : (M % 2 == 0 ? 2 : 1));
-#endif
-    static constexpr int G = M / VW;       // lanes that hold data in a row
-    static constexpr int L = next_pow2(G); // lanes per row
-    static constexpr int RPP = kBlock / L; // rows per pass of the workgroup
+    static constexpr int G = (M + VW - 1) / VW;  // lanes that hold data in a row
+    static constexpr int TAIL = M - (G - 1) * VW; // columns of the row's last lane (1..VW)
+    static constexpr int L = next_pow2(G);        // lanes per row
+    static constexpr int RPP = kBlock / L;        // rows per pass of the workgroup
     static constexpr int TR = RPP > kTileRows ? RPP : kTileRows;  // rows per tile
     static constexpr int NZCAP = TR * MRHS_NZ_PER_ROW;            // staged nonzeros per tile
     static constexpr int PASSES = TR / RPP;
-    static_assert(G * VW == M, "lane width must divide M");
     static_assert(PASSES >= 1 && PASSES * RPP == TR, "a tile must hold whole passes");
     static_assert(L <= 64, "a row must fit one wave");
 };
@@ -196,6 +191,82 @@ struct Vec<float, 4> {
     }
 };
 
+// Vectors of VW elements at element (not vector) alignment: the rows of a
+// block whose width VW does not divide start at any element.
+template <typename T, int VW>
+struct VecU {
+    typedef T vu __attribute__((ext_vector_type(VW), aligned(sizeof(T))));
+    static __device__ __forceinline__ void load(const T *p, T *v)
+    {
+        const vu t = *reinterpret_cast<const vu *>(p);
+#pragma unroll
+        for (int q = 0; q < VW; ++q)
+            v[q] = t[q];
+    }
+    static __device__ __forceinline__ void store_nt(T *p, const T *v)
+    {
+        vu t;
+#pragma unroll
+        for (int q = 0; q < VW; ++q)
+            t[q] = v[q];
+        __builtin_nontemporal_store(t, reinterpret_cast<vu *>(p));
+    }
+    static __device__ __forceinline__ void store(T *p, const T *v)
+    {
+        vu t;
+#pragma unroll
+        for (int q = 0; q < VW; ++q)
+            t[q] = v[q];
+        *reinterpret_cast<vu *>(p) = t;
+    }
+};
+
+#ifndef MRHS_NT_STORE
+#define MRHS_NT_STORE 1
+#endif
+
+// Lane g's VW elements of row `row` of an n x M block.  The last lane of a row
+// whose width VW does not divide reads its TAIL elements one by one (the rest
+// of v is zero), so no access leaves the row.
+template <typename T, int M>
+__device__ __forceinline__ void ld(const T *base, int32_t row, int g, T *v)
+{
+    using S = Shape<T, M>;
+    const T *p = base + static_cast<size_t>(row) * M + g * S::VW;
+    if constexpr (S::TAIL == S::VW) {
+        Vec<T, S::VW>::load(p, v);
+    } else if (g == S::G - 1) {
+#pragma unroll
+        for (int q = 0; q < S::VW; ++q)
+            v[q] = q < S::TAIL ? p[q] : T(0);
+    } else {
+        VecU<T, S::VW>::load(p, v);
+    }
+}
+
+// Stores lane g's elements of a row; block outputs use streaming
+// (nontemporal) stores: every block is far larger than the caches, and
+// keeping written lines out of L2 leaves it to the gathered block rows.
+template <typename T, int M>
+__device__ __forceinline__ void st(T *base, int32_t row, int g, const T *v)
+{
+    using S = Shape<T, M>;
+    T *p = base + static_cast<size_t>(row) * M + g * S::VW;
+    if constexpr (S::TAIL == S::VW) {
+#if MRHS_NT_STORE
+        Vec<T, S::VW>::store_nt(p, v);
+#else
+        Vec<T, S::VW>::store(p, v);
+#endif
+    } else if (g == S::G - 1) {
+#pragma unroll
+        for (int q = 0; q < S::TAIL; ++q)
+            __builtin_nontemporal_store(v[q], p + q);
+    } else {
+        VecU<T, S::VW>::store_nt(p, v);
+    }
+}
+
 // Address of element (row, col0) of an n x M row-interleaved block.
 template <typename T, int M>
 __device__ __forceinline__ const T *blk(const T *base, int32_t row, int col0)
@@ -210,53 +281,6 @@ __device__ __forceinline__ T *blk(T *base, int32_t row, int col0)
 }
 
 // 32-byte lanes: two 16-byte accesses
-template <>
-struct Vec<double, 4> {
-    static __device__ __forceinline__ void load(const double *p, double *v)
-    {
-        Vec<double, 2>::load(p, v);
-        Vec<double, 2>::load(p + 2, v + 2);
-    }
-    static __device__ __forceinline__ void load_nt(const double *p, double *v)
-    {
-        Vec<double, 2>::load_nt(p, v);
-        Vec<double, 2>::load_nt(p + 2, v + 2);
-    }
-    static __device__ __forceinline__ void store(double *p, const double *v)
-    {
-        Vec<double, 2>::store(p, v);
-        Vec<double, 2>::store(p + 2, v + 2);
-    }
-    static __device__ __forceinline__ void store_nt(double *p, const double *v)
-    {
-        Vec<double, 2>::store_nt(p, v);
-        Vec<double, 2>::store_nt(p + 2, v + 2);
-    }
-};
-
-template <>
-struct Vec<float, 8> {
-    static __device__ __forceinline__ void load(const float *p, float *v)
-    {
-        Vec<float, 4>::load(p, v);
-        Vec<float, 4>::load(p + 4, v + 4);
-    }
-    static __device__ __forceinline__ void load_nt(const float *p, float *v)
-    {
-        Vec<float, 4>::load_nt(p, v);
-        Vec<float, 4>::load_nt(p + 4, v + 4);
-    }
-    static __device__ __forceinline__ void store(float *p, const float *v)
-    {
-        Vec<float, 4>::store(p, v);
-        Vec<float, 4>::store(p + 4, v + 4);
-    }
-    static __device__ __forceinline__ void store_nt(float *p, const float *v)
-    {
-        Vec<float, 4>::store_nt(p, v);
-        Vec<float, 4>::store_nt(p + 4, v + 4);
-    }
-};
 
 // ---- tile schedule ------------------------------------------------------------
 // Steps s = first, first + stride, ... < end of this workgroup; step s is
@@ -580,7 +604,8 @@ __device__ __forceinline__ void grid_reduce(Acc<T, Shape<T, M>::VW, NDOT> &acc, 
         for (int d = 0; d < NDOT; ++d)
 #pragma unroll
             for (int v = 0; v < S::VW; ++v)
-                s_w[wave][d * M + g * S::VW + v] = acc.a[d][v];
+                if (g * S::VW + v < M)  // the last lane may hold fewer columns
+                    s_w[wave][d * M + g * S::VW + v] = acc.a[d][v];
     }
     __syncthreads();
     const int b = blockIdx.x;

@@ -104,40 +104,6 @@ struct Kry {
     T beta[kMaxM];  // for the p update of the current iteration
 };
 
-#ifndef MRHS_NT_STORE
-#define MRHS_NT_STORE 1
-#endif
-
-// Block outputs are written with streaming (nontemporal) stores: every block
-// is far larger than the caches, and keeping written lines out of L2 leaves
-// it to the gathered block rows.
-template <typename T, int VW>
-__device__ __forceinline__ void put(T *p, const T *v)
-{
-#if MRHS_NT_STORE
-    Vec<T, VW>::store_nt(p, v);
-#else
-    Vec<T, VW>::store(p, v);
-#endif
-}
-
-#ifndef MRHS_NT_LOAD
-#define MRHS_NT_LOAD 0
-#endif
-
-// Row-aligned block operands that are read once (not gathered through the
-// matrix) are loaded with streaming loads, so they do not displace gathered
-// rows from L2.
-template <typename T, int VW>
-__device__ __forceinline__ void get(const T *p, T *v)
-{
-#if MRHS_NT_LOAD
-    Vec<T, VW>::load_nt(p, v);
-#else
-    Vec<T, VW>::load(p, v);
-#endif
-}
-
 template <typename T>
 __device__ __forceinline__ bool bad(T v)
 {
@@ -217,12 +183,12 @@ struct OpStore {
     __device__ Lane lane(int) const { return {true}; }
     __device__ __forceinline__ void gather(const Lane &, int32_t c, int g, T *x) const
     {
-        Vec<T, S::VW>::load(blk<T, M>(X, c, g * S::VW), x);
+        ld<T, M>(X, c, g, x);
     }
     __device__ __forceinline__ void row(const Lane &, int32_t i, int g, const T *sum,
                                         Acc<T, S::VW, NDOT> &) const
     {
-        put<T, S::VW>(blk<T, M>(Y, i, g * S::VW), sum);
+        st<T, M>(Y, i, g, sum);
     }
     __device__ void finish(const T *) const {}
 };
@@ -259,6 +225,8 @@ struct OpResid {
     };
     __device__ bool col_on(int c) const
     {
+        if (c >= M)
+            return false;
         const int32_t st = ctl->status[c];
         switch (kind) {
         case RES_SETUP:
@@ -283,14 +251,14 @@ struct OpResid {
     }
     __device__ __forceinline__ void gather(const Lane &, int32_t c, int g, double *x) const
     {
-        Vec<double, S::VW>::load(blk<T, M>(X, c, g * S::VW), x);
+        ld<double, M>(X, c, g, x);
     }
     __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, const double *sum,
                                         Acc<double, S::VW, NDOT> &acc) const
     {
         const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         double b[S::VW], r[S::VW];
-        get<double, S::VW>(B + o, b);
+        ld<double, M>(B, i, g, b);
         const bool restart = kind == RES_SETUP || kind == RES_CHECK;
         const double h = restart ? shadow<double>(i) : 0.0;
 #pragma unroll
@@ -308,11 +276,11 @@ struct OpResid {
             all = all && ln.act[v];
         if (all) {
             if (R)
-                put<double, S::VW>(R + o, r);
+                st<double, M>(R, i, g, r);
             if (R2)
-                put<double, S::VW>(R2 + o, r);
+                st<double, M>(R2, i, g, r);
             if (R3)
-                put<double, S::VW>(R3 + o, r);
+                st<double, M>(R3, i, g, r);
         } else {
             // only the columns this kind owns are written
 #pragma unroll
@@ -442,7 +410,7 @@ __device__ __forceinline__ RunLane<T, M> run_lane(const Ctl *ctl, int g)
     ln.on = false;
 #pragma unroll
     for (int v = 0; v < S::VW; ++v) {
-        ln.act[v] = ctl->status[g * S::VW + v] == COL_RUN;
+        ln.act[v] = g * S::VW + v < M && ctl->status[g * S::VW + v] == COL_RUN;
         ln.on = ln.on || ln.act[v];
     }
     return ln;
@@ -463,7 +431,7 @@ struct OpSpmv1 {
     __device__ Lane lane(int g) const { return run_lane<T, M>(ctl, g); }
     __device__ __forceinline__ void gather(const Lane &, int32_t c, int g, T *x) const
     {
-        Vec<T, S::VW>::load(blk<T, M>(p, c, g * S::VW), x);
+        ld<T, M>(p, c, g, x);
     }
     __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, const T *sum,
                                         Acc<T, S::VW, NDOT> &acc) const
@@ -471,7 +439,7 @@ struct OpSpmv1 {
         const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         T h[S::VW];
         shadow_row<T, M>(sgn, i, g, h);
-        put<T, S::VW>(v + o, sum);
+        st<T, M>(v, i, g, sum);
 #pragma unroll
         for (int q = 0; q < S::VW; ++q)
             if (ln.act[q])
@@ -525,10 +493,9 @@ struct OpSpmv2 {
     }
     __device__ __forceinline__ void gather(const Lane &ln, int32_t c, int g, T *x) const
     {
-        const size_t o = static_cast<size_t>(c) * M + g * S::VW;
         T rr[S::VW], vv[S::VW];
-        Vec<T, S::VW>::load(r + o, rr);
-        Vec<T, S::VW>::load(v + o, vv);
+        ld<T, M>(r, c, g, rr);
+        ld<T, M>(v, c, g, vv);
 #pragma unroll
         for (int q = 0; q < S::VW; ++q)
             x[q] = rr[q] - ln.alpha[q] * vv[q];
@@ -540,7 +507,7 @@ struct OpSpmv2 {
         T s[S::VW], h[S::VW];
         gather(ln, i, g, s);
         shadow_row<T, M>(sgn, i, g, h);
-        put<T, S::VW>(t + o, sum);
+        st<T, M>(t, i, g, sum);
 #pragma unroll
         for (int q = 0; q < S::VW; ++q) {
             if (ln.act[q]) {
@@ -618,11 +585,11 @@ struct OpXR {
     {
         const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         T yy[S::VW], rr[S::VW], pp[S::VW], vv[S::VW], tt[S::VW];
-        get<T, S::VW>(y + o, yy);
-        get<T, S::VW>(r + o, rr);
-        get<T, S::VW>(p + o, pp);
-        get<T, S::VW>(v + o, vv);
-        get<T, S::VW>(t + o, tt);
+        ld<T, M>(y, i, g, yy);
+        ld<T, M>(r, i, g, rr);
+        ld<T, M>(p, i, g, pp);
+        ld<T, M>(v, i, g, vv);
+        ld<T, M>(t, i, g, tt);
         T hh[S::VW];
         shadow_row<T, M>(sgn, i, g, hh);
 #pragma unroll
@@ -641,9 +608,9 @@ struct OpXR {
                 acc.a[1][q] += rr[q] * rr[q];
             }
         }
-        put<T, S::VW>(y + o, yy);
-        put<T, S::VW>(r + o, rr);
-        put<T, S::VW>(p + o, pp);
+        st<T, M>(y, i, g, yy);
+        st<T, M>(r, i, g, rr);
+        st<T, M>(p, i, g, pp);
     }
     __device__ void finish(const T *tot) const
     {
@@ -710,7 +677,7 @@ struct OpRestart {
 #pragma unroll
         for (int q = 0; q < S::VW; ++q) {
             const int c = g * S::VW + q;
-            ln.act[q] = (ctl->flag[c] & F_RESTART) && ctl->status[c] == COL_RUN;
+            ln.act[q] = c < M && (ctl->flag[c] & F_RESTART) && ctl->status[c] == COL_RUN;
             ln.on = ln.on || ln.act[q];
         }
         return ln;
@@ -719,17 +686,17 @@ struct OpRestart {
     {
         const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         T a[S::VW], b[S::VW], pp[S::VW];
-        get<T, S::VW>(rt + o, a);
-        get<T, S::VW>(r + o, b);
-        get<T, S::VW>(p + o, pp);
+        ld<T, M>(rt, i, g, a);
+        ld<T, M>(r, i, g, b);
+        ld<T, M>(p, i, g, pp);
 #pragma unroll
         for (int q = 0; q < S::VW; ++q)
             if (ln.act[q]) {
                 b[q] = a[q];
                 pp[q] = a[q];
             }
-        put<T, S::VW>(r + o, b);
-        put<T, S::VW>(p + o, pp);
+        st<T, M>(r, i, g, b);
+        st<T, M>(p, i, g, pp);
     }
     __device__ void finish(const T *) const {}
 };
@@ -768,7 +735,7 @@ struct OpScale {
 #pragma unroll
         for (int q = 0; q < S::VW; ++q) {
             const int c = g * S::VW + q;
-            ln.act[q] = (cmask >> c) & 1u;
+            ln.act[q] = c < M && ((cmask >> c) & 1u);
             ln.zero[q] = (ctl->flag[c] & F_ZERO_X) != 0;
             ln.mean[q] = ctl->colsum[c] / static_cast<double>(ctl->n);
             ln.on = ln.on || ln.act[q];
@@ -779,7 +746,7 @@ struct OpScale {
     {
         const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         double a[S::VW];
-        get<double, S::VW>(x + o, a);
+        ld<double, M>(x, i, g, a);
         const double di = (kind == SC_IN) ? diag[i] : (kind == SC_OUT ? dinv[i] : 1.0);
 #pragma unroll
         for (int q = 0; q < S::VW; ++q) {
@@ -794,7 +761,7 @@ struct OpScale {
             else if (kind == SC_IN || kind == SC_OUT)
                 a[q] = a[q] * di;
         }
-        put<double, S::VW>(x + o, a);
+        st<double, M>(x, i, g, a);
     }
     __device__ void finish(const double *) const {}
 };
@@ -818,7 +785,7 @@ struct OpColSum {
         ln.on = false;
 #pragma unroll
         for (int q = 0; q < S::VW; ++q) {
-            ln.act[q] = (cmask >> (g * S::VW + q)) & 1u;
+            ln.act[q] = g * S::VW + q < M && ((cmask >> (g * S::VW + q)) & 1u);
             ln.on = ln.on || ln.act[q];
         }
         return ln;
@@ -826,7 +793,7 @@ struct OpColSum {
     __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, Acc<double, S::VW, NDOT> &acc) const
     {
         double a[S::VW];
-        get<double, S::VW>(x + static_cast<size_t>(i) * M + g * S::VW, a);
+        ld<double, M>(x, i, g, a);
 #pragma unroll
         for (int q = 0; q < S::VW; ++q)
             if (ln.act[q])
@@ -868,7 +835,7 @@ struct OpCast {
 #pragma unroll
         for (int q = 0; q < S::VW; ++q) {
             const int c = g * S::VW + q;
-            ln.act[q] = ctl->status[c] == COL_OUTER;
+            ln.act[q] = c < M && ctl->status[c] == COL_OUTER;
             ln.scale[q] = ctl->rscale[c];
             ln.on = ln.on || ln.act[q];
         }
@@ -878,9 +845,9 @@ struct OpCast {
     {
         const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         float a[S::VW], z[S::VW], pp[S::VW];
-        get<float, S::VW>(r + o, a);
-        get<float, S::VW>(y + o, z);
-        get<float, S::VW>(p + o, pp);
+        ld<float, M>(r, i, g, a);
+        ld<float, M>(y, i, g, z);
+        ld<float, M>(p, i, g, pp);
         uint8_t *sb = sgn + static_cast<size_t>(i) * S::L + g;
         uint32_t bits = *sb;
 #pragma unroll
@@ -895,9 +862,9 @@ struct OpCast {
                 bits = (f < 0.0f) ? (bits | (1u << q)) : (bits & ~(1u << q));
             }
         }
-        put<float, S::VW>(r + o, a);
-        put<float, S::VW>(y + o, z);
-        put<float, S::VW>(p + o, pp);
+        st<float, M>(r, i, g, a);
+        st<float, M>(y, i, g, z);
+        st<float, M>(p, i, g, pp);
         *sb = static_cast<uint8_t>(bits);
     }
     __device__ void finish(const float *tot) const
@@ -949,7 +916,7 @@ __device__ __forceinline__ RunLane<double, M> inner_done_lane(const Ctl *ctl, in
     ln.on = false;
 #pragma unroll
     for (int q = 0; q < S::VW; ++q) {
-        ln.act[q] = ctl->status[g * S::VW + q] == COL_INNER_DONE;
+        ln.act[q] = g * S::VW + q < M && ctl->status[g * S::VW + q] == COL_INNER_DONE;
         ln.on = ln.on || ln.act[q];
     }
     return ln;
@@ -977,7 +944,7 @@ struct OpGcrZ {
 #pragma unroll
         for (int q = 0; q < S::VW; ++q) {
             const int c = g * S::VW + q;
-            ln.act[q] = ctl->status[c] == COL_INNER_DONE;
+            ln.act[q] = c < M && ctl->status[c] == COL_INNER_DONE;
             ln.scale[q] = ctl->rscale[c];
         }
         return ln;
@@ -990,7 +957,7 @@ struct OpGcrZ {
 #pragma unroll
         for (int q = 0; q < S::VW; ++q)
             a[q] = ln.act[q] ? ln.scale[q] * (di * static_cast<double>(y[o + q])) : 0.0;
-        put<double, S::VW>(z + o, a);
+        st<double, M>(z, i, g, a);
     }
     __device__ void finish(const double *) const {}
 };
@@ -1010,13 +977,13 @@ struct OpGcrDots {
     {
         const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         double wn[S::VW];
-        get<double, S::VW>(b.wnew + o, wn);
+        ld<double, M>(b.wnew, i, g, wn);
 #pragma unroll
         for (int j = 0; j < kGcrMax; ++j) {
             if (j >= b.jmax)
                 break;
             double wj[S::VW];
-            get<double, S::VW>(b.w[j] + o, wj);
+            ld<double, M>(b.w[j], i, g, wj);
 #pragma unroll
             for (int q = 0; q < S::VW; ++q)
                 if (ln.act[q])
@@ -1071,16 +1038,16 @@ struct OpGcrOrth {
     {
         const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         double wn[S::VW], zn[S::VW], rr[S::VW];
-        get<double, S::VW>(b.wnew + o, wn);
-        get<double, S::VW>(b.znew + o, zn);
-        get<double, S::VW>(r + o, rr);
+        ld<double, M>(b.wnew, i, g, wn);
+        ld<double, M>(b.znew, i, g, zn);
+        ld<double, M>(r, i, g, rr);
 #pragma unroll
         for (int j = 0; j < kGcrMax; ++j) {
             if (j >= b.jmax)
                 break;
             double wj[S::VW], zj[S::VW];
-            get<double, S::VW>(b.w[j] + o, wj);
-            get<double, S::VW>(b.z[j] + o, zj);
+            ld<double, M>(b.w[j], i, g, wj);
+            ld<double, M>(b.z[j], i, g, zj);
 #pragma unroll
             for (int q = 0; q < S::VW; ++q) {
                 if (ln.act[q] && ln.beta[j][q] != 0.0) {
@@ -1097,8 +1064,8 @@ struct OpGcrOrth {
             }
         }
         if (b.jmax > 0) {
-            put<double, S::VW>(b.wnew + o, wn);
-            put<double, S::VW>(b.znew + o, zn);
+            st<double, M>(b.wnew, i, g, wn);
+            st<double, M>(b.znew, i, g, zn);
         }
     }
     __device__ void finish(const double *tot) const
@@ -1151,10 +1118,10 @@ struct OpGcrUpdate {
     {
         const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         double xx[S::VW], rr[S::VW], zz[S::VW], ww[S::VW];
-        get<double, S::VW>(x + o, xx);
-        get<double, S::VW>(r + o, rr);
-        get<double, S::VW>(b.znew + o, zz);
-        get<double, S::VW>(b.wnew + o, ww);
+        ld<double, M>(x, i, g, xx);
+        ld<double, M>(r, i, g, rr);
+        ld<double, M>(b.znew, i, g, zz);
+        ld<double, M>(b.wnew, i, g, ww);
 #pragma unroll
         for (int q = 0; q < S::VW; ++q) {
             if (ln.act[q]) {
@@ -1165,8 +1132,8 @@ struct OpGcrUpdate {
                 __builtin_nontemporal_store(ww[q], ln.ws[q] + o + q);
             }
         }
-        put<double, S::VW>(x + o, xx);
-        put<double, S::VW>(r + o, rr);
+        st<double, M>(x, i, g, xx);
+        st<double, M>(r, i, g, rr);
     }
     __device__ void finish(const double *tot) const
     {
