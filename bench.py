@@ -63,7 +63,10 @@ def kernel_bytes(name, n, nnz, m, S):
     blk = S * m * n
     # the binary64 shadow residual is generated in the kernels; binary32
     # inner solves read its sign bits, one byte per lane of a row
-    sgn = 0 if S == 8 else n * next_pow2(m // (4 if m % 4 == 0 else 2 if m % 2 == 0 else 1))
+    VW = 4 if m % 4 == 0 else 2 if m % 2 == 0 else 1
+    G = m // VW
+    L = G if (VW == 1 or G == 5) and 64 // G > 64 // next_pow2(G) else next_pow2(G)
+    sgn = 0 if S == 8 else n * L
     table = {
         "gspmv": mat + 2 * blk,             # read X, write Y
         "spmv_sigma": mat + 2 * blk + sgn,  # read p (gathered); write v

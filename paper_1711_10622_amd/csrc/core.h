@@ -69,13 +69,24 @@ struct Shape {
                                                              : (M % 4 == 0 ? 4 : (M % 2 == 0 ? 2 : 1));
     static constexpr int G = (M + VW - 1) / VW;  // lanes that hold data in a row
     static constexpr int TAIL = M - (G - 1) * VW; // columns of the row's last lane (1..VW)
-    static constexpr int L = next_pow2(G);        // lanes per row
-    static constexpr int RPP = kBlock / L;        // rows per pass of the workgroup
-    static constexpr int TR = RPP > kTileRows ? RPP : kTileRows;  // rows per tile
-    static constexpr int NZCAP = TR * MRHS_NZ_PER_ROW;            // staged nonzeros per tile
-    static constexpr int PASSES = TR / RPP;
-    static_assert(PASSES >= 1 && PASSES * RPP == TR, "a tile must hold whole passes");
+    // lanes per row: the next power of two of G, or G itself for one-element
+    // lanes (odd M) and G = 5 when that fits more rows into a wave.  Measured
+    // on the 12.6M-row channel: +6..+43 % for odd M; for 16-byte lanes only
+    // G = 5 gained (binary32 M = 10: +25 %), G = 3, 6, 7 lost up to 12 %.
+    static constexpr bool EXACT = (VW == 1 || G == 5) && 64 / G > 64 / next_pow2(G);
+    static constexpr int L = EXACT ? G : next_pow2(G);
+    static constexpr bool POW2 = L == next_pow2(L);
+    static constexpr int RW = 64 / L;             // rows per wave (lanes past RW*L idle)
+    static constexpr int RPP = (kBlock / 64) * RW; // rows per pass of the workgroup
+    static constexpr int PASSES = RPP >= kTileRows ? 1 : kTileRows / RPP;
+    static constexpr int TR = RPP * PASSES;       // rows per tile
+    static constexpr int NZCAP = TR * MRHS_NZ_PER_ROW;  // staged nonzeros per tile
     static_assert(L <= 64, "a row must fit one wave");
+    static_assert(L <= kMaxM, "a row's lanes fit the per-row byte arrays");
+    // thread -> (lane in row, row in pass); lane_on = false for idle lanes
+    static __device__ __forceinline__ int lane_of(int tid) { return (tid & 63) % L; }
+    static __device__ __forceinline__ int row_of(int tid) { return (tid >> 6) * RW + (tid & 63) / L; }
+    static __device__ __forceinline__ bool used(int tid) { return (tid & 63) < RW * L; }
 };
 
 // ---- 8/16-byte vector access ------------------------------------------------
@@ -395,10 +406,10 @@ __device__ __forceinline__ void gspmv_tiles(const CsrView<T> &A, const Op &op,
     __shared__ __align__(16) int32_t s_ci[S::NZCAP + 4];
     __shared__ __align__(16) T s_va[S::NZCAP + 4];
     const int tid = threadIdx.x;
-    const int g = tid % S::L;
-    const int rl = tid / S::L;
+    const int g = S::lane_of(tid);
+    const int rl = S::row_of(tid);
     const typename Op::Lane ln = op.lane(g < S::G ? g : 0);
-    const bool lane_on = g < S::G && ln.on;
+    const bool lane_on = S::used(tid) && g < S::G && ln.on;
     const int32_t ntiles = static_cast<int32_t>((static_cast<int64_t>(A.n) + S::TR - 1) / S::TR);
     const TileRange tr = tile_range(ntiles, plane_tiles(A.reach, S::TR, ntiles));
     for (int32_t step = tr.first; step < tr.end; step += tr.stride) {
@@ -486,9 +497,9 @@ __device__ __forceinline__ void stream_tiles(int32_t n, const Op &op,
 {
     using S = Shape<T, M>;
     const int tid = threadIdx.x;
-    const int g = tid % S::L;
-    const int rl = tid / S::L;
-    if (g >= S::G)
+    const int g = S::lane_of(tid);
+    const int rl = S::row_of(tid);
+    if (!S::used(tid) || g >= S::G)
         return;
     const typename Op::Lane ln = op.lane(g);
     if (!ln.on)
@@ -590,15 +601,31 @@ __device__ __forceinline__ void grid_reduce(Acc<T, Shape<T, M>::VW, NDOT> &acc, 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int g = tid % S::L;
+    const int g = S::lane_of(tid);
 
+    // sum the wave's rows lane by lane: a xor butterfly when rows are a power
+    // of two of lanes wide, else a fixed shift-down tree over the RW rows
+    // (idle lanes past RW*L hold zeros)
+    if constexpr (S::POW2) {
 #pragma unroll
-    for (int off = S::L; off < 64; off <<= 1)
+        for (int off = S::L; off < 64; off <<= 1)
 #pragma unroll
-        for (int d = 0; d < NDOT; ++d)
+            for (int d = 0; d < NDOT; ++d)
 #pragma unroll
-            for (int v = 0; v < S::VW; ++v)
-                acc.a[d][v] += __shfl_xor(acc.a[d][v], off);
+                for (int v = 0; v < S::VW; ++v)
+                    acc.a[d][v] += __shfl_xor(acc.a[d][v], off);
+    } else {
+#pragma unroll
+        for (int off = S::L; off < S::RW * S::L; off <<= 1)
+#pragma unroll
+            for (int d = 0; d < NDOT; ++d)
+#pragma unroll
+                for (int v = 0; v < S::VW; ++v) {
+                    const T o = __shfl_down(acc.a[d][v], off);
+                    if (lane + off < S::RW * S::L)
+                        acc.a[d][v] += o;
+                }
+    }
     if (lane < S::L && g < S::G) {
 #pragma unroll
         for (int d = 0; d < NDOT; ++d)
