@@ -319,6 +319,8 @@ Engine::Engine(const mrhs_csr_s &A, int m, uint32_t flags, void *ws, const doubl
     chunk_ = env_int("MRHS_POLL_ITERS", 16, 1, 1024);
     tol_in_ = env_double("MRHS_INNER_TOL", 0.1);
     max_outer_ = env_int("MRHS_MAX_OUTER", 500, 1, 100000);
+    outer_batch_ = env_double("MRHS_OUTER_BATCH", 1.0);
+    outer_wait_ = env_int("MRHS_OUTER_WAIT", 0, 0, 100000);
 }
 
 Engine::~Engine()
@@ -337,6 +339,7 @@ mrhs_status Engine::reset()
     }
     std::memset(host_, 0, sizeof(Ctl));
     gcr_steps_ = 0;
+    waited_ = 0;
     c_.gcr.jmax = 0;
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s_, tickets_, kGroups + 1, 0u);
     hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, s_, c_.ctl, mixed_ ? MODE_INNER : MODE_F64, tol_in_,
@@ -408,10 +411,21 @@ mrhs_status Engine::advance(bool *busy)
     }
     if (pend)
         MRHS_HIP(T_->mixed_check(c_));
+    // A refinement step streams every row of the block whatever the number
+    // of columns it serves (a row of the block is one or two cache lines), so
+    // columns whose inner solve ended wait, idle, until they are a share
+    // outer_batch_ of the active columns, nothing else runs, or the first of
+    // them has waited outer_wait_ iterations.  A column's arithmetic does not
+    // depend on when its step comes.
     if (done_in) {
-        MRHS_HIP(T_->mixed_step(c_));
-        ++gcr_steps_;
-        c_.gcr.jmax = std::min(gcr_steps_, ndirs_);
+        if (run == 0 || done_in >= outer_batch_ * (run + done_in) || waited_ >= outer_wait_) {
+            MRHS_HIP(T_->mixed_step(c_));
+            ++gcr_steps_;
+            c_.gcr.jmax = std::min(gcr_steps_, ndirs_);
+            waited_ = 0;
+        } else {
+            waited_ += chunk_;
+        }
     }
     MRHS_HIP(T_->mixed_cast(c_));
     MRHS_HIP(T_->inner_iterate(c_, chunk_));
