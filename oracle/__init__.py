@@ -128,6 +128,21 @@ def row_subset(A, rows):
     return _Rows(len(rows), srp.astype(np.int32), A.col[src], A.val[src])
 
 
+def gspmv_part(S, X):
+    """S X for a row subset S of a matrix (from ``row_subset``) and the full
+    block X: the rows of A X that S holds."""
+    lib = _load()
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    if X.ndim == 1:
+        X = X[:, None]
+    m = X.shape[1]
+    Y = np.empty((S.n, m), dtype=np.float64)
+    rp, ci, va = _csr(S)
+    lib.oracle_gspmv(S.n, _p(rp, ctypes.c_int32), _p(ci, ctypes.c_int32), _p(va, ctypes.c_double), m,
+                     _p(X, ctypes.c_double), _p(Y, ctypes.c_double))
+    return Y
+
+
 def gspmv_rows(A, X, rows, dot2=False):
     """Rows ``rows`` of A X, for sampled checks of products too large to
     recompute whole."""
