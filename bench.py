@@ -292,7 +292,7 @@ def cpu_baseline(A, B, ncols):
     return {"value": wall / ncols, "unit": "s/RHS", "cores": ncols, "kind": "oracle",
             "sample": f"{ncols} of the {B.shape[1]} right-hand sides of the same workload, "
                       f"one host thread per column, FP64 to 1e-10 (wall {wall:.2f} s)",
-            "iters": [i["iters"] for i in infos]}
+            "iters": [i["iters"] for i in infos]}, X
 
 
 def host_info():
@@ -391,6 +391,7 @@ def main():
         timed_solves(torch, M, B, X, ws, args.warmup)
     step_s, infos, trace = timed_solves(torch, M, B, X, ws, args.steps, trace=True)
     dom = dominant_kernel(trace, A.n, A.nnz)
+    X_f64 = X[:, :4].cpu().numpy()  # for the per-RHS error against the oracle
     log(f"step {step_s * 1e3:.2f} ms, dominant {dom['kernel']} {dom['avg_us']:.1f} us")
     relres = max(i["relres"] for i in infos)
     extra = {"iters": [i["iters"] for i in infos], "max_relres": relres,
@@ -448,6 +449,7 @@ def main():
                           "iters": [i["iters"] for i in imix], "outer": [i["outer"] for i in imix],
                           "max_relres": max(i["relres"] for i in imix)}
         log(f"mixed {tmix * 1e3:.1f} ms")
+        X_mix = X[:, :4].cpu().numpy()
         del M, ws, B, X
         torch.cuda.empty_cache()
         extra["gspmv_chan128"] = gspmv_sweep(torch, A, [1, 2, 4, 8, 16], ("f64",), flush=True)
@@ -466,8 +468,13 @@ def main():
         log("gspmv chan256 done")
         del L
     if not args.no_cpu:
-        result["cpu_baseline"] = cpu_baseline(A, Bh, 4)
+        result["cpu_baseline"], Xo = cpu_baseline(A, Bh, 4)
         result["cpu_baseline"]["host"] = host_info()
+        # per-RHS relative error of the GPU solutions against the oracle's
+        rel = lambda Xg: [float(np.linalg.norm(Xg[:, l] - Xo[:, l]) / np.linalg.norm(Xo[:, l])) for l in range(4)]
+        extra["error_vs_oracle_first4"] = {"fp64": rel(X_f64)}
+        if not args.quick:
+            extra["error_vs_oracle_first4"]["mixed"] = rel(X_mix)
         if not args.quick:
             extra["cpu_gspmv_chan128"] = cpu_gspmv(A, 16, min(16, os.cpu_count() or 1))
     result["extra"] = extra
