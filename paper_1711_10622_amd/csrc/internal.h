@@ -206,7 +206,8 @@ class Engine {
     int chunk_ = 16, ndirs_ = kGcrMax, gcr_steps_ = 0, max_outer_ = 500;
     double tol_in_ = 0.1;
     double outer_batch_ = 1.0;  // share of a block's active columns that triggers a refinement step
-    int outer_wait_ = 0;        // ... or this many iterations waited by a column, whichever first
+    int outer_wait_ = 8;        // ... or this many iterations waited by a column, whichever first
+    int mixed_chunk_ = 8;       // inner iterations between polls (mixed precision)
     int waited_ = 0;
 };
 

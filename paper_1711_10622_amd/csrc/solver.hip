@@ -320,7 +320,8 @@ Engine::Engine(const mrhs_csr_s &A, int m, uint32_t flags, void *ws, const doubl
     tol_in_ = env_double("MRHS_INNER_TOL", 0.1);
     max_outer_ = env_int("MRHS_MAX_OUTER", 500, 1, 100000);
     outer_batch_ = env_double("MRHS_OUTER_BATCH", 1.0);
-    outer_wait_ = env_int("MRHS_OUTER_WAIT", 0, 0, 100000);
+    outer_wait_ = env_int("MRHS_OUTER_WAIT", 8, 0, 100000);
+    mixed_chunk_ = env_int("MRHS_MIXED_POLL", 8, 1, 1024);
 }
 
 Engine::~Engine()
@@ -424,11 +425,11 @@ mrhs_status Engine::advance(bool *busy)
             c_.gcr.jmax = std::min(gcr_steps_, ndirs_);
             waited_ = 0;
         } else {
-            waited_ += chunk_;
+            waited_ += mixed_chunk_;
         }
     }
     MRHS_HIP(T_->mixed_cast(c_));
-    MRHS_HIP(T_->inner_iterate(c_, chunk_));
+    MRHS_HIP(T_->inner_iterate(c_, mixed_chunk_));
     return MRHS_OK;
 }
 
