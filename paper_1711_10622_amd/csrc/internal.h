@@ -165,8 +165,8 @@ struct StepTable {
     hipError_t (*f64_check)(Ctx &);
     hipError_t (*finish)(Ctx &, uint32_t, bool, bool);
     hipError_t (*mixed_start)(Ctx &, uint32_t, bool);
-    hipError_t (*mixed_step)(Ctx &);
-    hipError_t (*mixed_check)(Ctx &);
+    hipError_t (*mixed_step)(Ctx &, uint32_t, const int32_t *, const int32_t *);
+    hipError_t (*mixed_check)(Ctx &, uint32_t);
     hipError_t (*mixed_cast)(Ctx &);
     hipError_t (*inner_iterate)(Ctx &, int);
 };
@@ -203,11 +203,12 @@ class Engine {
     Ctx c_{};
     unsigned *tickets_ = nullptr;
     Ctl *host_ = nullptr;
-    int chunk_ = 16, ndirs_ = kGcrMax, gcr_steps_ = 0, max_outer_ = 500;
+    int chunk_ = 16, ndirs_ = kGcrMax, max_outer_ = 500;
+    int col_steps_[kMaxM] = {};  // refinement steps of each column since its admission (slot = steps % ndirs)
     double tol_in_ = 0.1;
     double outer_batch_ = 1.0;  // share of a block's active columns that triggers a refinement step
-    int outer_wait_ = 8;        // ... or this many iterations waited by a column, whichever first
-    int mixed_chunk_ = 8;       // inner iterations between polls (mixed precision)
+    int outer_wait_ = 0;        // ... or this many iterations waited by a column, whichever first
+    int mixed_chunk_ = 4;       // inner iterations between polls (mixed precision)
     int waited_ = 0;
 };
 

@@ -219,6 +219,7 @@ struct OpResid {
     Kry<double> *kry;
     int32_t kind;
     uint32_t cmask;  // columns of RES_FINAL / RES_NORM
+    int32_t rcm;     // > 0: R is column-major with column stride rcm (R2, R3 unused)
     struct Lane {
         bool on;
         bool act[S::VW];
@@ -269,6 +270,13 @@ struct OpResid {
                 acc.a[1][v] += b[v] * b[v];
                 acc.a[2][v] += h * r[v];
             }
+        }
+        if (rcm > 0) {
+#pragma unroll
+            for (int v = 0; v < S::VW; ++v)
+                if (ln.act[v] && R)
+                    R[static_cast<size_t>(g * S::VW + v) * rcm + i] = r[v];
+            return;
         }
         bool all = true;
 #pragma unroll
@@ -816,13 +824,14 @@ struct OpCast {
     static constexpr const char *kName = "cast32";
     using S = Shape<float, M>;
     static constexpr int NDOT = 2;
-    const double *r64;
+    const double *r64;  // column-major n x m
     float *r;
     uint8_t *sgn;
     float *y;
     float *p;
     Ctl *ctl;
     Kry<float> *kry;
+    int32_t n;
     struct Lane {
         bool on;
         bool act[S::VW];
@@ -853,7 +862,7 @@ struct OpCast {
 #pragma unroll
         for (int q = 0; q < S::VW; ++q) {
             if (ln.act[q]) {
-                const float f = static_cast<float>(r64[o + q] / ln.scale[q]);
+                const float f = static_cast<float>(r64[static_cast<size_t>(g * S::VW + q) * n + i] / ln.scale[q]);
                 a[q] = f;
                 pp[q] = f;
                 z[q] = 0.0f;
@@ -897,41 +906,34 @@ struct OpCast {
 // truncated to the most recent ndirs directions):
 //   w -= sum_j beta_j w_j, z -= sum_j beta_j z_j, beta_j = (w, w_j)/(w_j, w_j)
 //   gamma = (r, w)/(w, w);  x += gamma z;  r -= gamma w.
-// Every column keeps its own directions (slot kcol[c] receives the next one),
-// so a column's arithmetic never depends on the other columns of the block.
+// The refinement vectors are kept per column, column-major (column c's n
+// values at offset c * n of an n x m buffer): r, the accumulated correction
+// of x, the new direction z, w and the ndirs stored directions (slot kcol[c]
+// receives the next one).  A step then streams only its own column's
+// vectors, so it runs as soon as that column's inner solve ends; over
+// row-interleaved blocks every step would stream all columns' rows.  A
+// column's arithmetic never depends on the other columns of the block.
 struct GcrBlocks {
-    double *z[kGcrMax];
-    double *w[kGcrMax];
-    double *znew;
+    double *z[kGcrMax];  // stored directions z_j
+    double *w[kGcrMax];  // and w_j = A z_j
+    double *znew;        // the direction being formed
     double *wnew;
-    int32_t ndirs;  // directions kept per column
-    int32_t jmax;   // slots that can hold a direction of any column so far
+    double *xacc;        // accumulated correction of x (folded into X before checks and at the end)
+    int32_t ndirs;       // directions kept per column
 };
 
-template <int M>
-__device__ __forceinline__ RunLane<double, M> inner_done_lane(const Ctl *ctl, int g)
-{
-    using S = Shape<double, M>;
-    RunLane<double, M> ln;
-    ln.on = false;
-#pragma unroll
-    for (int q = 0; q < S::VW; ++q) {
-        ln.act[q] = g * S::VW + q < M && ctl->status[g * S::VW + q] == COL_INNER_DONE;
-        ln.on = ln.on || ln.act[q];
-    }
-    return ln;
-}
-
-// z_new = ||r|| * D^-1 * y32 (zero in the other columns)
+// z_new(:, c) = ||r_c|| D^-1 y32(:, c) for the columns whose inner solve ended
+// (row-interleaved binary32 in, column-major binary64 out)
 template <int M>
 struct OpGcrZ {
-    using S = Shape<double, M>;
+    using S = Shape<float, M>;
     static constexpr const char *kName = "gcr_z";
     static constexpr int NDOT = 0;
     double *z;
     const float *y;
     const double *dinv;
     const Ctl *ctl;
+    int32_t n;
     struct Lane {
         bool on;
         bool act[S::VW];
@@ -940,211 +942,165 @@ struct OpGcrZ {
     __device__ Lane lane(int g) const
     {
         Lane ln;
-        ln.on = true;
+        ln.on = false;
 #pragma unroll
         for (int q = 0; q < S::VW; ++q) {
             const int c = g * S::VW + q;
             ln.act[q] = c < M && ctl->status[c] == COL_INNER_DONE;
             ln.scale[q] = ctl->rscale[c];
+            ln.on = ln.on || ln.act[q];
         }
         return ln;
     }
-    __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, Acc<double, S::VW, NDOT> &) const
+    __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, Acc<float, S::VW, NDOT> &) const
     {
-        const size_t o = static_cast<size_t>(i) * M + g * S::VW;
-        double a[S::VW];
+        float yy[S::VW];
+        ld<float, M>(y, i, g, yy);
         const double di = dinv[i];
 #pragma unroll
         for (int q = 0; q < S::VW; ++q)
-            a[q] = ln.act[q] ? ln.scale[q] * (di * static_cast<double>(y[o + q])) : 0.0;
-        st<double, M>(z, i, g, a);
+            if (ln.act[q])
+                __builtin_nontemporal_store(ln.scale[q] * (di * static_cast<double>(yy[q])),
+                                            z + static_cast<size_t>(g * S::VW + q) * n + i);
     }
-    __device__ void finish(const double *) const {}
+    __device__ void finish(const float *) const {}
 };
 
-// beta_j = (w_new, w_j) / (w_j, w_j) over the column's stored directions
-// (slot kcol[c] is about to be replaced and is left out)
-template <int M>
-struct OpGcrDots {
-    using S = Shape<double, M>;
+// ---- per-column refinement ops: streams over one column's n-vectors (M = 1)
+struct ColLane {
+    bool on;
+};
+
+// beta_j = (w, w_j) / (w_j, w_j) over the column's stored directions (slot
+// kcol[c] is about to be replaced and is left out)
+struct OpColDots {
+    using S = Shape<double, 1>;
     static constexpr const char *kName = "gcr_dots";
     static constexpr int NDOT = kGcrMax;
-    GcrBlocks b;
+    const double *w;
+    const double *W[kGcrMax];
+    int32_t jmax;
+    int32_t col;
     Ctl *ctl;
-    using Lane = RunLane<double, M>;
-    __device__ Lane lane(int g) const { return inner_done_lane<M>(ctl, g); }
-    __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, Acc<double, S::VW, NDOT> &acc) const
+    using Lane = ColLane;
+    __device__ Lane lane(int) const { return {true}; }
+    __device__ __forceinline__ void row(const Lane &, int32_t i, int, Acc<double, 1, NDOT> &acc) const
     {
-        const size_t o = static_cast<size_t>(i) * M + g * S::VW;
-        double wn[S::VW];
-        ld<double, M>(b.wnew, i, g, wn);
+        const double wi = w[i];
 #pragma unroll
-        for (int j = 0; j < kGcrMax; ++j) {
-            if (j >= b.jmax)
-                break;
-            double wj[S::VW];
-            ld<double, M>(b.w[j], i, g, wj);
-#pragma unroll
-            for (int q = 0; q < S::VW; ++q)
-                if (ln.act[q])
-                    acc.a[j][q] += wn[q] * wj[q];
-        }
+        for (int j = 0; j < kGcrMax; ++j)
+            if (j < jmax)
+                acc.a[j][0] += wi * W[j][i];
     }
     __device__ void finish(const double *tot) const
     {
-        const int c = threadIdx.x;
-        if (c >= M || ctl->status[c] != COL_INNER_DONE)
+        if (threadIdx.x != 0)
             return;
+        const int c = col;
         for (int j = 0; j < kGcrMax; ++j) {
             const double d = ctl->wnorm2[j][c];
-            const bool valid = j < b.jmax && j != ctl->kcol[c] && d > 0.0 && isfinite(d);
-            const double bj = valid ? tot[j * M + c] / d : 0.0;
+            const bool valid = j < jmax && j != ctl->kcol[c] && d > 0.0 && isfinite(d);
+            const double bj = valid ? tot[j] / d : 0.0;
             ctl->beta[j][c] = isfinite(bj) ? bj : 0.0;
         }
     }
 };
 
-// w_new -= sum beta_j w_j, z_new -= sum beta_j z_j; sums (w_new, w_new) and
-// (r, w_new).  Terms with beta_j = 0 are skipped, so slots holding stale data
-// of other requests never enter a column's arithmetic.
-template <int M>
-struct OpGcrOrth {
-    using S = Shape<double, M>;
+// w -= sum beta_j w_j, z -= sum beta_j z_j; sums (w, w) and (r, w).  Terms
+// with beta_j = 0 are skipped, so slots holding stale data of an earlier
+// request in the slot never enter the column's arithmetic.
+struct OpColOrth {
+    using S = Shape<double, 1>;
     static constexpr const char *kName = "gcr_orth";
     static constexpr int NDOT = 2;
-    GcrBlocks b;
+    double *w;
+    double *z;
+    const double *W[kGcrMax];
+    const double *Z[kGcrMax];
     const double *r;
+    int32_t jmax;
+    int32_t col;
     Ctl *ctl;
     struct Lane {
         bool on;
-        bool act[S::VW];
-        double beta[kGcrMax][S::VW];
+        double beta[kGcrMax];
     };
-    __device__ Lane lane(int g) const
+    __device__ Lane lane(int) const
     {
         Lane ln;
-        const RunLane<double, M> rl = inner_done_lane<M>(ctl, g);
-        ln.on = rl.on;
+        ln.on = true;
 #pragma unroll
-        for (int q = 0; q < S::VW; ++q) {
-            ln.act[q] = rl.act[q];
-#pragma unroll
-            for (int j = 0; j < kGcrMax; ++j)
-                ln.beta[j][q] = ctl->beta[j][g * S::VW + q];
-        }
+        for (int j = 0; j < kGcrMax; ++j)
+            ln.beta[j] = j < jmax ? ctl->beta[j][col] : 0.0;
         return ln;
     }
-    __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, Acc<double, S::VW, NDOT> &acc) const
+    __device__ __forceinline__ void row(const Lane &ln, int32_t i, int, Acc<double, 1, NDOT> &acc) const
     {
-        const size_t o = static_cast<size_t>(i) * M + g * S::VW;
-        double wn[S::VW], zn[S::VW], rr[S::VW];
-        ld<double, M>(b.wnew, i, g, wn);
-        ld<double, M>(b.znew, i, g, zn);
-        ld<double, M>(r, i, g, rr);
+        double wi = w[i], zi = z[i];
 #pragma unroll
         for (int j = 0; j < kGcrMax; ++j) {
-            if (j >= b.jmax)
-                break;
-            double wj[S::VW], zj[S::VW];
-            ld<double, M>(b.w[j], i, g, wj);
-            ld<double, M>(b.z[j], i, g, zj);
-#pragma unroll
-            for (int q = 0; q < S::VW; ++q) {
-                if (ln.act[q] && ln.beta[j][q] != 0.0) {
-                    wn[q] -= ln.beta[j][q] * wj[q];
-                    zn[q] -= ln.beta[j][q] * zj[q];
-                }
+            if (j < jmax && ln.beta[j] != 0.0) {
+                wi -= ln.beta[j] * W[j][i];
+                zi -= ln.beta[j] * Z[j][i];
             }
         }
-#pragma unroll
-        for (int q = 0; q < S::VW; ++q) {
-            if (ln.act[q]) {
-                acc.a[0][q] += wn[q] * wn[q];
-                acc.a[1][q] += rr[q] * wn[q];
-            }
-        }
-        if (b.jmax > 0) {
-            st<double, M>(b.wnew, i, g, wn);
-            st<double, M>(b.znew, i, g, zn);
+        acc.a[0][0] += wi * wi;
+        acc.a[1][0] += r[i] * wi;
+        if (jmax > 0) {
+            __builtin_nontemporal_store(wi, w + i);
+            __builtin_nontemporal_store(zi, z + i);
         }
     }
     __device__ void finish(const double *tot) const
     {
-        const int c = threadIdx.x;
-        if (c >= M || ctl->status[c] != COL_INNER_DONE)
+        if (threadIdx.x != 0)
             return;
-        const double ww = tot[c], rw = tot[M + c];
-        ctl->wnew2[c] = ww;
-        ctl->gamma[c] = (ww > 0.0 && isfinite(ww) && isfinite(rw)) ? rw / ww : 0.0;
+        const double ww = tot[0], rw = tot[1];
+        ctl->wnew2[col] = ww;
+        ctl->gamma[col] = (ww > 0.0 && isfinite(ww) && isfinite(rw)) ? rw / ww : 0.0;
     }
 };
 
-// x += gamma z_new;  r -= gamma w_new; the new direction is stored in the
-// column's slot kcol[c]; sums (r, r).  The last workgroup decides each
-// column's next state.
-template <int M>
-struct OpGcrUpdate {
-    using S = Shape<double, M>;
+// x_acc += gamma z;  r -= gamma w; the direction goes to the column's slot
+// kcol[c]; sums (r, r).  The last workgroup decides the column's next state.
+struct OpColUpdate {
+    using S = Shape<double, 1>;
     static constexpr const char *kName = "gcr_update";
     static constexpr int NDOT = 1;
-    double *x;
+    double *xacc;
     double *r;
-    GcrBlocks b;
+    const double *z;
+    const double *w;
+    double *zslot;
+    double *wslot;
+    int32_t ndirs;
+    int32_t col;
     Ctl *ctl;
     struct Lane {
         bool on;
-        bool act[S::VW];
-        double gamma[S::VW];
-        double *zs[S::VW];
-        double *ws[S::VW];
+        double gamma;
     };
-    __device__ Lane lane(int g) const
+    __device__ Lane lane(int) const { return {true, ctl->gamma[col]}; }
+    __device__ __forceinline__ void row(const Lane &ln, int32_t i, int, Acc<double, 1, NDOT> &acc) const
     {
-        Lane ln;
-        const RunLane<double, M> rl = inner_done_lane<M>(ctl, g);
-        ln.on = rl.on;
-#pragma unroll
-        for (int q = 0; q < S::VW; ++q) {
-            const int c = g * S::VW + q;
-            ln.act[q] = rl.act[q];
-            ln.gamma[q] = ctl->gamma[c];
-            const int k = ctl->kcol[c];
-            ln.zs[q] = b.z[k];
-            ln.ws[q] = b.w[k];
-        }
-        return ln;
-    }
-    __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, Acc<double, S::VW, NDOT> &acc) const
-    {
-        const size_t o = static_cast<size_t>(i) * M + g * S::VW;
-        double xx[S::VW], rr[S::VW], zz[S::VW], ww[S::VW];
-        ld<double, M>(x, i, g, xx);
-        ld<double, M>(r, i, g, rr);
-        ld<double, M>(b.znew, i, g, zz);
-        ld<double, M>(b.wnew, i, g, ww);
-#pragma unroll
-        for (int q = 0; q < S::VW; ++q) {
-            if (ln.act[q]) {
-                xx[q] += ln.gamma[q] * zz[q];
-                rr[q] -= ln.gamma[q] * ww[q];
-                acc.a[0][q] += rr[q] * rr[q];
-                __builtin_nontemporal_store(zz[q], ln.zs[q] + o + q);
-                __builtin_nontemporal_store(ww[q], ln.ws[q] + o + q);
-            }
-        }
-        st<double, M>(x, i, g, xx);
-        st<double, M>(r, i, g, rr);
+        const double zi = z[i], wi = w[i];
+        const double ri = r[i] - ln.gamma * wi;
+        __builtin_nontemporal_store(xacc[i] + ln.gamma * zi, xacc + i);
+        __builtin_nontemporal_store(ri, r + i);
+        __builtin_nontemporal_store(zi, zslot + i);
+        __builtin_nontemporal_store(wi, wslot + i);
+        acc.a[0][0] += ri * ri;
     }
     __device__ void finish(const double *tot) const
     {
-        const int c = threadIdx.x;
-        if (c >= M || ctl->status[c] != COL_INNER_DONE)
+        if (threadIdx.x != 0)
             return;
+        const int c = col;
         Ctl &k = *ctl;
         const int slot = k.kcol[c];
         k.wnorm2[slot][c] = k.wnew2[c];
-        k.kcol[c] = (slot + 1) % b.ndirs;
-        const double nr = sqrt(tot[c]);
+        k.kcol[c] = (slot + 1) % ndirs;
+        const double nr = sqrt(tot[0]);
         k.total_iters[c] += k.iters[c];
         k.iters[c] = 0;
         k.outer[c] += 1;
@@ -1160,6 +1116,54 @@ struct OpGcrUpdate {
             k.status[c] = COL_OUTER;
         }
     }
+};
+
+// X(:, c) += x_acc(:, c) and x_acc(:, c) = 0 (FOLD), or x_acc(:, c) = 0
+// (ZERO), for the columns in cmask.
+enum FoldKind : int32_t { FOLD_ADD = 0, FOLD_ZERO = 1 };
+
+template <int M>
+struct OpFold {
+    using S = Shape<double, M>;
+    static constexpr const char *kName = "fold";
+    static constexpr int NDOT = 0;
+    double *X;
+    double *xacc;
+    int32_t n;
+    int32_t kind;
+    uint32_t cmask;
+    struct Lane {
+        bool on;
+        bool act[S::VW];
+    };
+    __device__ Lane lane(int g) const
+    {
+        Lane ln;
+        ln.on = false;
+#pragma unroll
+        for (int q = 0; q < S::VW; ++q) {
+            const int c = g * S::VW + q;
+            ln.act[q] = c < M && ((cmask >> c) & 1u);
+            ln.on = ln.on || ln.act[q];
+        }
+        return ln;
+    }
+    __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, Acc<double, S::VW, NDOT> &) const
+    {
+#pragma unroll
+        for (int q = 0; q < S::VW; ++q) {
+            if (!ln.act[q])
+                continue;
+            const int c = g * S::VW + q;
+            double *a = xacc + static_cast<size_t>(c) * n + i;
+            if (kind == FOLD_ADD) {
+                double *xp = X + static_cast<size_t>(i) * M + c;
+                *xp = *xp + *a;
+            }
+            *a = 0.0;
+        }
+    }
+    __device__ void finish(const double *) const {}
 };
 
 // Admission of columns into a block: reset their control state.

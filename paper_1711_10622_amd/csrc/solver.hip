@@ -44,6 +44,8 @@ struct Layout {
     size_t z[kGcrMax];  // stored directions z_j           (mixed)
     size_t w[kGcrMax];  // and w_j = A z_j                 (mixed)
     size_t znew, wnew;  // the direction being formed      (mixed)
+    size_t xacc;        // accumulated correction of x      (mixed)
+    // (the mixed-precision binary64 buffers are column-major, one n-vector per column)
     size_t v32[5];      // r, p, v, t, y                   (mixed, binary32)
     size_t sgn32;       // sign bits of the inner shadow residual (mixed)
     size_t total;
@@ -75,6 +77,7 @@ Layout layout(int32_t n, int32_t m, uint32_t flags)
         }
         L.znew = take(blk64);
         L.wnew = take(blk64);
+        L.xacc = take(blk64);
         for (int i = 0; i < 5; ++i)
             L.v32[i] = take(blk32);
         L.sgn32 = take(static_cast<size_t>(n) * kMaxM);  // n x (lanes per row <= 16) bytes
@@ -180,6 +183,8 @@ struct Steps {
     }
     static hipError_t finish(Ctx &c, uint32_t cmask, bool mixed, bool nullspace)
     {
+        if (mixed)  // the accumulated corrections into X
+            MRHS_TRY((launch_stream<double, M>(c.n, OpFold<M>{c.X, c.gcr.xacc, c.n, FOLD_ADD, cmask}, c.rb64, c.s)));
         MRHS_TRY((launch_stream<double, M>(
             c.n, OpScale<M>{c.X, c.A->diag, c.A->dinv, c.ctl, mixed ? SC_FIX_ZERO : SC_OUT, cmask}, c.rb64, c.s)));
         if (nullspace) {
@@ -196,31 +201,60 @@ struct Steps {
         if (!x0)
             MRHS_TRY((launch_stream<double, M>(
                 c.n, OpScale<M>{c.X, c.A->diag, c.A->dinv, c.ctl, SC_ZERO, cmask}, c.rb64, c.s)));
+        MRHS_TRY((launch_stream<double, M>(c.n, OpFold<M>{c.X, c.gcr.xacc, c.n, FOLD_ZERO, cmask}, c.rb64, c.s)));
         return launch_gspmv<double, M>(view<double>(*c.A, false),
-                                       OpResid<M>{c.X, c.B, c.r64, nullptr, nullptr, c.ctl, c.kry64, RES_SETUP, 0u},
+                                       OpResid<M>{c.X, c.B, c.r64, nullptr, nullptr, c.ctl, c.kry64, RES_SETUP, 0u, c.n},
                                        c.rb64, c.s);
     }
-    // one refinement step for every column whose inner solve ended
-    static hipError_t mixed_step(Ctx &c)
+    // one refinement step for each column of cmask (their inner solves ended);
+    // jmax[c]: directions the column has stored, slot[c]: the slot its new
+    // direction goes to (the device's kcol[c], which every step advances)
+    static hipError_t mixed_step(Ctx &c, uint32_t cmask, const int32_t *jmax, const int32_t *slot)
     {
-        MRHS_TRY((launch_stream<double, M>(c.n, OpGcrZ<M>{c.gcr.znew, c.y32, c.A->dinv, c.ctl}, c.rb64, c.s)));
-        MRHS_TRY((launch_gspmv<double, M>(view<double>(*c.A, false), OpStore<double, M>{c.gcr.znew, c.gcr.wnew},
-                                           c.rb64, c.s)));
-        if (c.gcr.jmax > 0)
-            MRHS_TRY((launch_stream<double, M>(c.n, OpGcrDots<M>{c.gcr, c.ctl}, c.rb64, c.s)));
-        MRHS_TRY((launch_stream<double, M>(c.n, OpGcrOrth<M>{c.gcr, c.r64, c.ctl}, c.rb64, c.s)));
-        return launch_stream<double, M>(c.n, OpGcrUpdate<M>{c.X, c.r64, c.gcr, c.ctl}, c.rb64, c.s);
+        MRHS_TRY((launch_stream<float, M>(c.n, OpGcrZ<M>{c.gcr.znew, c.y32, c.A->dinv, c.ctl, c.n}, c.rb32, c.s)));
+        const CsrView<double> A = view<double>(*c.A, false);
+        const size_t n = static_cast<size_t>(c.n);
+        for (int col = 0; col < M; ++col) {
+            if (!((cmask >> col) & 1u))
+                continue;
+            const size_t off = static_cast<size_t>(col) * n;
+            double *z = c.gcr.znew + off, *w = c.gcr.wnew + off, *r = c.r64 + off;
+            MRHS_TRY((launch_gspmv<double, 1>(A, OpStore<double, 1>{z, w}, c.rb64, c.s)));
+            OpColDots dots{};
+            OpColOrth orth{};
+            for (int j = 0; j < kGcrMax; ++j) {
+                const bool have = j < c.gcr.ndirs;
+                dots.W[j] = orth.W[j] = have ? c.gcr.w[j] + off : nullptr;
+                orth.Z[j] = have ? c.gcr.z[j] + off : nullptr;
+            }
+            dots.w = w;
+            dots.jmax = orth.jmax = jmax[col];
+            dots.col = orth.col = col;
+            dots.ctl = orth.ctl = c.ctl;
+            orth.w = w;
+            orth.z = z;
+            orth.r = r;
+            if (jmax[col] > 0)
+                MRHS_TRY((launch_stream<double, 1>(c.n, dots, c.rb64, c.s)));
+            MRHS_TRY((launch_stream<double, 1>(c.n, orth, c.rb64, c.s)));
+            const OpColUpdate upd{c.gcr.xacc + off, r, z, w, c.gcr.z[slot[col]] + off, c.gcr.w[slot[col]] + off,
+                                  c.gcr.ndirs, col, c.ctl};
+            MRHS_TRY((launch_stream<double, 1>(c.n, upd, c.rb64, c.s)));
+        }
+        return hipSuccess;
     }
     // true residual of columns whose refinement residual met the tolerance
-    static hipError_t mixed_check(Ctx &c)
+    // (their accumulated corrections are folded into X first)
+    static hipError_t mixed_check(Ctx &c, uint32_t pend)
     {
+        MRHS_TRY((launch_stream<double, M>(c.n, OpFold<M>{c.X, c.gcr.xacc, c.n, FOLD_ADD, pend}, c.rb64, c.s)));
         return launch_gspmv<double, M>(view<double>(*c.A, false),
-                                       OpResid<M>{c.X, c.B, c.r64, nullptr, nullptr, c.ctl, c.kry64, RES_MIXCHECK, 0u},
+                                       OpResid<M>{c.X, c.B, c.r64, nullptr, nullptr, c.ctl, c.kry64, RES_MIXCHECK, 0u, c.n},
                                        c.rb64, c.s);
     }
     static hipError_t mixed_cast(Ctx &c)
     {
-        return launch_stream<float, M>(c.n, OpCast<M>{c.r64, c.r32, c.sgn32, c.y32, c.p32, c.ctl, c.kry32}, c.rb32,
+        return launch_stream<float, M>(c.n, OpCast<M>{c.r64, c.r32, c.sgn32, c.y32, c.p32, c.ctl, c.kry32, c.n}, c.rb32,
                                        c.s);
     }
     static hipError_t inner_iterate(Ctx &c, int k)
@@ -305,8 +339,8 @@ Engine::Engine(const mrhs_csr_s &A, int m, uint32_t flags, void *ws, const doubl
         }
         c_.gcr.znew = reinterpret_cast<double *>(base + L.znew);
         c_.gcr.wnew = reinterpret_cast<double *>(base + L.wnew);
+        c_.gcr.xacc = reinterpret_cast<double *>(base + L.xacc);
         c_.gcr.ndirs = ndirs_;
-        c_.gcr.jmax = 0;
         float **v32[5] = {&c_.r32, &c_.p32, &c_.v32, &c_.t32, &c_.y32};
         for (int i = 0; i < 5; ++i)
             *v32[i] = reinterpret_cast<float *>(base + L.v32[i]);
@@ -320,8 +354,8 @@ Engine::Engine(const mrhs_csr_s &A, int m, uint32_t flags, void *ws, const doubl
     tol_in_ = env_double("MRHS_INNER_TOL", 0.1);
     max_outer_ = env_int("MRHS_MAX_OUTER", 500, 1, 100000);
     outer_batch_ = env_double("MRHS_OUTER_BATCH", 1.0);
-    outer_wait_ = env_int("MRHS_OUTER_WAIT", 8, 0, 100000);
-    mixed_chunk_ = env_int("MRHS_MIXED_POLL", 8, 1, 1024);
+    outer_wait_ = env_int("MRHS_OUTER_WAIT", 0, 0, 100000);
+    mixed_chunk_ = env_int("MRHS_MIXED_POLL", 4, 1, 1024);
 }
 
 Engine::~Engine()
@@ -339,9 +373,9 @@ mrhs_status Engine::reset()
         host_ = static_cast<Ctl *>(q);
     }
     std::memset(host_, 0, sizeof(Ctl));
-    gcr_steps_ = 0;
+    for (int c = 0; c < kMaxM; ++c)
+        col_steps_[c] = 0;
     waited_ = 0;
-    c_.gcr.jmax = 0;
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s_, tickets_, kGroups + 1, 0u);
     hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, s_, c_.ctl, mixed_ ? MODE_INNER : MODE_F64, tol_in_,
                        max_outer_, A_.n);
@@ -357,6 +391,9 @@ mrhs_status Engine::start(uint32_t cmask, const double *tol, const int32_t *maxi
         si.maxit[c] = c < m_ ? maxit[c] : 1;
     }
     cmask &= (1u << m_) - 1u;
+    for (int c = 0; c < m_; ++c)
+        if ((cmask >> c) & 1u)
+            col_steps_[c] = 0;  // the device resets kcol[c] to slot 0
     hipLaunchKernelGGL(k_slot_init, dim3(1), dim3(64), 0, s_, c_.ctl, cmask, si);
     MRHS_HIP(hipGetLastError());
     MRHS_HIP(mixed_ ? T_->mixed_start(c_, cmask, x0) : T_->f64_start(c_, cmask, x0));
@@ -410,19 +447,33 @@ mrhs_status Engine::advance(bool *busy)
         MRHS_HIP(T_->f64_iterate(c_, chunk_));
         return MRHS_OK;
     }
+    uint32_t pend_mask = 0, done_mask = 0;
+    for (int c = 0; c < m_; ++c) {
+        const int32_t s = host_->status[c];
+        if (s == COL_PEND_CHECK || s == COL_PEND_BD)
+            pend_mask |= 1u << c;
+        if (s == COL_INNER_DONE)
+            done_mask |= 1u << c;
+    }
     if (pend)
-        MRHS_HIP(T_->mixed_check(c_));
-    // A refinement step streams every row of the block whatever the number
-    // of columns it serves (a row of the block is one or two cache lines), so
-    // columns whose inner solve ended wait, idle, until they are a share
-    // outer_batch_ of the active columns, nothing else runs, or the first of
-    // them has waited outer_wait_ iterations.  A column's arithmetic does not
-    // depend on when its step comes.
+        MRHS_HIP(T_->mixed_check(c_, pend_mask));
+    // Refinement steps are per column (column-major vectors), but the z
+    // formation and the cast back to binary32 pass over the row-interleaved
+    // blocks once per round; columns whose inner solve ended may wait for a
+    // share outer_batch_ of the active columns, nothing else running, or
+    // outer_wait_ iterations.  A column's arithmetic does not depend on when
+    // its step comes.
     if (done_in) {
         if (run == 0 || done_in >= outer_batch_ * (run + done_in) || waited_ >= outer_wait_) {
-            MRHS_HIP(T_->mixed_step(c_));
-            ++gcr_steps_;
-            c_.gcr.jmax = std::min(gcr_steps_, ndirs_);
+            int32_t jmax[kMaxM], slot[kMaxM];
+            for (int c = 0; c < kMaxM; ++c) {
+                jmax[c] = std::min(col_steps_[c], ndirs_);
+                slot[c] = col_steps_[c] % ndirs_;
+            }
+            MRHS_HIP(T_->mixed_step(c_, done_mask, jmax, slot));
+            for (int c = 0; c < m_; ++c)
+                if ((done_mask >> c) & 1u)
+                    ++col_steps_[c];
             waited_ = 0;
         } else {
             waited_ += mixed_chunk_;
