@@ -209,6 +209,7 @@ class Engine {
     double outer_batch_ = 1.0;  // share of a block's active columns that triggers a refinement step
     int outer_wait_ = 0;        // ... or this many iterations waited by a column, whichever first
     int mixed_chunk_ = 4;       // inner iterations between polls (mixed precision)
+    int stag_window_ = kStagWindow;
     int waited_ = 0;
 };
 

@@ -32,8 +32,10 @@
 //   * maxit iterations end the column (restarts count toward maxit).
 // The inner solve of mixed-precision refinement runs the same iteration in
 // binary32 without restarts; it ends on its relative tolerance, on a
-// breakdown, on stagnation (no halving of ||r|| over kStagWindow
-// iterations) or on its iteration budget.
+// breakdown, on stagnation (no halving of ||r|| over stag_window iterations,
+// 80 by default: shorter windows end inner solves that are still converging,
+// 50 cost 13 % more time on the 256x192x256 channel) or on its iteration
+// budget.
 #pragma once
 
 #include "core.h"
@@ -60,7 +62,7 @@ enum SolveMode : int32_t { MODE_F64 = 0, MODE_INNER = 1 };
 
 constexpr int kMaxBreakdownRestarts = 3;
 constexpr int kGcrMax = 8;  // stored refinement directions (mixed precision)
-constexpr int kStagWindow = 50;
+constexpr int kStagWindow = 80;  // default of Ctl::stag_window
 
 struct Ctl {
     int32_t status[kMaxM];
@@ -91,7 +93,7 @@ struct Ctl {
     int32_t mode;
     int32_t max_outer;
     int32_t n;
-    int32_t pad_;
+    int32_t stag_window;  // mixed: inner iterations over which ||r|| must halve
 };
 
 template <typename T>
@@ -652,7 +654,7 @@ struct OpXR {
         } else if (inner) {
             if (k.iters[c] >= k.inner_maxit[c]) {
                 k.status[c] = COL_INNER_DONE;
-            } else if (k.iters[c] - k.stag_it[c] >= kStagWindow) {
+            } else if (k.iters[c] - k.stag_it[c] >= k.stag_window) {
                 if (rn > 0.5 * k.stag_rn[c])
                     k.status[c] = COL_INNER_DONE;
                 k.stag_it[c] = k.iters[c];

@@ -131,7 +131,8 @@ __global__ void k_slot_init(Ctl *ctl, uint32_t cmask, SlotInit si)
     }
 }
 
-__global__ void k_ctl_reset(Ctl *ctl, int32_t mode, double tol_in, int32_t max_outer, int32_t n)
+__global__ void k_ctl_reset(Ctl *ctl, int32_t mode, double tol_in, int32_t max_outer, int32_t n,
+                            int32_t stag_window)
 {
     if (threadIdx.x == 0) {
         Ctl &k = *ctl;
@@ -141,6 +142,7 @@ __global__ void k_ctl_reset(Ctl *ctl, int32_t mode, double tol_in, int32_t max_o
         k.tol_in = tol_in;
         k.max_outer = max_outer;
         k.n = n;
+        k.stag_window = stag_window;
     }
 }
 
@@ -356,6 +358,7 @@ Engine::Engine(const mrhs_csr_s &A, int m, uint32_t flags, void *ws, const doubl
     outer_batch_ = env_double("MRHS_OUTER_BATCH", 1.0);
     outer_wait_ = env_int("MRHS_OUTER_WAIT", 0, 0, 100000);
     mixed_chunk_ = env_int("MRHS_MIXED_POLL", 4, 1, 1024);
+    stag_window_ = env_int("MRHS_STAG_WINDOW", kStagWindow, 4, 100000);
 }
 
 Engine::~Engine()
@@ -378,7 +381,7 @@ mrhs_status Engine::reset()
     waited_ = 0;
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s_, tickets_, kGroups + 1, 0u);
     hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, s_, c_.ctl, mixed_ ? MODE_INNER : MODE_F64, tol_in_,
-                       max_outer_, A_.n);
+                       max_outer_, A_.n, stag_window_);
     MRHS_HIP(hipGetLastError());
     return MRHS_OK;
 }
