@@ -96,7 +96,6 @@ struct Vec;
 template <typename T>
 struct Vec<T, 1> {
     static __device__ __forceinline__ void load(const T *p, T *v) { v[0] = *p; }
-    static __device__ __forceinline__ void load_nt(const T *p, T *v) { v[0] = __builtin_nontemporal_load(p); }
     static __device__ __forceinline__ void store(T *p, const T *v) { *p = v[0]; }
     static __device__ __forceinline__ void store_nt(T *p, const T *v) { __builtin_nontemporal_store(v[0], p); }
 };
@@ -107,12 +106,6 @@ struct Vec<double, 2> {
     static __device__ __forceinline__ void load(const double *p, double *v)
     {
         v2 t = *reinterpret_cast<const v2 *>(p);
-        v[0] = t.x;
-        v[1] = t.y;
-    }
-    static __device__ __forceinline__ void load_nt(const double *p, double *v)
-    {
-        v2 t = __builtin_nontemporal_load(reinterpret_cast<const v2 *>(p));
         v[0] = t.x;
         v[1] = t.y;
     }
@@ -141,12 +134,6 @@ struct Vec<float, 2> {
         v[0] = t.x;
         v[1] = t.y;
     }
-    static __device__ __forceinline__ void load_nt(const float *p, float *v)
-    {
-        v2 t = __builtin_nontemporal_load(reinterpret_cast<const v2 *>(p));
-        v[0] = t.x;
-        v[1] = t.y;
-    }
     static __device__ __forceinline__ void store(float *p, const float *v)
     {
         v2 t;
@@ -169,14 +156,6 @@ struct Vec<float, 4> {
     static __device__ __forceinline__ void load(const float *p, float *v)
     {
         v4 t = *reinterpret_cast<const v4 *>(p);
-        v[0] = t.x;
-        v[1] = t.y;
-        v[2] = t.z;
-        v[3] = t.w;
-    }
-    static __device__ __forceinline__ void load_nt(const float *p, float *v)
-    {
-        v4 t = __builtin_nontemporal_load(reinterpret_cast<const v4 *>(p));
         v[0] = t.x;
         v[1] = t.y;
         v[2] = t.z;
@@ -278,18 +257,6 @@ __device__ __forceinline__ void st(T *base, int32_t row, int g, const T *v)
     }
 }
 
-// Address of element (row, col0) of an n x M row-interleaved block.
-template <typename T, int M>
-__device__ __forceinline__ const T *blk(const T *base, int32_t row, int col0)
-{
-    return base + static_cast<size_t>(row) * M + col0;
-}
-
-template <typename T, int M>
-__device__ __forceinline__ T *blk(T *base, int32_t row, int col0)
-{
-    return const_cast<T *>(blk<T, M>(const_cast<const T *>(base), row, col0));
-}
 
 // 32-byte lanes: two 16-byte accesses
 
