@@ -14,6 +14,9 @@
 // tiles, group x owns the x-th eighth of every plane and walks the planes in
 // order, so the rows a tile gathers from the planes before and after it were
 // fetched into the same XCD's L2 by the tiles just before and just after it.
+// Wide blocks make a group's eighth of a plane too large for its L2 to keep
+// two of them; then every plane is cut into C chunks and the planes are
+// walked C times, once per chunk.
 //
 // Lane layout for an n x M row-interleaved block.  Each lane handles VW
 // consecutive columns of one row (VW elements = one 16-byte access when M is
@@ -47,6 +50,9 @@ namespace mrhs {
 #endif
 #ifndef MRHS_GATHER_BATCH
 #define MRHS_GATHER_BATCH 7  // one batch covers a 7-point stencil row
+#endif
+#ifndef MRHS_PLANE_CHUNKS
+#define MRHS_PLANE_CHUNKS 0  // 0: chosen per product from its block bytes per tile
 #endif
 #ifndef MRHS_XCD_GROUPS
 #define MRHS_XCD_GROUPS 1
@@ -262,33 +268,44 @@ __device__ __forceinline__ void st(T *base, int32_t row, int g, const T *v)
 
 // ---- tile schedule ------------------------------------------------------------
 // Steps s = first, first + stride, ... < end of this workgroup; step s is
-// tile s (contiguous mode, P = 0) or, in plane mode, tile
-// (s / cg) * P + lo + s % cg, which may fall past the last tile in the
-// final, partial plane (then it is skipped).
+// tile s (contiguous mode, P = 0) or, in plane mode with chunks of W = P / C
+// tiles and sc = planes * cg steps per chunk, tile
+// (s / sc) * W + (t / cg) * P + lo + t % cg with t = s % sc, which may fall
+// past the last tile in the final, partial plane (then it is skipped).
 struct TileRange {
     int32_t first, end, stride;
     int32_t P, lo, cg;
-    __device__ __forceinline__ int32_t tile(int32_t s) const { return P ? (s / cg) * P + lo + s % cg : s; }
+    int32_t W, sc;  // chunk width in tiles, steps per chunk
+    __device__ __forceinline__ int32_t tile(int32_t s) const
+    {
+        if (!P)
+            return s;
+        const int32_t c = s / sc, t = s - c * sc;
+        return c * W + (t / cg) * P + lo + t % cg;
+    }
 };
 
-__device__ __forceinline__ TileRange tile_range(int32_t ntiles, int32_t P = 0)
+__device__ __forceinline__ TileRange tile_range(int32_t ntiles, int32_t P = 0, int32_t C = 1)
 {
 #if !MRHS_XCD_GROUPS
-    return {static_cast<int32_t>(blockIdx.x), ntiles, static_cast<int32_t>(gridDim.x), 0, 0, 1};
+    return {static_cast<int32_t>(blockIdx.x), ntiles, static_cast<int32_t>(gridDim.x), 0, 0, 1, 1, 1};
 #endif
     const int b = blockIdx.x;
     const int grp = b % kGroups;
     const int q = b / kGroups;
     const int gx = gridDim.x / kGroups;
     if (P) {
-        const int32_t lo = P * grp / kGroups;
-        const int32_t cg = P * (grp + 1) / kGroups - lo;
+        if (P % C != 0 || P / C < 2 * kGroups)
+            C = 1;
+        const int32_t W = P / C;
+        const int32_t lo = W * grp / kGroups;
+        const int32_t cg = W * (grp + 1) / kGroups - lo;
         const int32_t planes = (ntiles + P - 1) / P;
-        return {q, planes * cg, gx, P, lo, cg};
+        return {q, C * planes * cg, gx, P, lo, cg, W, planes * cg};
     }
     const int32_t lo = static_cast<int32_t>(static_cast<int64_t>(ntiles) * grp / kGroups);
     const int32_t hi = static_cast<int32_t>(static_cast<int64_t>(ntiles) * (grp + 1) / kGroups);
-    return {lo + q, hi, gx, 0, 0, 1};
+    return {lo + q, hi, gx, 0, 0, 1, 1, 1};
 }
 
 // Tiles per plane for the plane-interleaved schedule of a product, or 0 for
@@ -300,6 +317,41 @@ __device__ __forceinline__ int32_t plane_tiles(int32_t reach, int32_t tile_rows,
 {
     const int32_t P = (reach + tile_rows / 2) / tile_rows;
     return (P >= 2 * kGroups && ntiles >= 4 * P) ? P : 0;
+}
+
+// Chunks per plane: a row gathers from the plane before and the plane after
+// its own, so a group's block rows must stay in its L2 while it works through
+// about two of its plane shares.  Splitting every plane into C chunks, swept
+// one chunk at a time through all planes, divides that share by C.  C is the
+// smallest divisor of P that brings the share's block bytes under
+// kPlaneShareBytes while leaving at least kMinChunkTiles tiles per chunk, and
+// 1 when there is none or when the reach is not a whole number of tiles
+// (measured on the 12.6M-row channel: binary64 m = 16 +8 %, m = 8 +2 % with
+// whole-tile planes; 4-9 % slower at m = 7, 9, 10, 11, whose 240- and 252-row
+// tiles split a plane).
+#ifndef MRHS_PLANE_SHARE_KB
+#define MRHS_PLANE_SHARE_KB 700
+#endif
+#ifndef MRHS_PLANE_MIN_CHUNK
+#define MRHS_PLANE_MIN_CHUNK 16
+#endif
+constexpr int32_t kPlaneShareBytes = MRHS_PLANE_SHARE_KB << 10;
+constexpr int32_t kMinChunkTiles = MRHS_PLANE_MIN_CHUNK;
+
+__device__ __forceinline__ int32_t plane_chunks(int32_t P, int32_t reach, int32_t tile_rows,
+                                                int32_t block_bytes_per_tile)
+{
+#if MRHS_PLANE_CHUNKS
+    return MRHS_PLANE_CHUNKS;
+#endif
+    if (!P || reach % tile_rows != 0)
+        return 1;
+    const int64_t share = static_cast<int64_t>((P + kGroups - 1) / kGroups) * block_bytes_per_tile;
+    for (int32_t C = static_cast<int32_t>((share + kPlaneShareBytes - 1) / kPlaneShareBytes);
+         C > 1 && P / C >= kMinChunkTiles; ++C)
+        if (P % C == 0)
+            return C;
+    return 1;
 }
 
 // ---- matrix view ----------------------------------------------------------------
@@ -378,7 +430,9 @@ __device__ __forceinline__ void gspmv_tiles(const CsrView<T> &A, const Op &op,
     const typename Op::Lane ln = op.lane(g < S::G ? g : 0);
     const bool lane_on = S::used(tid) && g < S::G && ln.on;
     const int32_t ntiles = static_cast<int32_t>((static_cast<int64_t>(A.n) + S::TR - 1) / S::TR);
-    const TileRange tr = tile_range(ntiles, plane_tiles(A.reach, S::TR, ntiles));
+    const int32_t P = plane_tiles(A.reach, S::TR, ntiles);
+    const TileRange tr = tile_range(ntiles, P,
+                                    plane_chunks(P, A.reach, S::TR, 2 * S::TR * M * static_cast<int32_t>(sizeof(T))));
     for (int32_t step = tr.first; step < tr.end; step += tr.stride) {
         const int32_t tile = tr.tile(step);
         if (tile >= ntiles)  // past the end of the last, partial plane

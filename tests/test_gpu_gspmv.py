@@ -186,6 +186,29 @@ def test_full_size_channel_f64(torch_cuda, mrhs, m):
     assert np.all(np.abs(Y - ref) <= 1e-13 * abs_bound(A, X))
 
 
+@pytest.mark.parametrize("dtype,m", [(np.float64, 8), (np.float64, 16), (np.float32, 16)])
+def test_plane_chunked_schedule(torch_cuda, mrhs, dtype, m):
+    """A channel with planes of 192 tiles of 256 rows: wide blocks make the
+    products sweep every plane in 2 (binary64 m = 8, binary32 m = 16) or 3
+    (binary64 m = 16) chunks.  The last plane is short of cells, so the final
+    plane of tiles is partial; every row is checked."""
+    solid = np.zeros((5, 192, 256), dtype=bool)
+    solid[4, 100:, :] = True
+    A = grids.channel7(256, 192, 5, beta=2.0, solid=solid)
+    assert A.n == 4 * 192 * 256 + 100 * 256
+    X = rng.rhs_block(A.n, m, 500 + m)
+    if dtype == np.float64:
+        Y = gpu_gspmv(mrhs, torch_cuda, A, X)
+        ref = oracle.gspmv(A, X)
+        assert np.all(np.abs(Y - ref) <= 1e-13 * abs_bound(A, X))
+    else:
+        X = round32(X)
+        A32 = f32_matrix(A)
+        Y = gpu_gspmv(mrhs, torch_cuda, A, X, dtype=np.float32)
+        ref = oracle.gspmv(A32, X)
+        assert np.all(np.abs(Y - ref) <= gamma(max_row_len(A), U32) * abs_bound(A32, X))
+
+
 def test_large_channel_sampled(torch_cuda, mrhs):
     """The 256x192x256 channel (12.6M rows, m = 16), on 20k sampled rows
     including the first and last tiles."""
