@@ -411,6 +411,16 @@ struct Acc {
     }
 };
 
+// Blocks a product gathers per entry (Op::GATHERED when the op defines it).
+template <class Op, class = void>
+struct gathered_blocks {
+    static constexpr int value = 1;
+};
+template <class Op>
+struct gathered_blocks<Op, std::void_t<decltype(Op::GATHERED)>> {
+    static constexpr int value = Op::GATHERED;
+};
+
 // Y-side of a generalized SpMV over every tile of this workgroup.  The
 // tile's row offsets, column indices and values are first staged in LDS with
 // coalesced streaming loads (one pass over HBM, no reuse in cache needed), then
@@ -431,8 +441,8 @@ __device__ __forceinline__ void gspmv_tiles(const CsrView<T> &A, const Op &op,
     const bool lane_on = S::used(tid) && g < S::G && ln.on;
     const int32_t ntiles = static_cast<int32_t>((static_cast<int64_t>(A.n) + S::TR - 1) / S::TR);
     const int32_t P = plane_tiles(A.reach, S::TR, ntiles);
-    const TileRange tr = tile_range(ntiles, P,
-                                    plane_chunks(P, A.reach, S::TR, 2 * S::TR * M * static_cast<int32_t>(sizeof(T))));
+    constexpr int32_t kBlockBytes = (gathered_blocks<Op>::value + 1) * S::TR * M * static_cast<int32_t>(sizeof(T));
+    const TileRange tr = tile_range(ntiles, P, plane_chunks(P, A.reach, S::TR, kBlockBytes));
     for (int32_t step = tr.first; step < tr.end; step += tr.stride) {
         const int32_t tile = tr.tile(step);
         if (tile >= ntiles)  // past the end of the last, partial plane

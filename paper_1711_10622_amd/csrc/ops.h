@@ -478,6 +478,10 @@ struct OpSpmv2 {
     static constexpr const char *kName = "spmv_omega";
     using S = Shape<T, M>;
     static constexpr int NDOT = 4;
+#ifndef MRHS_OMEGA_GATHERED
+#define MRHS_OMEGA_GATHERED 2
+#endif
+    static constexpr int GATHERED = MRHS_OMEGA_GATHERED;  // r and v
     const T *r;
     const T *v;
     const uint8_t *sgn;  // sign bits of the shadow residual, or null: generated

@@ -179,3 +179,29 @@ def test_channel_full_m16(torch_cuda, mrhs, mixed):
             # alone: 456-512 iterations for one column under three dot-product
             # orders in binary64 on the CPU, so two orders may differ by ~12%
             assert abs(infos[l]["iters"] - io[l]["iters"]) <= 0.15 * io[l]["iters"]
+
+
+@pytest.fixture(scope="module")
+def chunked_channel():
+    """A channel with planes of 192 tiles of 256 rows and a short last plane,
+    a mean-free block of 16 right-hand sides, and the oracle's solution of
+    the first column."""
+    solid = np.zeros((5, 192, 256), dtype=bool)
+    solid[4, 100:, :] = True
+    A = grids.channel7(256, 192, 5, beta=2.0, solid=solid)
+    B = mean_free(rng.rhs_block(A.n, 16, 1717))
+    Xo, _, _ = oracle.bicgstab(A, B[:, :1], tol=1e-10, threads=1, shadow_seed=SHADOW_SEED)
+    return A, B, Xo
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_chunked_channel_solve(torch_cuda, mrhs, chunked_channel, mixed):
+    """m = 16 on a matrix whose products sweep its planes in chunks (binary64
+    spmv_omega in 4, the other products in 2 or 3)."""
+    A, B, Xo = chunked_channel
+    X, infos, st = gpu_solve(mrhs, torch_cuda, A, B, tol=1e-10, maxit=20000, mixed=mixed)
+    assert st == 0, infos
+    rr = true_relres(A, X, B)
+    assert np.all(rr <= 1e-10), rr
+    err = np.linalg.norm(X[:, 0] - Xo[:, 0]) / np.linalg.norm(Xo[:, 0])
+    assert err <= 1e-5, err
