@@ -348,6 +348,33 @@ def copy_calibration():
     return 0
 
 
+def gspmv_only(name):
+    """Five GSpMV launches per case (binary64 and binary32, m = 8 and 16) on
+    one matrix, for counter runs under rocprofv3."""
+    import torch
+    import paper_1711_10622_amd as mrhs
+    from workloads import configs
+    mrhs.load(build_if_missing=False)
+    A = configs.MATRICES[name]()
+    M = mrhs.CsrMatrix.from_csr(A)
+    for dt in (torch.float64, torch.float32):
+        for m in (8, 16):
+            X = torch.empty((A.n, m), dtype=dt, device="cuda").uniform_(-1, 1)
+            Y = torch.empty_like(X)
+            M.gspmv(X, out=Y)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(True), torch.cuda.Event(True)
+            e0.record()
+            for _ in range(5):
+                M.gspmv(X, out=Y)
+            e1.record()
+            torch.cuda.synchronize()
+            log(f"gspmv {name} {str(dt)[6:]} m={m}: {e0.elapsed_time(e1) / 5 * 1e3:.1f} us")
+            del X, Y
+    M.close()
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -358,6 +385,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB copy (counter calibration under rocprofv3)")
+    ap.add_argument("--gspmv-only", metavar="MATRIX",
+                    help="run only five GSpMV launches per case on MATRIX (counter runs under rocprofv3)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -366,6 +395,8 @@ def main():
         return 2
     if args.copy_calibration:
         return copy_calibration()
+    if args.gspmv_only:
+        return gspmv_only(args.gspmv_only)
 
     import numpy as np
     import torch
