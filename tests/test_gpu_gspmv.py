@@ -221,3 +221,26 @@ def test_large_channel_sampled(torch_cuda, mrhs):
     ref = oracle.gspmv_rows(A, X, rows)
     bound = abs_bound(A, X, rows)
     assert np.all(np.abs(Y[rows] - ref) <= 1e-13 * bound)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_cube_full_sampled(torch_cuda, mrhs, dtype):
+    """The relabelled wall-mounted-cube channel (2.29M rows, random row order)
+    at m = 8, the case the mixed solve is measured on: 20k sampled rows plus
+    the first and last tiles."""
+    A = configs.MATRICES["cube192"]()
+    X = configs.WORKLOADS["cube192"].rhs(A.n, 8)
+    r = np.random.default_rng(1)
+    rows = np.unique(np.concatenate([np.arange(512), np.arange(A.n - 512, A.n),
+                                     r.integers(0, A.n, size=20000)]))
+    if dtype == np.float64:
+        Y = gpu_gspmv(mrhs, torch_cuda, A, X)
+        ref = oracle.gspmv_rows(A, X, rows)
+        assert np.all(np.abs(Y[rows] - ref) <= 1e-13 * abs_bound(A, X, rows))
+    else:
+        X = round32(X)
+        A32 = f32_matrix(A)
+        Y = gpu_gspmv(mrhs, torch_cuda, A, X, dtype=np.float32)
+        ref = oracle.gspmv_rows(A32, X, rows)
+        tol = gamma(max_row_len(A), U32) * abs_bound(A32, X, rows)
+        assert np.all(np.abs(Y[rows] - ref) <= tol)
