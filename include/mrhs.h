@@ -180,8 +180,11 @@ mrhs_status block_bicgstab_workspace_size(mrhs_csr A, int32_t m, uint32_t flags,
  *
  * Device memory is admitted against hbm_budget_bytes: registered matrices
  * (their csr_info device bytes) plus the engine of every matrix that has work
- * (its block workspace).  An idle matrix gives its engine memory back when
- * another matrix waits for budget.  All functions are thread-safe.
+ * (its block workspace).  Matrices waiting for engine memory get it in the
+ * order they asked; while one waits, the others admit no new columns, finish
+ * the ones in flight and give their engine memory back, so under a tight
+ * budget the matrices take turns, one batch at a time.  All functions are
+ * thread-safe.
  */
 #define MRHS_SERVER_MIXED 1u /* binary32 inner solves with binary64 refinement */
 
@@ -191,8 +194,10 @@ mrhs_status solve_server_create(size_t hbm_budget_bytes, uint32_t flags,
 
 /*
  * Make matrix A servable; *matrix_id names it in submits.  A must outlive
- * the server.  EBUDGET when A and its engine can never fit the budget;
- * EINVAL for an empty matrix or a zero diagonal entry.
+ * the server.  EBUDGET unless all registered matrices, A, and the largest
+ * engine among them (A's included) fit the budget together, which is what
+ * lets every matrix run once the other engines are released; EINVAL for an
+ * empty matrix or a zero diagonal entry.
  */
 mrhs_status solve_server_register(mrhs_server S, mrhs_csr A, int32_t *matrix_id);
 

@@ -6,8 +6,12 @@
 // overlap on the device.  A request's columns join the block as slots free
 // up, between rounds of iterations, and leave it as soon as they finish.
 // Device memory is admitted against a byte budget: a matrix's engine is
-// allocated when it has work and the budget allows, and released when idle
-// if another matrix is waiting for budget.
+// allocated when it has work and the budget allows.  Matrices waiting for
+// budget are served first come, first served; while one waits, every engine
+// stops admitting new columns, finishes the ones in flight and is released,
+// so a busy matrix cannot starve another.  Registration keeps every resident
+// matrix plus the largest engine within the budget, so each matrix's engine
+// fits once the others are released.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -78,6 +82,7 @@ struct Lane {
     std::deque<std::shared_ptr<Request>> queue;  // requests with columns still to admit
     std::thread th;
     bool has_engine = false;  // device memory currently held
+    bool fresh = false;       // engine just acquired: may admit one batch even while others wait
 };
 
 struct Server {
@@ -87,7 +92,8 @@ struct Server {
     size_t used = 0;  // resident matrices + live engines
     uint32_t flags = 0;
     bool shutdown = false;
-    int budget_waiters = 0;
+    size_t matrix_bytes = 0;                // resident matrices alone
+    std::deque<int32_t> budget_queue;       // lanes waiting for device memory, in order
     uint64_t next_ticket = 1;
     std::vector<std::unique_ptr<Lane>> lanes;
     std::map<uint64_t, std::shared_ptr<Request>> requests;
@@ -190,33 +196,38 @@ void lane_main(Lane *L)
             for (;;) {
                 if (S.shutdown)
                     break;
-                const bool work = active_count() > 0 || !L->queue.empty();
-                if (!work) {
-                    // idle: give the budget back if someone is waiting for it
-                    if (L->has_engine && S.budget_waiters > 0) {
-                        lk.unlock();
-                        em.release();
-                        lk.lock();
-                        L->has_engine = false;
-                        S.used -= L->engine_bytes;
-                        S.cv.notify_all();
-                    }
+                const int active = active_count();
+                // another matrix waits for device memory: hand this engine back
+                // as soon as none of its columns is in flight
+                if (L->has_engine && active == 0 && !S.budget_queue.empty()) {
+                    lk.unlock();
+                    em.release();
+                    lk.lock();
+                    L->has_engine = false;
+                    S.used -= L->engine_bytes;
+                    S.cv.notify_all();
+                    continue;
+                }
+                if (active == 0 && L->queue.empty()) {
                     S.cv.wait(lk);
                     continue;
                 }
                 if (!L->has_engine) {
-                    if (S.used + L->engine_bytes > S.budget) {
-                        ++S.budget_waiters;
-                        S.cv.notify_all();
+                    auto &q = S.budget_queue;
+                    if (std::find(q.begin(), q.end(), L->id) == q.end())
+                        q.push_back(L->id);
+                    if (q.front() != L->id || S.used + L->engine_bytes > S.budget) {
                         S.cv.wait(lk);
-                        --S.budget_waiters;
                         continue;
                     }
+                    q.pop_front();
                     S.used += L->engine_bytes;
                     L->has_engine = true;
+                    L->fresh = true;
                     lk.unlock();
                     const bool ok = alloc_engine(em, A, eflags);
                     lk.lock();
+                    S.cv.notify_all();  // the next in line may fit as well
                     if (!ok) {
                         L->has_engine = false;
                         S.used -= L->engine_bytes;
@@ -225,7 +236,6 @@ void lane_main(Lane *L)
                             for (int c = r->next_col; c < r->k; ++c)
                                 fail_request_col(S, r, c, MRHS_ENOMEM);
                         L->queue.clear();
-                        S.cv.notify_all();
                         continue;
                     }
                 }
@@ -233,8 +243,12 @@ void lane_main(Lane *L)
             }
             if (S.shutdown)
                 break;
-            // admit queued columns into free slots, oldest request first
-            for (int c = 0; c < kSlots && !L->queue.empty(); ++c) {
+            // admit queued columns into free slots, oldest request first; while
+            // another matrix waits for device memory, only the first batch
+            // after this engine was acquired (so every turn makes progress)
+            const bool may_admit = S.budget_queue.empty() || L->fresh;
+            L->fresh = false;
+            for (int c = 0; c < kSlots && !L->queue.empty() && may_admit; ++c) {
                 if (slots[c].req)
                     continue;
                 std::shared_ptr<Request> r = L->queue.front();
@@ -366,15 +380,23 @@ MRHS_API mrhs_status solve_server_register(mrhs_server srv, mrhs_csr A, int32_t 
     std::lock_guard<std::mutex> lk(S.mu);
     if (S.shutdown)
         return set_error(MRHS_ESHUTDOWN, "server is shutting down");
-    if (S.used + A->bytes + eb > S.budget)
-        return set_error(MRHS_EBUDGET, "matrix (%zu B) and its engine (%zu B) exceed the free budget (%zu of %zu B)",
-                         A->bytes, eb, S.budget - std::min(S.used, S.budget), S.budget);
+    // every resident matrix plus the largest engine must fit, so that each
+    // matrix can run once the other engines are released
+    size_t max_eb = eb;
+    for (auto &L : S.lanes)
+        max_eb = std::max(max_eb, L->engine_bytes);
+    if (S.matrix_bytes + A->bytes + max_eb > S.budget)
+        return set_error(MRHS_EBUDGET,
+                         "resident matrices (%zu B) plus this one (%zu B) and the largest engine (%zu B) "
+                         "exceed the budget (%zu B)",
+                         S.matrix_bytes, A->bytes, max_eb, S.budget);
     auto L = std::make_unique<Lane>();
     L->srv = &S;
     L->id = static_cast<int32_t>(S.lanes.size());
     L->A = A;
     L->engine_bytes = eb;
     S.used += A->bytes;
+    S.matrix_bytes += A->bytes;
     Lane *raw = L.get();
     S.lanes.push_back(std::move(L));
     raw->th = std::thread(lane_main, raw);

@@ -144,3 +144,54 @@ def test_budget_shared_between_matrices(mrhs, mats):
         assert st == 0, infs
     assert srv.stats()["admitted_bytes"] <= budget
     srv.close()
+
+
+def test_budget_registration_keeps_every_engine_feasible(mrhs, mats):
+    """A matrix is refused when the registered matrices plus the largest engine
+    of any of them would exceed the budget, even if its own engine would fit:
+    otherwise the larger engine could never be allocated again."""
+    As, Ms = mats
+    import paper_1711_10622_amd._lib as L
+    dev = {k: Ms[k].device_bytes() for k in ("dir12", "chan")}
+    eng = {k: Ms[k].workspace_size(16) + 3 * 8 * 16 * As[k].n for k in ("dir12", "chan")}
+    assert eng["chan"] > eng["dir12"]
+    budget = dev["chan"] + dev["dir12"] + eng["chan"] - 1
+    assert dev["chan"] + eng["chan"] <= budget and dev["chan"] + dev["dir12"] + eng["dir12"] <= budget
+    srv = mrhs.SolveServer(budget)
+    b = srv.register(Ms["chan"])
+    with pytest.raises(mrhs.MrhsError) as e:
+        srv.register(Ms["dir12"])
+    assert e.value.status == L.EBUDGET
+    _, infs, st = srv.wait(srv.submit(b, rhs_for(As["chan"], 2, 3), tol=1e-10), timeout=120)
+    assert st == 0, infs
+    srv.close()
+
+
+def test_budget_turns_no_starvation(mrhs, mats):
+    """With room for one engine, a matrix kept busy by a long stream of
+    requests yields its engine to a waiting matrix between batches: the
+    waiting request finishes while most of the stream is still queued."""
+    As, Ms = mats
+    dev = sum(Ms[k].device_bytes() for k in ("dir12", "chan"))
+    eng = max(Ms[k].workspace_size(16) + 3 * 8 * 16 * As[k].n for k in ("dir12", "chan"))
+    srv = mrhs.SolveServer(dev + eng + (1 << 20))
+    a = srv.register(Ms["dir12"])
+    b = srv.register(Ms["chan"])
+    stream = [srv.submit(a, rhs_for(As["dir12"], 16, 100 + i), tol=1e-10) for i in range(60)]
+    tb = srv.submit(b, rhs_for(As["chan"], 4, 7), tol=1e-10)
+    _, infs, st = srv.wait(tb, timeout=120)
+    assert st == 0, infs
+    pending = 0
+    done = []
+    for t in stream:
+        r = srv.poll(t)
+        if r is None:
+            pending += 1
+        else:
+            done.append(r)
+    assert pending >= 30, pending
+    for t in stream:
+        if srv._k.get(t) is not None:
+            done.append(srv.wait(t, timeout=120))
+    assert len(done) == 60 and all(st == 0 for _, _, st in done)
+    srv.close()
