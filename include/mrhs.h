@@ -117,7 +117,8 @@ mrhs_status csr_info(mrhs_csr A, int32_t *n, int64_t *nnz, size_t *device_bytes)
 /*
  * Y = A X (Section 2.3, Figure 1) for device blocks X, Y of m binary64
  * vectors on the null stream; returns when the product is enqueued.
- * EINVAL: m outside [1, 16], NULL pointers with n > 0, or X == Y.
+ * EINVAL: m outside [1, 16], NULL pointers with n > 0, or X and Y sharing
+ * any byte of their n x m blocks.
  */
 mrhs_status gspmv(mrhs_csr A, const double *X, double *Y, int32_t m);
 
@@ -155,7 +156,8 @@ mrhs_status block_bicgstab(mrhs_csr A, const double *B, double *X, int32_t m,
  * Full form.  flags: MRHS_X0_GIVEN, MRHS_MIXED.  workspace: device memory of
  * at least block_bicgstab_workspace_size() bytes owned by the caller, or NULL
  * to let the library allocate and free it.  info: host array of m entries or
- * NULL.  Blocks the calling thread until the solve is done.
+ * NULL.  Blocks the calling thread until the solve is done.  EINVAL when B
+ * and X, or the workspace and either of them, share any byte.
  */
 mrhs_status block_bicgstab_ex(mrhs_csr A, const double *B, double *X, int32_t m,
                               double tol, int32_t maxit, uint32_t flags,

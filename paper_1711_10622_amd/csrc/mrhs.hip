@@ -230,6 +230,13 @@ constexpr size_t kPad = 4;  // elements of padding after the nnz entries
 
 bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
+// Do the byte ranges [a, a + na) and [b, b + nb) share a byte?
+bool overlap(const void *a, size_t na, const void *b, size_t nb)
+{
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return na > 0 && nb > 0 && x < y + nb && y < x + na;
+}
+
 template <typename T>
 struct StoreLaunch {
     const mrhs_csr_s *A;
@@ -398,8 +405,9 @@ MRHS_API mrhs_status gspmv_ex(mrhs_csr A, int32_t dtype, const void *X, void *Y,
         return MRHS_OK;
     if (!X || !Y)
         return set_error(MRHS_EINVAL, "X or Y is NULL");
-    if (X == Y)
-        return set_error(MRHS_EINVAL, "X and Y must not alias");
+    const size_t blk = static_cast<size_t>(A->n) * m * (dtype == MRHS_F64 ? sizeof(double) : sizeof(float));
+    if (overlap(X, blk, Y, blk))
+        return set_error(MRHS_EINVAL, "X and Y overlap");
     if (!aligned16(X) || !aligned16(Y))
         return set_error(MRHS_EINVAL, "X and Y must be 16-byte aligned");
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
@@ -449,8 +457,11 @@ MRHS_API mrhs_status block_bicgstab_ex(mrhs_csr A, const double *B, double *X, i
     }
     if (!B || !X)
         return set_error(MRHS_EINVAL, "B or X is NULL");
-    if (static_cast<const void *>(B) == static_cast<const void *>(X))
-        return set_error(MRHS_EINVAL, "B and X must not alias");
+    const size_t blk = static_cast<size_t>(A->n) * m * sizeof(double);
+    if (overlap(B, blk, X, blk))
+        return set_error(MRHS_EINVAL, "B and X overlap");
+    if (workspace && (overlap(workspace, ws_bytes, B, blk) || overlap(workspace, ws_bytes, X, blk)))
+        return set_error(MRHS_EINVAL, "the workspace overlaps B or X");
     if (!aligned16(B) || !aligned16(X) || (workspace && !aligned16(workspace)))
         return set_error(MRHS_EINVAL, "B, X and the workspace must be 16-byte aligned");
     if (A->zero_diag)

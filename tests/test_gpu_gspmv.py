@@ -150,6 +150,11 @@ def test_argument_errors(torch_cuda, mrhs):
     assert lib.gspmv(M.handle, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(X.data_ptr()), 2) == L.EINVAL
     assert lib.gspmv(M.handle, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(X.data_ptr()), 17) == L.EINVAL
     assert lib.gspmv(M.handle, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(X.data_ptr()), 0) == L.EINVAL
+    # partial overlap: Y starts one row (16 bytes) into X
+    P = torch_cuda.zeros((A.n + 1) * 2, dtype=torch_cuda.float64, device="cuda")
+    p0 = P.data_ptr()
+    assert lib.gspmv(M.handle, ctypes.c_void_p(p0), ctypes.c_void_p(p0 + 16), 2) == L.EINVAL
+    assert lib.gspmv(M.handle, ctypes.c_void_p(p0 + 16), ctypes.c_void_p(p0), 2) == L.EINVAL
     E = mrhs.CsrMatrix(0, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0))
     assert lib.gspmv(E.handle, None, None, 4) == L.OK
     M.close()
