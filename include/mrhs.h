@@ -63,6 +63,7 @@ enum { MRHS_F64 = 0, MRHS_F32 = 1 };
 
 typedef struct mrhs_csr_s *mrhs_csr;
 typedef struct mrhs_server_s *mrhs_server;
+typedef struct mrhs_grid_s *mrhs_grid;
 
 /* Per-column outcome of a solve. */
 typedef struct {
@@ -230,6 +231,53 @@ mrhs_status solve_server_stats(mrhs_server S, mrhs_server_stats *out);
 /* Stop the serving threads (work in progress is abandoned) and free the
  * server.  NULL is accepted. */
 mrhs_status solve_server_destroy(mrhs_server S);
+
+/*
+ * Ensemble projection step (Section 2.2, eqs. (3)-(4)): m preliminary
+ * velocity fields u* on one staggered channel grid give m pressure
+ * right-hand sides, solved together by block_bicgstab, and the pressures
+ * correct the m fields to divergence-free ones.
+ *
+ * Grid: nx x ny x nz cells (x fastest), periodic in x and z, walls at the y
+ * faces y_faces[0] and y_faces[ny] (host array of ny + 1 strictly increasing
+ * coordinates), uniform spacings dx and dz, and optional solid cells
+ * (solid: host array of nx*ny*nz bytes, nonzero = solid, or NULL).  Fluid
+ * cells carry the pressure unknowns in natural order, as the matching
+ * channel pressure matrix numbers its rows: x-faces couple with dy_j dz / dx,
+ * y-faces with dx dz / (yc_j - yc_{j-1}), z-faces with dx dy_j / dz (yc the
+ * cell centres), so that D G = -A with D and G below.
+ *
+ * Face blocks (device, row-interleaved, rows x m binary64, 16-byte aligned):
+ *   U: nz*ny*nx rows, row (k*ny + j)*nx + i = x-face west of cell (i, j, k);
+ *   V: nz*(ny+1)*nx rows, row (k*(ny+1) + j)*nx + i = y-face below cell
+ *      (i, j, k), j = 0..ny (rows j = 0 and j = ny lie on the walls);
+ *   W: nz*ny*nx rows, row (k*ny + j)*nx + i = z-face behind cell (i, j, k).
+ * Faces on a wall or next to a solid cell are closed: no flux passes them,
+ * projection_rhs ignores their values and projection_correct leaves them.
+ * Cell blocks (B, P): n_fluid rows x m.  The blocks of one call must not
+ * share any byte (EINVAL).  Calls are enqueued on hip_stream (NULL = the
+ * null stream) and return at once.
+ */
+mrhs_status grid_create(int32_t nx, int32_t ny, int32_t nz, double dx, double dz,
+                        const double *y_faces, const uint8_t *solid, mrhs_grid *out);
+mrhs_status grid_destroy(mrhs_grid G);
+/* Fluid cells, all cells and y-face rows of the grid (NULL outputs skipped). */
+mrhs_status grid_info(mrhs_grid G, int32_t *n_fluid, int64_t *cells, int64_t *v_faces);
+
+/*
+ * B = -(1/tau) D(U, V, W) for m fields: D is the volume-integrated discrete
+ * divergence, sum over a fluid cell's open faces of area times the outward
+ * normal velocity.  tau = -1 gives D itself.  EINVAL for tau = 0.
+ */
+mrhs_status projection_rhs(mrhs_grid G, const double *U, const double *V, const double *W,
+                           double tau, double *B, int32_t m, void *hip_stream);
+
+/*
+ * U -= tau G P, V -= tau G P, W -= tau G P on every open face: the pressure
+ * difference across the face over the distance between the two cell centres.
+ */
+mrhs_status projection_correct(mrhs_grid G, double *U, double *V, double *W,
+                               const double *P, double tau, int32_t m, void *hip_stream);
 
 /*
  * Kernel timing.  mrhs_trace_enable(k), k >= 1, clears the statistics and

@@ -28,6 +28,7 @@ EXPORTS = (
     "block_bicgstab", "block_bicgstab_ex", "block_bicgstab_workspace_size",
     "solve_server_create", "solve_server_register", "solve_server_submit", "solve_server_poll",
     "solve_server_stats", "solve_server_destroy",
+    "grid_create", "grid_destroy", "grid_info", "projection_rhs", "projection_correct",
     "mrhs_trace_enable", "mrhs_trace_read",
 )
 
@@ -81,6 +82,11 @@ def _declare(lib):
         "solve_server_poll": [vp, c.c_uint64, vp, c.POINTER(ColInfo)],
         "solve_server_stats": [vp, c.POINTER(ServerStats)],
         "solve_server_destroy": [vp],
+        "grid_create": [i32, i32, i32, f64, f64, vp, vp, c.POINTER(vp)],
+        "grid_destroy": [vp],
+        "grid_info": [vp, c.POINTER(i32), c.POINTER(i64), c.POINTER(i64)],
+        "projection_rhs": [vp, vp, vp, vp, f64, vp, i32, vp],
+        "projection_correct": [vp, vp, vp, vp, vp, f64, i32, vp],
         "mrhs_trace_enable": [c.c_int],
         "mrhs_trace_read": [c.c_char_p, sz, c.POINTER(sz)],
     }

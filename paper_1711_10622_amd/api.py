@@ -247,3 +247,75 @@ class SolveServer:
             self.close()
         except Exception:
             pass
+
+
+class ChannelGrid:
+    """Staggered channel grid of the ensemble projection step (``grid_create``):
+    ``rhs`` gives the m pressure right-hand sides -(1/tau) D u*, ``correct``
+    applies u -= tau G p to the m fields in place."""
+
+    def __init__(self, nx, ny, nz, dx, dz, y_faces, solid=None):
+        lib = _lib.load()
+        self._lib = lib
+        yf = np.ascontiguousarray(y_faces, dtype=np.float64)
+        if yf.shape != (ny + 1,):
+            raise ValueError(f"y_faces must hold ny + 1 = {ny + 1} coordinates")
+        sd = None
+        if solid is not None:
+            sd = np.ascontiguousarray(solid, dtype=np.uint8)
+            if sd.size != nx * ny * nz:
+                raise ValueError("solid must hold nx*ny*nz cells")
+        h = ctypes.c_void_p()
+        _lib.check(lib.grid_create(int(nx), int(ny), int(nz), float(dx), float(dz), yf.ctypes.data,
+                                   sd.ctypes.data if sd is not None else None, ctypes.byref(h)), "grid_create")
+        self._h = h
+        n, cells, vf = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
+        _lib.check(lib.grid_info(h, ctypes.byref(n), ctypes.byref(cells), ctypes.byref(vf)), "grid_info")
+        self.n, self.cells, self.v_faces = n.value, cells.value, vf.value
+        self.shape = (int(nx), int(ny), int(nz))
+
+    def _faces(self, U, V, W):
+        torch = _torch()
+        m = 1 if U.dim() == 1 else int(U.shape[1])
+        return (m, _check_block(U, self.cells, m, torch.float64, "U"),
+                _check_block(V, self.v_faces, m, torch.float64, "V"),
+                _check_block(W, self.cells, m, torch.float64, "W"))
+
+    def rhs(self, U, V, W, tau, out=None, stream=None):
+        """-(1/tau) D(U, V, W) as an (n_fluid, m) block (``projection_rhs``)."""
+        torch = _torch()
+        m, U, V, W = self._faces(U, V, W)
+        if out is None:
+            out = torch.empty((self.n, m), dtype=torch.float64, device=U.device)
+        B = _check_block(out, self.n, m, torch.float64, "out")
+        _lib.check(self._lib.projection_rhs(self._h, ctypes.c_void_p(U.data_ptr()), ctypes.c_void_p(V.data_ptr()),
+                                            ctypes.c_void_p(W.data_ptr()), float(tau),
+                                            ctypes.c_void_p(B.data_ptr()), m, _stream_handle(stream)),
+                   "projection_rhs")
+        return out
+
+    def correct(self, U, V, W, P, tau, stream=None):
+        """U, V, W -= tau G P in place (``projection_correct``)."""
+        torch = _torch()
+        m, U, V, W = self._faces(U, V, W)
+        Pb = _check_block(P, self.n, m, torch.float64, "P")
+        _lib.check(self._lib.projection_correct(self._h, ctypes.c_void_p(U.data_ptr()),
+                                                ctypes.c_void_p(V.data_ptr()), ctypes.c_void_p(W.data_ptr()),
+                                                ctypes.c_void_p(Pb.data_ptr()), float(tau), m,
+                                                _stream_handle(stream)),
+                   "projection_correct")
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.grid_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
