@@ -162,6 +162,66 @@ def event_times_us(torch, fn, reps, warm, between=None):
     return np.array([a.elapsed_time(b) * 1e3 for a, b in ev])
 
 
+def projection_step(torch, ms=(1, 16), tau=0.05, reps=20):
+    """The ensemble projection step on the 128x64x64 channel (Section 2.2,
+    eqs. (3)-(4)): pressure right-hand sides, block solve to 1e-10,
+    correction, for m fields at once.  Kernel times from HIP events (median of
+    ``reps``) with their algorithmic bytes, the solve's share theta of the
+    step, and the whole-step gain m t_1 / t_m."""
+    import numpy as np
+    import paper_1711_10622_amd as mrhs
+    from paper_1711_10622_amd import estimates as est
+    from workloads import configs, staggered
+    nx, ny, nz = 128, 64, 64
+    geo = staggered.channel_geometry(nx, ny, nz)
+    G = mrhs.ChannelGrid(nx, ny, nz, geo["dx"], geo["dz"], geo["y_faces"])
+    M = mrhs.CsrMatrix.from_csr(configs.MATRICES["chan128"]())
+    out = {}
+    for m in ms:
+        U, V, W = (torch.from_numpy(a).cuda() for a in staggered.velocity_blocks(nx, ny, nz, m, 1716))
+        B = torch.empty((G.n, m), dtype=torch.float64, device="cuda")
+        P = torch.empty_like(B)
+        ws = torch.empty(M.workspace_size(m), dtype=torch.uint8, device="cuda")
+        U0, V0, W0 = U.clone(), V.clone(), W.clone()
+        t_rhs = float(np.median(event_times_us(torch, lambda: G.rhs(U, V, W, tau, out=B), reps, 3)))
+        t_cor = float(np.median(event_times_us(
+            torch, lambda: G.correct(U, V, W, P, tau), reps, 3,
+            between=lambda: (U.copy_(U0), V.copy_(V0), W.copy_(W0)))))
+        U.copy_(U0); V.copy_(V0); W.copy_(W0)
+        G.rhs(U, V, W, tau, out=B)
+        timed_solves(torch, M, B, P, ws, 1)  # warm-up
+        t_solve, infos, _ = timed_solves(torch, M, B, P, ws, 2)
+        t0 = time.perf_counter()
+        G.rhs(U, V, W, tau, out=B)
+        M.solve(B, tol=1e-10, out=P, workspace=ws)
+        G.correct(U, V, W, P, tau)
+        torch.cuda.synchronize()
+        t_step = time.perf_counter() - t0
+        S = 8 * m
+        rhs_bytes = S * (2 * G.cells + G.v_faces + G.n) + 4 * G.cells
+        cor_bytes = S * (G.n + 2 * (2 * G.cells + G.v_faces)) + 4 * G.cells
+        out[str(m)] = {
+            "rhs_us": round(t_rhs, 2), "rhs_GBps": round(rhs_bytes / t_rhs / 1e3, 1),
+            "correct_us": round(t_cor, 2), "correct_GBps": round(cor_bytes / t_cor / 1e3, 1),
+            "solve_ms": round(t_solve * 1e3, 3), "step_ms": round(t_step * 1e3, 3),
+            "theta_solve": round(t_solve / (t_solve + (t_rhs + t_cor) * 1e-6), 5),
+            "iters_max": max(i["iters"] for i in infos),
+        }
+        del U, V, W, U0, V0, W0, B, P, ws
+    if "1" in out:
+        # eq. est2_1 with measured inputs: the step gain predicted from the
+        # m = 1 solve share theta and the measured solve gain, beside the
+        # measured step gain
+        th = out["1"]["theta_solve"]
+        for k, v in out.items():
+            v["solve_gain_vs_m1"] = round(int(k) * out["1"]["solve_ms"] / v["solve_ms"], 3)
+            v["step_gain_vs_m1"] = round(int(k) * out["1"]["step_ms"] / v["step_ms"], 3)
+            v["est2_1_step_gain"] = round(est.step_gain(th, v["solve_gain_vs_m1"]), 3)
+    M.close()
+    G.close()
+    return out
+
+
 def gspmv_sweep(torch, A, ms, dtypes, flush=False, reps=50):
     import numpy as np
     import paper_1711_10622_amd as mrhs
@@ -486,6 +546,8 @@ def main():
         extra["gspmv_chan128"] = gspmv_sweep(torch, A, [1, 2, 4, 8, 16], ("f64",), flush=True)
         log("gspmv chan128 done")
         extra["cube192_m8"] = solve_pair(torch, "cube192", 8, 2)
+        extra["projection_chan128"] = projection_step(torch)
+        log(f"projection: {extra['projection_chan128']}")
         extra["serving"] = {"offered_5ms_gaps": serving(torch)}
         cap = extra["serving"]["offered_5ms_gaps"]["served_rhs_per_s"]
         off = extra["serving"]["offered_5ms_gaps"]["offered_rhs_per_s"]
