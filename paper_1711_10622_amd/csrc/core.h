@@ -689,8 +689,21 @@ __device__ __forceinline__ void grid_reduce(Acc<T, Shape<T, M>::VW, NDOT> &acc, 
         const int v = tid % V;
         const int k = tid / V;
         T s = T(0);
-        for (int q = k; q < gx; q += TPV)
-            s += fetch_published(&rb.part[static_cast<size_t>(grp + q * kGroups) * V + v]);
+        // partials q = k, k + TPV, ... in that order; eight loads in flight
+        // at a time (a load-then-add loop waits out one round trip each)
+        constexpr int U8 = 8;
+        for (int q0 = k; q0 < gx; q0 += U8 * TPV) {
+            T w[U8];
+#pragma unroll
+            for (int u = 0; u < U8; ++u) {
+                const int q = q0 + u * TPV;
+                w[u] = q < gx ? fetch_published(&rb.part[static_cast<size_t>(grp + q * kGroups) * V + v]) : T(0);
+            }
+#pragma unroll
+            for (int u = 0; u < U8; ++u)
+                if (q0 + u * TPV < gx)
+                    s += w[u];
+        }
         s_k[k][v] = s;
     }
     __syncthreads();
