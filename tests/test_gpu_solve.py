@@ -81,6 +81,40 @@ def test_channel_small_all_shapes(torch_cuda, mrhs, m):
         assert np.linalg.norm(mean_free(X[:, l:l + 1]) - Xo[:, l:l + 1]) <= 1e-6 * np.linalg.norm(Xo[:, l])
 
 
+@pytest.mark.parametrize("m", [1, 2, 3, 5, 6, 7, 9, 10, 12, 13, 15])
+def test_channel_small_mixed_all_widths(torch_cuda, mrhs, m):
+    """Mixed precision at block widths whose binary32 lanes hold 1 (odd m),
+    2 (m = 2 mod 4) or 4 columns, with the shadow residual's sign bytes laid
+    out per lane: every column reaches the binary64 true residual 1e-10 and
+    agrees with the binary64 block solve."""
+    A = grids.channel7(32, 16, 24, beta=2.0)
+    B = rng.rhs_block(A.n, m, 710 + m, mean_zero=True)
+    X, infos, st = gpu_solve(mrhs, torch_cuda, A, B, tol=1e-10, mixed=True)
+    assert st == 0, infos
+    assert np.all(true_relres(A, X, B) <= 1e-10)
+    X64, _, st64 = gpu_solve(mrhs, torch_cuda, A, B, tol=1e-10)
+    assert st64 == 0
+    err = np.linalg.norm(mean_free(X) - mean_free(X64), axis=0) / np.linalg.norm(mean_free(X64), axis=0)
+    assert np.all(err <= 1e-5), err
+
+
+def test_mixed_nan_and_zero_columns_isolated(torch_cuda, mrhs):
+    """Mixed precision: a zero right-hand side returns x = 0 at once, a NaN
+    column fails alone, and the other columns still converge."""
+    A = grids.dirichlet7(10)
+    B = rng.rhs_block(A.n, 6, 910)
+    B[:, 4] = 0.0
+    X1, i1, st1 = gpu_solve(mrhs, torch_cuda, A, B, tol=1e-10, mixed=True)
+    assert st1 == 0 and i1[4]["iters"] == 0 and np.all(X1[:, 4] == 0)
+    Bn = B.copy()
+    Bn[11, 2] = np.nan
+    Xn, inn, st = gpu_solve(mrhs, torch_cuda, A, Bn, tol=1e-10, mixed=True)
+    assert st < 0 and inn[2]["status"] < 0
+    for l in (0, 1, 3, 5):
+        assert inn[l]["status"] == 0
+        assert np.all(true_relres(A, Xn[:, l:l + 1], B[:, l:l + 1]) <= 1e-10)
+
+
 def test_block_equals_singles(torch_cuda, mrhs):
     A = grids.dirichlet7(12, 10, 14)
     B = rng.rhs_block(A.n, 5, 800)
