@@ -435,6 +435,30 @@ def gspmv_only(name):
     return 0
 
 
+def solve_only(name, mixed, steps):
+    """``steps`` block solves to 1e-10 of one workload at its configured m
+    (binary64, or mixed), after one untimed solve: for kernel traces under
+    rocprofv3."""
+    import numpy as np
+    import torch
+    import paper_1711_10622_amd as mrhs
+    from workloads import configs
+    mrhs.load(build_if_missing=False)
+    wl = configs.WORKLOADS[name]
+    m = max(wl.ms)
+    A = wl.matrix()
+    M = mrhs.CsrMatrix.from_csr(A)
+    B = torch.from_numpy(np.ascontiguousarray(wl.rhs(A.n, m))).cuda()
+    X = torch.empty_like(B)
+    ws = torch.empty(M.workspace_size(m, mixed), dtype=torch.uint8, device="cuda")
+    timed_solves(torch, M, B, X, ws, 1, mixed=mixed)
+    t, infos, _ = timed_solves(torch, M, B, X, ws, steps, mixed=mixed)
+    log(f"solve {name} m={m} {'mixed' if mixed else 'fp64'}: {t * 1e3:.1f} ms per solve, "
+        f"iterations max {max(i['iters'] for i in infos)}, outer max {max(i['outer'] for i in infos)}")
+    M.close()
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -445,6 +469,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB copy (counter calibration under rocprofv3)")
+    ap.add_argument("--solve-only", metavar="WORKLOAD",
+                    help="run only --steps solves of WORKLOAD (after one warm-up), for kernel traces")
+    ap.add_argument("--mixed", action="store_true", help="with --solve-only: mixed precision")
     ap.add_argument("--gspmv-only", metavar="MATRIX",
                     help="run only five GSpMV launches per case on MATRIX (counter runs under rocprofv3)")
     args = ap.parse_args()
@@ -457,6 +484,8 @@ def main():
         return copy_calibration()
     if args.gspmv_only:
         return gspmv_only(args.gspmv_only)
+    if args.solve_only:
+        return solve_only(args.solve_only, args.mixed, args.steps)
 
     import numpy as np
     import torch
