@@ -221,14 +221,15 @@ struct VecU {
 #define MRHS_NT_STORE 1
 #endif
 
-// Lane g's VW elements of row `row` of an n x M block.  The last lane of a row
-// whose width VW does not divide reads its TAIL elements one by one (the rest
-// of v is zero), so no access leaves the row.
+// Lane g's VW elements of row `row` of an n x M block whose rows lie ld
+// elements apart (ld = M, or 2M for a half of an interleaved pair of blocks).
+// The last lane of a row whose width VW does not divide reads its TAIL
+// elements one by one (the rest of v is zero), so no access leaves the row.
 template <typename T, int M>
-__device__ __forceinline__ void ld(const T *base, int32_t row, int g, T *v)
+__device__ __forceinline__ void ld(const T *base, int32_t row, int g, T *v, int32_t ld = M)
 {
     using S = Shape<T, M>;
-    const T *p = base + static_cast<size_t>(row) * M + g * S::VW;
+    const T *p = base + static_cast<size_t>(row) * ld + g * S::VW;
     if constexpr (S::TAIL == S::VW) {
         Vec<T, S::VW>::load(p, v);
     } else if (g == S::G - 1) {
@@ -244,10 +245,10 @@ __device__ __forceinline__ void ld(const T *base, int32_t row, int g, T *v)
 // (nontemporal) stores: every block is far larger than the caches, and
 // keeping written lines out of L2 leaves it to the gathered block rows.
 template <typename T, int M>
-__device__ __forceinline__ void st(T *base, int32_t row, int g, const T *v)
+__device__ __forceinline__ void st(T *base, int32_t row, int g, const T *v, int32_t ld = M)
 {
     using S = Shape<T, M>;
-    T *p = base + static_cast<size_t>(row) * M + g * S::VW;
+    T *p = base + static_cast<size_t>(row) * ld + g * S::VW;
     if constexpr (S::TAIL == S::VW) {
 #if MRHS_NT_STORE
         Vec<T, S::VW>::store_nt(p, v);

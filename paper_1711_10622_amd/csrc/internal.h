@@ -156,6 +156,7 @@ struct Ctx {
     double *r64;
     GcrBlocks gcr;
     float *r32, *p32, *v32, *t32, *y32;
+    int32_t ldp64 = 0, ldp32 = 0;  // row stride of the r/v blocks: 2m interleaved, else m
     uint8_t *sgn32;
 };
 

@@ -195,6 +195,12 @@ struct OpStore {
     __device__ void finish(const T *) const {}
 };
 
+// The solver may keep r and v as one interleaved n x 2M block (row i = r_i
+// then v_i, so v = r + M): the two rows spmv_omega gathers from one column
+// index then share cache lines, which halves the lines fetched per entry when
+// rows are visited in no particular order.  Ops take the row stride of r and
+// v as ldp (2M when interleaved, else M).
+
 // ---------------------------------------------------------------------------
 // Residual R = B - A X with per-column sums of R*R and B*B.  Which columns are
 // computed, and what the last workgroup does with the norms, depends on kind.
@@ -222,6 +228,7 @@ struct OpResid {
     int32_t kind;
     uint32_t cmask;  // columns of RES_FINAL / RES_NORM
     int32_t rcm;     // > 0: R is column-major with column stride rcm (R2, R3 unused)
+    int32_t rld;     // row stride of R when rcm == 0 (0: M; 2M for the r half of an r/v pair)
     struct Lane {
         bool on;
         bool act[S::VW];
@@ -286,19 +293,20 @@ struct OpResid {
             all = all && ln.act[v];
         if (all) {
             if (R)
-                st<double, M>(R, i, g, r);
+                st<double, M>(R, i, g, r, rld ? rld : M);
             if (R2)
                 st<double, M>(R2, i, g, r);
             if (R3)
                 st<double, M>(R3, i, g, r);
         } else {
             // only the columns this kind owns are written
+            const size_t orow = static_cast<size_t>(i) * (rld ? rld : M) + g * S::VW;
 #pragma unroll
             for (int v = 0; v < S::VW; ++v) {
                 if (!ln.act[v])
                     continue;
                 if (R)
-                    R[o + v] = r[v];
+                    R[orow + v] = r[v];
                 if (R2)
                     R2[o + v] = r[v];
                 if (R3)
@@ -437,6 +445,7 @@ struct OpSpmv1 {
     const uint8_t *sgn;  // sign bits of the shadow residual, or null: generated
     Ctl *ctl;
     Kry<T> *kry;
+    int32_t ldp;  // row stride of v
     using Lane = RunLane<T, M>;
     __device__ Lane lane(int g) const { return run_lane<T, M>(ctl, g); }
     __device__ __forceinline__ void gather(const Lane &, int32_t c, int g, T *x) const
@@ -449,7 +458,7 @@ struct OpSpmv1 {
         const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         T h[S::VW];
         shadow_row<T, M>(sgn, i, g, h);
-        st<T, M>(v, i, g, sum);
+        st<T, M>(v, i, g, sum, ldp);
 #pragma unroll
         for (int q = 0; q < S::VW; ++q)
             if (ln.act[q])
@@ -488,6 +497,7 @@ struct OpSpmv2 {
     T *t;
     Ctl *ctl;
     Kry<T> *kry;
+    int32_t ldp;  // row stride of r and v
     struct Lane {
         bool on;
         bool act[S::VW];
@@ -508,8 +518,8 @@ struct OpSpmv2 {
     __device__ __forceinline__ void gather(const Lane &ln, int32_t c, int g, T *x) const
     {
         T rr[S::VW], vv[S::VW];
-        ld<T, M>(r, c, g, rr);
-        ld<T, M>(v, c, g, vv);
+        ld<T, M>(r, c, g, rr, ldp);
+        ld<T, M>(v, c, g, vv, ldp);
 #pragma unroll
         for (int q = 0; q < S::VW; ++q)
             x[q] = rr[q] - ln.alpha[q] * vv[q];
@@ -573,6 +583,7 @@ struct OpXR {
     const uint8_t *sgn;  // sign bits of the shadow residual, or null: generated
     Ctl *ctl;
     Kry<T> *kry;
+    int32_t ldp;  // row stride of r and v
     struct Lane {
         bool on;
         bool act[S::VW];
@@ -600,9 +611,9 @@ struct OpXR {
         const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         T yy[S::VW], rr[S::VW], pp[S::VW], vv[S::VW], tt[S::VW];
         ld<T, M>(y, i, g, yy);
-        ld<T, M>(r, i, g, rr);
+        ld<T, M>(r, i, g, rr, ldp);
         ld<T, M>(p, i, g, pp);
-        ld<T, M>(v, i, g, vv);
+        ld<T, M>(v, i, g, vv, ldp);
         ld<T, M>(t, i, g, tt);
         T hh[S::VW];
         shadow_row<T, M>(sgn, i, g, hh);
@@ -623,7 +634,7 @@ struct OpXR {
             }
         }
         st<T, M>(y, i, g, yy);
-        st<T, M>(r, i, g, rr);
+        st<T, M>(r, i, g, rr, ldp);
         st<T, M>(p, i, g, pp);
     }
     __device__ void finish(const T *tot) const
@@ -680,6 +691,7 @@ struct OpRestart {
     T *r;
     T *p;
     const Ctl *ctl;
+    int32_t ldp;  // row stride of r
     struct Lane {
         bool on;
         bool act[S::VW];
@@ -701,7 +713,7 @@ struct OpRestart {
         const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         T a[S::VW], b[S::VW], pp[S::VW];
         ld<T, M>(rt, i, g, a);
-        ld<T, M>(r, i, g, b);
+        ld<T, M>(r, i, g, b, ldp);
         ld<T, M>(p, i, g, pp);
 #pragma unroll
         for (int q = 0; q < S::VW; ++q)
@@ -709,7 +721,7 @@ struct OpRestart {
                 b[q] = a[q];
                 pp[q] = a[q];
             }
-        st<T, M>(r, i, g, b);
+        st<T, M>(r, i, g, b, ldp);
         st<T, M>(p, i, g, pp);
     }
     __device__ void finish(const T *) const {}
@@ -838,6 +850,7 @@ struct OpCast {
     Ctl *ctl;
     Kry<float> *kry;
     int32_t n;
+    int32_t ldp;  // row stride of r
     struct Lane {
         bool on;
         bool act[S::VW];
@@ -860,7 +873,7 @@ struct OpCast {
     {
         const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         float a[S::VW], z[S::VW], pp[S::VW];
-        ld<float, M>(r, i, g, a);
+        ld<float, M>(r, i, g, a, ldp);
         ld<float, M>(y, i, g, z);
         ld<float, M>(p, i, g, pp);
         uint8_t *sb = sgn + static_cast<size_t>(i) * S::L + g;
@@ -877,7 +890,7 @@ struct OpCast {
                 bits = (f < 0.0f) ? (bits | (1u << q)) : (bits & ~(1u << q));
             }
         }
-        st<float, M>(r, i, g, a);
+        st<float, M>(r, i, g, a, ldp);
         st<float, M>(y, i, g, z);
         st<float, M>(p, i, g, pp);
         *sb = static_cast<uint8_t>(bits);

@@ -39,17 +39,37 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
     size_t ctl, kry64, kry32, tickets, part, gpart;
-    size_t v64[4];      // r, p, v, t                      (binary64 solve)
+    size_t rv64, p64, t64;  // r/v pair (n x 2m, v = r + m), p, t (binary64 solve)
     size_t r64;         // refinement residual             (mixed)
     size_t z[kGcrMax];  // stored directions z_j           (mixed)
     size_t w[kGcrMax];  // and w_j = A z_j                 (mixed)
     size_t znew, wnew;  // the direction being formed      (mixed)
     size_t xacc;        // accumulated correction of x      (mixed)
     // (the mixed-precision binary64 buffers are column-major, one n-vector per column)
-    size_t v32[5];      // r, p, v, t, y                   (mixed, binary32)
+    size_t rv32, v32[3];    // r/v pair (n x 2m), then p, t, y  (mixed, binary32)
     size_t sgn32;       // sign bits of the inner shadow residual (mixed)
     size_t total;
 };
+
+// Plain (not interleaved) r and v blocks lie kPairGap bytes further apart
+// than their size, for the reason the workspace blocks are staggered (see
+// layout).
+constexpr size_t kPairGap = 8192;
+
+// r and v share one region of 2 n m elements (+ kPairGap bytes): interleaved
+// row by row (v = r + m, row stride 2m) when the matrix has no regular plane
+// structure (its gathers visit rows in no particular order, and one line then
+// serves both rows of an entry: relabelled cube, m = 8, spmv_omega 601 -> 357
+// us binary64 and 553 -> 301 us binary32) or when each half is a whole
+// 128-byte line; else as two plain blocks (half-line rows made the channel's
+// binary32 passes 4 % slower).
+bool pair_rv(const mrhs_csr_s &A, int32_t m, size_t elem)
+{
+    const int64_t ntiles = (static_cast<int64_t>(A.n) + kTileRows - 1) / kTileRows;
+    const int64_t P = (static_cast<int64_t>(A.reach) + kTileRows / 2) / kTileRows;
+    const bool planes = P >= 2 * kGroups && ntiles >= 4 * P;
+    return !planes || m * elem >= 128;
+}
 
 Layout layout(int32_t n, int32_t m, uint32_t flags)
 {
@@ -89,12 +109,14 @@ Layout layout(int32_t n, int32_t m, uint32_t flags)
         L.znew = take_blk(blk64);
         L.wnew = take_blk(blk64);
         L.xacc = take_blk(blk64);
-        for (int i = 0; i < 5; ++i)
+        L.rv32 = take_blk(2 * blk32 + kPairGap);
+        for (int i = 0; i < 3; ++i)
             L.v32[i] = take_blk(blk32);
         L.sgn32 = take(static_cast<size_t>(n) * kMaxM);  // n x (lanes per row <= 16) bytes
     } else {
-        for (int i = 0; i < 4; ++i)
-            L.v64[i] = take_blk(blk64);
+        L.rv64 = take_blk(2 * blk64 + kPairGap);
+        L.p64 = take_blk(blk64);
+        L.t64 = take_blk(blk64);
     }
     L.total = off;
     return L;
@@ -171,19 +193,19 @@ struct Steps {
         MRHS_TRY((launch_stream<double, M>(
             c.n, OpScale<M>{c.X, c.A->diag, c.A->dinv, c.ctl, x0 ? SC_IN : SC_ZERO, cmask}, c.rb64, c.s)));
         return launch_gspmv<double, M>(view<double>(*c.A, true),
-                                       OpResid<M>{c.X, c.B, c.r, c.p, nullptr, c.ctl, c.kry64, RES_SETUP, 0u},
+                                       OpResid<M>{c.X, c.B, c.r, c.p, nullptr, c.ctl, c.kry64, RES_SETUP, 0u, 0, c.ldp64},
                                        c.rb64, c.s);
     }
     static hipError_t f64_iterate(Ctx &c, int k)
     {
         const CsrView<double> Ah = view<double>(*c.A, true);
         for (int it = 0; it < k; ++it) {
-            MRHS_TRY((launch_gspmv<double, M>(Ah, OpSpmv1<double, M>{c.p, c.v, nullptr, c.ctl, c.kry64},
+            MRHS_TRY((launch_gspmv<double, M>(Ah, OpSpmv1<double, M>{c.p, c.v, nullptr, c.ctl, c.kry64, c.ldp64},
                                                c.rb64, c.s)));
-            MRHS_TRY((launch_gspmv<double, M>(Ah, OpSpmv2<double, M>{c.r, c.v, nullptr, c.t, c.ctl, c.kry64},
+            MRHS_TRY((launch_gspmv<double, M>(Ah, OpSpmv2<double, M>{c.r, c.v, nullptr, c.t, c.ctl, c.kry64, c.ldp64},
                                                c.rb64, c.s)));
             MRHS_TRY((launch_stream<double, M>(
-                c.n, OpXR<double, M>{c.X, c.r, c.p, c.v, c.t, nullptr, c.ctl, c.kry64}, c.rb64, c.s)));
+                c.n, OpXR<double, M>{c.X, c.r, c.p, c.v, c.t, nullptr, c.ctl, c.kry64, c.ldp64}, c.rb64, c.s)));
         }
         return hipSuccess;
     }
@@ -192,7 +214,7 @@ struct Steps {
         MRHS_TRY((launch_gspmv<double, M>(view<double>(*c.A, true),
                                            OpResid<M>{c.X, c.B, c.t, nullptr, nullptr, c.ctl, c.kry64, RES_CHECK, 0u},
                                            c.rb64, c.s)));
-        return launch_stream<double, M>(c.n, OpRestart<double, M>{c.t, c.r, c.p, c.ctl}, c.rb64, c.s);
+        return launch_stream<double, M>(c.n, OpRestart<double, M>{c.t, c.r, c.p, c.ctl, c.ldp64}, c.rb64, c.s);
     }
     static hipError_t finish(Ctx &c, uint32_t cmask, bool mixed, bool nullspace)
     {
@@ -267,7 +289,7 @@ struct Steps {
     }
     static hipError_t mixed_cast(Ctx &c)
     {
-        return launch_stream<float, M>(c.n, OpCast<M>{c.r64, c.r32, c.sgn32, c.y32, c.p32, c.ctl, c.kry32, c.n}, c.rb32,
+        return launch_stream<float, M>(c.n, OpCast<M>{c.r64, c.r32, c.sgn32, c.y32, c.p32, c.ctl, c.kry32, c.n, c.ldp32}, c.rb32,
                                        c.s);
     }
     static hipError_t inner_iterate(Ctx &c, int k)
@@ -275,11 +297,11 @@ struct Steps {
         const CsrView<float> Ah = view<float>(*c.A, true);
         for (int it = 0; it < k; ++it) {
             MRHS_TRY((launch_gspmv<float, M>(
-                Ah, OpSpmv1<float, M>{c.p32, c.v32, c.sgn32, c.ctl, c.kry32}, c.rb32, c.s)));
+                Ah, OpSpmv1<float, M>{c.p32, c.v32, c.sgn32, c.ctl, c.kry32, c.ldp32}, c.rb32, c.s)));
             MRHS_TRY((launch_gspmv<float, M>(
-                Ah, OpSpmv2<float, M>{c.r32, c.v32, c.sgn32, c.t32, c.ctl, c.kry32}, c.rb32, c.s)));
+                Ah, OpSpmv2<float, M>{c.r32, c.v32, c.sgn32, c.t32, c.ctl, c.kry32, c.ldp32}, c.rb32, c.s)));
             MRHS_TRY((launch_stream<float, M>(
-                c.n, OpXR<float, M>{c.y32, c.r32, c.p32, c.v32, c.t32, c.sgn32, c.ctl, c.kry32}, c.rb32,
+                c.n, OpXR<float, M>{c.y32, c.r32, c.p32, c.v32, c.t32, c.sgn32, c.ctl, c.kry32, c.ldp32}, c.rb32,
                 c.s)));
         }
         return hipSuccess;
@@ -354,14 +376,21 @@ Engine::Engine(const mrhs_csr_s &A, int m, uint32_t flags, void *ws, const doubl
         c_.gcr.wnew = reinterpret_cast<double *>(base + L.wnew);
         c_.gcr.xacc = reinterpret_cast<double *>(base + L.xacc);
         c_.gcr.ndirs = ndirs_;
-        float **v32[5] = {&c_.r32, &c_.p32, &c_.v32, &c_.t32, &c_.y32};
-        for (int i = 0; i < 5; ++i)
+        const bool pair = pair_rv(A, m, sizeof(float));
+        c_.r32 = reinterpret_cast<float *>(base + L.rv32);
+        c_.v32 = pair ? c_.r32 + m_ : c_.r32 + static_cast<size_t>(A.n) * m_ + kPairGap / sizeof(float);
+        c_.ldp32 = pair ? 2 * m_ : m_;
+        float **v32[3] = {&c_.p32, &c_.t32, &c_.y32};
+        for (int i = 0; i < 3; ++i)
             *v32[i] = reinterpret_cast<float *>(base + L.v32[i]);
         c_.sgn32 = reinterpret_cast<uint8_t *>(base + L.sgn32);
     } else {
-        double **v64[4] = {&c_.r, &c_.p, &c_.v, &c_.t};
-        for (int i = 0; i < 4; ++i)
-            *v64[i] = reinterpret_cast<double *>(base + L.v64[i]);
+        const bool pair = pair_rv(A, m, sizeof(double));
+        c_.r = reinterpret_cast<double *>(base + L.rv64);
+        c_.v = pair ? c_.r + m_ : c_.r + static_cast<size_t>(A.n) * m_ + kPairGap / sizeof(double);
+        c_.ldp64 = pair ? 2 * m_ : m_;
+        c_.p = reinterpret_cast<double *>(base + L.p64);
+        c_.t = reinterpret_cast<double *>(base + L.t64);
     }
     chunk_ = env_int("MRHS_POLL_ITERS", 16, 1, 1024);
     tol_in_ = env_double("MRHS_INNER_TOL", 0.1);
