@@ -39,14 +39,14 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
     size_t ctl, kry64, kry32, tickets, part, gpart;
-    size_t rv64, p64, t64;  // r/v pair (n x 2m, v = r + m), p, t (binary64 solve)
+    size_t rv64, p64, t64;  // r and v (one region, see pair_rv), p, t (binary64 solve)
     size_t r64;         // refinement residual             (mixed)
     size_t z[kGcrMax];  // stored directions z_j           (mixed)
     size_t w[kGcrMax];  // and w_j = A z_j                 (mixed)
     size_t znew, wnew;  // the direction being formed      (mixed)
     size_t xacc;        // accumulated correction of x      (mixed)
     // (the mixed-precision binary64 buffers are column-major, one n-vector per column)
-    size_t rv32, v32[3];    // r/v pair (n x 2m), then p, t, y  (mixed, binary32)
+    size_t rv32, v32[3];    // r and v (one region), then p, t, y  (mixed, binary32)
     size_t sgn32;       // sign bits of the inner shadow residual (mixed)
     size_t total;
 };
