@@ -214,18 +214,25 @@ def test_plane_chunked_schedule(torch_cuda, mrhs, dtype, m):
         assert np.all(np.abs(Y - ref) <= gamma(max_row_len(A), U32) * abs_bound(A32, X))
 
 
-def test_large_channel_sampled(torch_cuda, mrhs):
-    """The 256x192x256 channel (12.6M rows, m = 16), on 20k sampled rows
-    including the first and last tiles."""
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_large_channel_sampled(torch_cuda, mrhs, dtype):
+    """The 256x192x256 channel (12.6M rows, m = 16, the chunked plane
+    schedule), on 20k sampled rows including the first and last tiles."""
     A = configs.MATRICES["chan256"]()
     X = configs.WORKLOADS["chan256"].rhs(A.n, 16)
-    Y = gpu_gspmv(mrhs, torch_cuda, A, X)
     r = np.random.default_rng(0)
     rows = np.unique(np.concatenate([np.arange(512), np.arange(A.n - 512, A.n),
                                      r.integers(0, A.n, size=20000)]))
-    ref = oracle.gspmv_rows(A, X, rows)
-    bound = abs_bound(A, X, rows)
-    assert np.all(np.abs(Y[rows] - ref) <= 1e-13 * bound)
+    if dtype == np.float64:
+        Y = gpu_gspmv(mrhs, torch_cuda, A, X)
+        ref = oracle.gspmv_rows(A, X, rows)
+        assert np.all(np.abs(Y[rows] - ref) <= 1e-13 * abs_bound(A, X, rows))
+    else:
+        X = round32(X)
+        A32 = f32_matrix(A)
+        Y = gpu_gspmv(mrhs, torch_cuda, A, X, dtype=np.float32)
+        ref = oracle.gspmv_rows(A32, X, rows)
+        assert np.all(np.abs(Y[rows] - ref) <= gamma(max_row_len(A), U32) * abs_bound(A32, X, rows))
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
