@@ -19,7 +19,8 @@
  *    repeated column adds (the Figure 1 loop sums every stored entry); an
  *    empty row yields 0.
  *  - A block X of m vectors is n x m, row-interleaved: X[i*m + l] is row i
- *    of vector l ("stored row-wise in single vectors", Section 2.3).
+ *    of vector l (the m values of a row lie together, the block layout of
+ *    Section 2.3).
  *  - 1 <= m <= 16.  Device pointers are HIP device memory of the current
  *    device, 16-byte aligned (EINVAL otherwise); a stream argument of NULL
  *    means the null stream.
