@@ -231,3 +231,36 @@ def test_initial_guess_exact():
     X, infos, _ = oracle.bicgstab(A, B, tol=1e-10, X0=xstar)
     assert infos[0]["iters"] == 0 and infos[0]["status"] == 0
     assert np.array_equal(X, xstar)
+
+
+@pytest.mark.parametrize("shadow", SHADOWS)
+def test_restart_continues_as_a_fresh_start(shadow):
+    """A restart from the true residual is a fresh start from the current
+    iterate: the shadow residual is re-taken as the new residual (r^ = r0
+    mode) or stays the one fixed vector (random mode), and the recurrence
+    scalars reset.  So the residual history after the first restart must
+    equal, bit for bit, that of a new solve started at the restart iterate.
+    A tolerance below the attainable accuracy forces the restarts: the
+    recurrence residual keeps falling while the true one stalls."""
+    A = grids.channel7(16, 12, 8, beta=2.0)
+    B = rng.rhs_block(A.n, 1, 31, mean_zero=True)
+    tol = 1e-15
+    K = None
+    for mx in range(60, 200):  # smallest maxit that ends right at the first restart
+        Xk, inf, _ = oracle.bicgstab(A, B, tol=tol, maxit=mx, shadow_seed=shadow, nullspace_const=False)
+        if inf[0]["restarts"] >= 1:
+            K = mx
+            break
+    assert K is not None and inf[0]["status"] == oracle.ENOCONV
+    J = 30
+    _, inf_l, hist_l = oracle.bicgstab(A, B, tol=tol, maxit=K + J, shadow_seed=shadow, hist_len=K + J + 1,
+                                       nullspace_const=False)
+    _, inf_f, hist_f = oracle.bicgstab(A, B, tol=tol, maxit=J, shadow_seed=shadow, hist_len=J + 1, X0=Xk,
+                                       nullspace_const=False)
+    assert inf_l[0]["restarts"] >= 2          # the continuation restarts again
+    a, b = hist_l[0, K:K + J + 1], hist_f[0, :J + 1]
+    used = ~np.isnan(a)
+    assert used.sum() >= 8 and np.array_equal(np.isnan(a), np.isnan(b))
+    assert np.array_equal(a[used], b[used])
+    assert inf_l[0]["restarts"] - 1 == inf_f[0]["restarts"]
+    assert inf_l[0]["iters"] - K == inf_f[0]["iters"]

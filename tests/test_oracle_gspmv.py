@@ -149,3 +149,84 @@ def test_generator_counts(shape):
     assert A.nnz == 7 * n - 2 * (ny * nz + nx * nz + nx * ny)
     C = grids.channel7(max(nx, 3), ny, max(nz, 3))
     assert C.nnz == 7 * C.n - 2 * max(nx, 3) * max(nz, 3)
+
+
+def _exact_rows(rp, col, val, X):
+    """Exact row sums (rationals) and sum |a||x| of a CSR product, column 0."""
+    from fractions import Fraction
+    out, mag = [], []
+    for i in range(len(rp) - 1):
+        s = Fraction(0)
+        a = Fraction(0)
+        for j in range(rp[i], rp[i + 1]):
+            t = Fraction(val[j]) * Fraction(X[col[j], 0])
+            s += t
+            a += abs(t)
+        out.append(s)
+        mag.append(a)
+    return out, mag
+
+
+def _cancelling_rows():
+    """Rows whose plain left-to-right sum loses everything: huge terms that
+    cancel around small ones, and products whose low-order half decides the
+    result.  Column j of row i multiplies X[j]; X holds the chosen factors."""
+    r = np.random.default_rng(1711)
+    rows = []
+    # (2^53, 1, -2^53) . (1, 1, 1) = 1; plain summation gives 0
+    rows.append([(2.0 ** 53, 1.0), (1.0, 1.0), (-(2.0 ** 53), 1.0)])
+    # (1 + 2^-30)(1 - 2^-30) - 1 = -2^-60; the rounded product is exactly 1
+    rows.append([(1.0 + 2.0 ** -30, 1.0 - 2.0 ** -30), (-1.0, 1.0)])
+    # a stencil-length row: two cancelling giants around three random terms,
+    # then minus the rounded sum of those terms, so the exact result is the
+    # rounding error of that sum
+    for _ in range(6):
+        small = r.uniform(-1, 1, 3) * 2.0 ** r.integers(-20, 20, 3)
+        big = float(2.0 ** int(r.integers(60, 90)))
+        s = float(sum(small))
+        rows.append([(big, 1.0), (small[0], 1.0), (small[1], 1.0), (-big, 1.0), (small[2], 1.0),
+                     (-s, 1.0), (r.uniform(-1, 1) * 2.0 ** -70, 1.0)])
+    # products with many significant bits: x_j y_j summed against the
+    # negated double-rounded sum of the products
+    for _ in range(6):
+        a = r.uniform(1, 2, 6) * np.where(r.random(6) < 0.5, -1, 1)
+        b = r.uniform(1, 2, 6)
+        s = float(np.sum(a * b))
+        rows.append([(a[k], b[k]) for k in range(6)] + [(-s, 1.0)])
+    return rows
+
+
+def test_dot2_compensation_on_cancelling_rows():
+    """Dot2 against the exact (rational) row sums on rows where plain
+    summation fails: within u|s| + gamma_k^2 sum|a||x| (Ogita, Rump & Oishi
+    2005, the Dot2 error bound), while the plain oracle product is wrong."""
+    rows = _cancelling_rows()
+    rp = [0]
+    col, val, xs = [], [], []
+    for row in rows:
+        for a, x in row:
+            col.append(len(xs))
+            val.append(a)
+            xs.append(x)
+        rp.append(len(col))
+    n = len(xs)
+    # square CSR: pad with empty rows so every factor has a row index
+    rp = rp + [rp[-1]] * (n - len(rows))
+    A = grids.CSRMatrix(n, np.array(rp, dtype=np.int32), np.array(col, dtype=np.int32),
+                        np.array(val, dtype=np.float64))
+    X = np.array(xs, dtype=np.float64)[:, None]
+    exact, mag = _exact_rows(rp, col, val, X)
+    Y2 = oracle.gspmv_dot2(A, X)[:, 0]
+    Y1 = oracle.gspmv(A, X)[:, 0]
+    wrong_plain = 0
+    for i in range(len(rows)):
+        k = rp[i + 1] - rp[i]
+        g = k * U64 / (1 - k * U64)
+        bound = U64 * abs(float(exact[i])) + g * g * float(mag[i])
+        from fractions import Fraction
+        assert abs(Fraction(Y2[i]) - exact[i]) <= Fraction(bound) * (1 + 1e-9), (i, Y2[i], float(exact[i]))
+        wrong_plain += Fraction(Y1[i]) != exact[i]
+    # the rows are hard: plain summation misses most of them
+    assert wrong_plain >= len(rows) - 2
+    assert Y2[0] == 1.0 and Y1[0] == 0.0
+    assert Y2[1] == -(2.0 ** -60)
