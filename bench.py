@@ -1,32 +1,39 @@
 #!/usr/bin/env python3
 """Benchmark of the block multi-RHS pressure-Poisson solve on one MI355X.
 
-Workload (the channel case the metric is quoted on): the finite-volume
-pressure operator of a 128 x 64 x 64 channel (periodic x/z, Neumann walls,
-tanh beta = 2 wall stretching; n = 524,288, nnz = 3,653,632) with m = 16
-mean-zero U[-1,1) right-hand sides (seed 1712), solved by block
+Workload (the large channel case of the metric): the finite-volume pressure
+operator of a 256 x 192 x 256 channel (periodic x/z, Neumann walls, tanh
+beta = 2 wall stretching; n = 12,582,912, nnz = 87,949,312) with m = 16
+mean-zero U[-1,1) right-hand sides (seed 1715), solved by block
 Jacobi-BiCGStab in binary64 to a true relative residual of 1e-10 from x0 = 0.
-One step = one such block solve (every kernel of the path: products,
-fused vector updates, per-column dots, device-side scalar control, true
-residual checks, the null-space projection and the final residual).
-``value`` = seconds per right-hand side = step time / m, with the matrix,
-B and the workspace already resident in HBM.
+One step = one such block solve (every kernel of the path: products, fused
+vector updates, per-column dots, device-side scalar control, true residual
+checks, the null-space projection and the final residual).  ``value`` =
+seconds per right-hand side = step time / m, with the matrix, B and the
+workspace already resident in HBM.
 
 ``roofline`` prices the kernel with the largest share of the timed steps:
 its algorithmic bytes per launch over its mean launch time, both taken from
 HIP events recorded around every 8th launch of each kernel class on the
-library's stream during the timed steps.  ``traffic`` is the HBM bytes per launch that rocprofv3's
-FETCH_SIZE and WRITE_SIZE counters saw for that kernel (scaled by what they
-read for a plain 1 GiB copy), taken from the committed profile summary and
-reported only while the kernel sources are the ones that were profiled.
+library's stream during the timed steps.  ``traffic`` is the HBM bytes per
+launch that rocprofv3's FETCH_SIZE and WRITE_SIZE counters saw for that
+kernel (scaled by what they read for a plain 1 GiB copy), taken from the
+committed profile summary and reported only while the kernel sources are the
+ones that were profiled.
 
-Also reported (not part of ``value``): the solve at m = 1, 2, 4, 8 with the
-speedup per right-hand side beside the paper's traffic models (Section 2.3),
-the time per iteration at a fixed iteration count, the mixed binary32 /
-binary64 solve, the relabelled cube channel (m = 8) and the 12.6M-row channel
-(m = 16) in both precisions, the generalized SpMV sweep m = 1..16 (binary64 and
-binary32) on the 12.6M-row channel and warm/flushed on the 524k-row channel,
-open-loop serving (p50/p99 latency, RHS/s), and the oracle on the host cores.
+``cpu_baseline``: the oracle's per-column BiCGStab on the same 16 columns,
+one host thread per column, run for 2 and for 12 iterations; the difference
+gives the time per iteration, and s/RHS is setup plus the GPU solve's
+iteration count times that, over m.
+
+Also reported (not part of ``value``): the library's streaming kernels'
+read/write/copy rates (the attainable memory ceilings), the mixed binary32 /
+binary64 solve of the same block, the time per iteration at a fixed count for
+m = 1, 2, 4, 8, 16 with the speedup per right-hand side beside the paper's
+traffic models (Section 2.3), the generalized SpMV sweep m = 1..16 (binary64
+and binary32), the 524k-row channel (solves per m, mixed, error against the
+oracle), the relabelled cube channel (m = 8) in both precisions, the ensemble
+projection step, and open-loop serving (p50/p99 latency, RHS/s).
 """
 from __future__ import annotations
 
@@ -48,7 +55,8 @@ HBM_PEAK_GBS = 8000.0
 # a pair leaves the stream idle for a few microseconds, which timing every
 # launch would add to every step
 TRACE_EVERY = 8
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_solve_chan128_m16.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_solve_chan256_m16.md")
+HEADLINE = "chan256"
 
 
 def log(msg):
@@ -341,18 +349,75 @@ def serving(torch, n_req=300, seed=1714, mean_gap_s=0.005, budget=16 << 30, rate
             "server_rhs_per_s": round(st["rhs_per_s"], 1), "max_outstanding": max_q, "not_ok": bad}
 
 
-def cpu_baseline(A, B, ncols):
+def host_cores():
+    try:
+        return len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(A, Bh, gpu_iters, threads):
+    """The oracle on the host cores: every column of Bh by its own
+    right-Jacobi BiCGStab (the same shadow residual as the GPU solve), one
+    thread per column, ``threads`` at a time, for 2 and for 12 iterations.
+    The difference is the wall time of 10 iterations of all columns; s/RHS =
+    (setup + gpu_iters iterations) / m."""
     import oracle
-    Bs = B[:, :ncols].copy()
-    t0 = time.perf_counter()
     import paper_1711_10622_amd as mrhs
-    X, infos, _ = oracle.bicgstab(A, Bs, tol=1e-10, maxit=20000, threads=ncols, shadow_seed=mrhs.SHADOW_SEED)
-    wall = time.perf_counter() - t0
+    m = Bh.shape[1]
+    wall = {}
+    for k in (2, 12):
+        t0 = time.perf_counter()
+        _, infos, _ = oracle.bicgstab(A, Bh, tol=1e-300, maxit=k, threads=threads, shadow_seed=mrhs.SHADOW_SEED)
+        wall[k] = time.perf_counter() - t0
+        assert all(i["iters"] == k for i in infos), infos
+        log(f"oracle {k} iterations x {m} columns on {threads} threads: {wall[k]:.2f} s")
+    per_iter = (wall[12] - wall[2]) / 10
+    setup = max(wall[2] - 2 * per_iter, 0.0)
+    value = (setup + gpu_iters * per_iter) / m
+    return {"value": value, "unit": "s/RHS", "cores": threads, "kind": "oracle",
+            "sample": f"all {m} right-hand sides of the same workload, one host thread per column ({threads} "
+                      f"threads), binary64, run for 2 and for 12 iterations ({wall[2]:.2f} s, {wall[12]:.2f} s): "
+                      f"{per_iter:.3f} s per iteration of the block, setup {setup:.2f} s; s/RHS = (setup + "
+                      f"{gpu_iters} iterations, the GPU solve's count) / {m}",
+            "per_iter_s": round(per_iter, 4), "iters_basis": gpu_iters}
+
+
+def oracle_error(A, Bh, Xgpu, ncols, threads):
+    """Per-RHS relative error (mean-free) of GPU solutions against the
+    oracle's own solves of the first ncols columns."""
+    import numpy as np
+    import oracle
+    import paper_1711_10622_amd as mrhs
+    t0 = time.perf_counter()
+    Xo, infos, _ = oracle.bicgstab(A, Bh[:, :ncols].copy(), tol=1e-10, maxit=20000, threads=threads,
+                                   shadow_seed=mrhs.SHADOW_SEED)
     assert all(i["status"] == 0 for i in infos), infos
-    return {"value": wall / ncols, "unit": "s/RHS", "cores": ncols, "kind": "oracle",
-            "sample": f"{ncols} of the {B.shape[1]} right-hand sides of the same workload, "
-                      f"one host thread per column, FP64 to 1e-10 (wall {wall:.2f} s)",
-            "iters": [i["iters"] for i in infos]}, X
+    out = {"oracle_s": round(time.perf_counter() - t0, 2), "oracle_iters": [i["iters"] for i in infos]}
+    for tag, X in Xgpu.items():
+        out[tag] = [float(np.linalg.norm(X[:, l] - Xo[:, l]) / np.linalg.norm(Xo[:, l])) for l in range(ncols)]
+    return out
+
+
+def memory_ceilings(torch, nbytes=2 << 30, reps=10):
+    """The library's streaming kernels over nbytes (8x the 256 MB
+    Infinity Cache): median GB/s of read, write and copy, plain and
+    nontemporal (a copy moves 2 nbytes)."""
+    import numpy as np
+    import paper_1711_10622_amd as mrhs
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    a.fill_(3)
+    out = {}
+    for kind in ("read", "read_nt", "write", "write_nt", "copy", "copy_nt"):
+        us = event_times_us(torch, lambda: mrhs.stream_probe(kind, a, b, nbytes), reps, 2)
+        moved = 2 * nbytes if kind.startswith("copy") else nbytes
+        med = float(np.median(us))
+        out[kind] = {"GBps": round(moved / (med * 1e-6) / 1e9, 1), "us_median": round(med, 1)}
+    del a, b
+    torch.cuda.empty_cache()
+    out["bytes"] = nbytes
+    return out
 
 
 def host_info():
@@ -364,7 +429,7 @@ def host_info():
                 break
     except OSError:
         pass
-    return {"nproc": os.cpu_count(), "cpu_model": model}
+    return {"nproc": host_cores(), "cpu_count": os.cpu_count(), "cpu_model": model}
 
 
 def cpu_gspmv(A, m, threads):
@@ -435,10 +500,11 @@ def gspmv_only(name):
     return 0
 
 
-def solve_only(name, mixed, steps):
-    """``steps`` block solves to 1e-10 of one workload at its configured m
-    (binary64, or mixed), after one untimed solve: for kernel traces under
-    rocprofv3."""
+def solve_only(name, mixed, steps, maxit=20000):
+    """``steps`` block solves of one workload at its largest configured m
+    (binary64, or mixed), after one untimed solve: for kernel traces and
+    counter runs under rocprofv3.  A small ``maxit`` caps the iterations
+    (every column stays active, so every launch moves its full bytes)."""
     import numpy as np
     import torch
     import paper_1711_10622_amd as mrhs
@@ -451,12 +517,83 @@ def solve_only(name, mixed, steps):
     B = torch.from_numpy(np.ascontiguousarray(wl.rhs(A.n, m))).cuda()
     X = torch.empty_like(B)
     ws = torch.empty(M.workspace_size(m, mixed), dtype=torch.uint8, device="cuda")
-    timed_solves(torch, M, B, X, ws, 1, mixed=mixed)
-    t, infos, _ = timed_solves(torch, M, B, X, ws, steps, mixed=mixed)
+    ok = maxit >= 20000
+    timed_solves(torch, M, B, X, ws, 1, mixed=mixed, maxit=maxit, expect_ok=ok)
+    t, infos, _ = timed_solves(torch, M, B, X, ws, steps, mixed=mixed, maxit=maxit, expect_ok=ok)
     log(f"solve {name} m={m} {'mixed' if mixed else 'fp64'}: {t * 1e3:.1f} ms per solve, "
         f"iterations max {max(i['iters'] for i in infos)}, outer max {max(i['outer'] for i in infos)}")
     M.close()
     return 0
+
+
+def per_iteration(torch, M, Bh, ms, reps=1):
+    """Time per block iteration at a fixed count (the paper's methodology,
+    Section 4.1): difference of 200- and 100-iteration runs, so setup and the
+    final residual cancel; with m t_1 / t_m beside the traffic models."""
+    import numpy as np
+    from paper_1711_10622_amd import estimates as est
+    out = {}
+    n, nnz = M.n, M.nnz
+    for mm in ms:
+        Bm = torch.from_numpy(np.ascontiguousarray(Bh[:, :mm])).to("cuda")
+        Xm = torch.empty_like(Bm)
+        ws = torch.empty(M.workspace_size(mm), dtype=torch.uint8, device="cuda")
+        t100, _, _ = timed_solves(torch, M, Bm, Xm, ws, reps, tol=1e-300, maxit=100, expect_ok=False)
+        t200, _, _ = timed_solves(torch, M, Bm, Xm, ws, reps, tol=1e-300, maxit=200, expect_ok=False)
+        out[mm] = {"ms_per_iter": (t200 - t100) / 100 * 1e3}
+        del Bm, Xm, ws
+    i1 = out[ms[0]]["ms_per_iter"] if ms[0] == 1 else None
+    for mm, d in out.items():
+        if i1:
+            d["iter_gain_vs_m1"] = round(mm * i1 / d["ms_per_iter"], 3)
+        d["paper_compact_5m_2m3"] = round(est.gain_compact(mm), 3)
+        d["paper_full_C"] = round(est.gain_full(mm, nnz / n), 3)
+        d["compulsory_bytes_model"] = round(est.gain_compulsory(n, nnz, mm), 3)
+        d["ms_per_iter"] = round(d["ms_per_iter"], 4)
+    torch.cuda.empty_cache()
+    return out
+
+
+def chan128_legs(torch, steps):
+    """The 524k-row channel (its matrix, m = 16 block and workspace fit the
+    256 MB Infinity Cache): binary64 solve, solves per m with the speedup per
+    right-hand side, mixed; returns the legs and its first four solutions."""
+    import numpy as np
+    import paper_1711_10622_amd as mrhs
+    from paper_1711_10622_amd import estimates as est
+    from workloads import configs
+    wl = configs.WORKLOADS["chan128"]
+    A = wl.matrix()
+    Bh = wl.rhs(A.n, 16)
+    M = mrhs.CsrMatrix.from_csr(A)
+    ws = torch.empty(max(M.workspace_size(16, mixed=True), M.workspace_size(16)), dtype=torch.uint8,
+                     device="cuda")
+    per_m = {}
+    Xs = {}
+    for mm in (1, 2, 4, 8, 16):
+        Bm = torch.from_numpy(np.ascontiguousarray(Bh[:, :mm])).to("cuda")
+        Xm = torch.empty_like(Bm)
+        timed_solves(torch, M, Bm, Xm, ws, 1)
+        t, inf, _ = timed_solves(torch, M, Bm, Xm, ws, steps)
+        per_m[mm] = {"s_per_rhs": t / mm, "iters_max": max(i["iters"] for i in inf)}
+        if mm == 16:
+            Xs["fp64"] = Xm[:, :4].cpu().numpy()
+            timed_solves(torch, M, Bm, Xm, ws, 1, mixed=True)
+            tm, im, _ = timed_solves(torch, M, Bm, Xm, ws, steps, mixed=True)
+            Xs["mixed"] = Xm[:, :4].cpu().numpy()
+            mixed = {"s_per_rhs": tm / 16, "speedup_vs_fp64": round(t / tm, 3),
+                     "iters_max": max(i["iters"] for i in im), "outer_max": max(i["outer"] for i in im),
+                     "max_relres": max(i["relres"] for i in im)}
+    t1 = per_m[1]["s_per_rhs"]
+    for mm, d in per_m.items():
+        d["gain_vs_m1"] = round(t1 / d["s_per_rhs"], 3)
+        d["paper_compact_5m_2m3"] = round(est.gain_compact(mm), 3)
+        d["compulsory_bytes_model"] = round(est.gain_compulsory(A.n, A.nnz, mm), 3)
+        d["s_per_rhs"] = round(d["s_per_rhs"], 6)
+    M.close()
+    del ws
+    torch.cuda.empty_cache()
+    return {"per_m_fp64": per_m, "mixed_m16": mixed}, A, Bh, Xs
 
 
 def main():
@@ -464,14 +601,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--m", type=int, default=16)
     ap.add_argument("--quick", action="store_true", help="only the timed solve (for profiling)")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB copy (counter calibration under rocprofv3)")
     ap.add_argument("--solve-only", metavar="WORKLOAD",
                     help="run only --steps solves of WORKLOAD (after one warm-up), for kernel traces")
     ap.add_argument("--mixed", action="store_true", help="with --solve-only: mixed precision")
+    ap.add_argument("--maxit", type=int, default=20000, help="with --solve-only: iteration cap")
     ap.add_argument("--gspmv-only", metavar="MATRIX",
                     help="run only five GSpMV launches per case on MATRIX (counter runs under rocprofv3)")
     args = ap.parse_args()
@@ -485,36 +622,34 @@ def main():
     if args.gspmv_only:
         return gspmv_only(args.gspmv_only)
     if args.solve_only:
-        return solve_only(args.solve_only, args.mixed, args.steps)
+        return solve_only(args.solve_only, args.mixed, args.steps, args.maxit)
 
     import numpy as np
     import torch
 
     import paper_1711_10622_amd as mrhs
-    from paper_1711_10622_amd import estimates as est
     from workloads import configs
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     mrhs.load(build_if_missing=True)
-    wl = configs.WORKLOADS["chan128"]
+    m = 16
+    wl = configs.WORKLOADS[HEADLINE]
     A = wl.matrix()
-    m = args.m
-    Bh = wl.rhs(A.n, 16)
+    Bh = wl.rhs(A.n, m)
     M = mrhs.CsrMatrix.from_csr(A)
-    B = torch.from_numpy(np.ascontiguousarray(Bh[:, :m])).to("cuda")
+    B = torch.from_numpy(Bh).to("cuda")
     X = torch.empty_like(B)
-    ws = torch.empty(max(M.workspace_size(m, mixed=True), M.workspace_size(16)), dtype=torch.uint8,
+    ws = torch.empty(max(M.workspace_size(m, mixed=True), M.workspace_size(m)), dtype=torch.uint8,
                      device="cuda")
-    log(f"workload chan128 n={A.n} nnz={A.nnz} m={m}")
+    log(f"workload {HEADLINE} n={A.n} nnz={A.nnz} m={m}")
 
     if args.warmup:
         timed_solves(torch, M, B, X, ws, args.warmup)
     step_s, infos, trace = timed_solves(torch, M, B, X, ws, args.steps, trace=True)
     dom = dominant_kernel(trace, A.n, A.nnz)
-    X_f64 = X[:, :4].cpu().numpy()  # for the per-RHS error against the oracle
-    log(f"step {step_s * 1e3:.2f} ms, dominant {dom['kernel']} {dom['avg_us']:.1f} us")
-    relres = max(i["relres"] for i in infos)
-    extra = {"iters": [i["iters"] for i in infos], "max_relres": relres,
+    iters = max(i["iters"] for i in infos)
+    log(f"step {step_s * 1e3:.2f} ms, {iters} iterations, dominant {dom['kernel']} {dom['avg_us']:.1f} us")
+    extra = {"iters": [i["iters"] for i in infos], "max_relres": max(i["relres"] for i in infos),
              "kernels": {k: {"launches": v["seen"], "timed": v["launches"],
                              "avg_us": round(v["total_ms"] / v["launches"] * 1e3, 2)}
                          for k, v in trace.items()}}
@@ -522,8 +657,9 @@ def main():
         "metric": METRIC, "value": step_s / m, "unit": "s/RHS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": step_s * 1e3, "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "chan128: stretched-channel pressure Poisson 128x64x64 (periodic x,z; Neumann y; "
-                               "tanh beta=2), FP64 block Jacobi-BiCGStab to 1e-10, x0=0",
+        "config": {"workload": "chan256: stretched-channel pressure Poisson 256x192x256 (periodic x,z; Neumann y; "
+                               "tanh beta=2), m=16 mean-zero U[-1,1) right-hand sides, FP64 block "
+                               "Jacobi-BiCGStab to 1e-10, x0=0",
                    "n": A.n, "nnz": A.nnz, "m": m, "tol": 1e-10},
         "roofline": {"bound": "hbm", "achieved": round(dom["achieved"], 1) if dom["achieved"] else None,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -533,72 +669,49 @@ def main():
     }
 
     if not args.quick:
-        # per-m solve times: speedup per right-hand side vs m = 1, beside the
-        # paper's compact and full traffic models and the compulsory-byte one
-        C = A.nnz / A.n
-        per_m = {}
-        for mm in (1, 2, 4, 8, 16):
-            Bm = torch.from_numpy(np.ascontiguousarray(Bh[:, :mm])).to("cuda")
-            Xm = torch.empty_like(Bm)
-            if mm == m:
-                t, inf = step_s, infos
-            else:
-                timed_solves(torch, M, Bm, Xm, ws, 1)
-                t, inf, _ = timed_solves(torch, M, Bm, Xm, ws, 2)
-            # time per iteration at a fixed count (the paper's methodology):
-            # difference of 200- and 100-iteration runs, so setup cancels
-            t100, _, _ = timed_solves(torch, M, Bm, Xm, ws, 2, tol=1e-300, maxit=100, expect_ok=False)
-            t200, _, _ = timed_solves(torch, M, Bm, Xm, ws, 2, tol=1e-300, maxit=200, expect_ok=False)
-            per_m[mm] = {"s_per_rhs": t / mm, "iters_max": max(i["iters"] for i in inf),
-                         "ms_per_iter": (t200 - t100) / 100 * 1e3}
-            log(f"per-m {mm}: {t * 1e3:.1f} ms, {per_m[mm]['ms_per_iter']:.3f} ms/iter")
-        t1, i1 = per_m[1]["s_per_rhs"], per_m[1]["ms_per_iter"]
-        for mm, d in per_m.items():
-            d["gain_vs_m1"] = round(t1 / d["s_per_rhs"], 3)
-            d["iter_gain_vs_m1"] = round(mm * i1 / d["ms_per_iter"], 3)
-            d["paper_compact_5m_2m3"] = round(est.gain_compact(mm), 3)
-            d["paper_full_C"] = round(est.gain_full(mm, C), 3)
-            d["compulsory_bytes_model"] = round(est.gain_compulsory(A.n, A.nnz, mm), 3)
-            d["s_per_rhs"] = round(d["s_per_rhs"], 6)
-            d["ms_per_iter"] = round(d["ms_per_iter"], 4)
-        extra["per_m_fp64"] = per_m
-        # mixed precision at the benchmark m
+        extra["memory_ceilings"] = memory_ceilings(torch)
+        log(f"memory ceilings: {extra['memory_ceilings']}")
+        # mixed precision on the same block
         timed_solves(torch, M, B, X, ws, 1, mixed=True)
-        tmix, imix, _ = timed_solves(torch, M, B, X, ws, args.steps, mixed=True)
+        Xf = torch.empty_like(B)
+        timed_solves(torch, M, B, Xf, ws, 1)
+        tmix, imix, trmix = timed_solves(torch, M, B, X, ws, 1, mixed=True, trace=True)
+        d = (X - Xf).cpu().numpy()
+        xf = Xf.cpu().numpy()
         extra["mixed"] = {"s_per_rhs": tmix / m, "speedup_vs_fp64": round(step_s / tmix, 3),
                           "iters": [i["iters"] for i in imix], "outer": [i["outer"] for i in imix],
-                          "max_relres": max(i["relres"] for i in imix)}
-        log(f"mixed {tmix * 1e3:.1f} ms")
-        X_mix = X[:, :4].cpu().numpy()
-        del M, ws, B, X
+                          "max_relres": max(i["relres"] for i in imix),
+                          "rel_diff_vs_fp64_solution": [float(np.linalg.norm(d[:, l]) / np.linalg.norm(xf[:, l]))
+                                                        for l in range(m)],
+                          "kernels": {k: {"launches": v["seen"],
+                                          "avg_us": round(v["total_ms"] / v["launches"] * 1e3, 2)}
+                                      for k, v in trmix.items()}}
+        log(f"mixed {tmix * 1e3:.1f} ms ({step_s / tmix:.3f}x)")
+        del Xf, d, xf
+        del ws, B, X
         torch.cuda.empty_cache()
-        extra["gspmv_chan128"] = gspmv_sweep(torch, A, [1, 2, 4, 8, 16], ("f64",), flush=True)
-        log("gspmv chan128 done")
-        extra["cube192_m8"] = solve_pair(torch, "cube192", 8, 2)
+        extra["per_iter_fp64"] = per_iteration(torch, M, Bh, (1, 2, 4, 8, 16))
+        log(f"per iteration: {extra['per_iter_fp64']}")
+        M.close()
+        extra["gspmv_chan256"] = gspmv_sweep(torch, A, list(range(1, 17)), ("f64", "f32"), reps=20)
+        log("gspmv sweep done")
+        legs, A2, Bh2, Xs2 = chan128_legs(torch, 2)
+        extra["chan128"] = legs
+        log(f"chan128: {legs}")
+        extra["cube192_m8"] = solve_pair(torch, "cube192", 8, 1)
         extra["projection_chan128"] = projection_step(torch)
-        log(f"projection: {extra['projection_chan128']}")
-        extra["serving"] = {"offered_5ms_gaps": serving(torch)}
+        extra["serving"] = {"offered_5ms_gaps": serving(torch, n_req=300)}
         cap = extra["serving"]["offered_5ms_gaps"]["served_rhs_per_s"]
         off = extra["serving"]["offered_5ms_gaps"]["offered_rhs_per_s"]
         scale = 0.8 * cap / off
         if scale < 1.0:
-            extra["serving"]["at_0.8x_capacity"] = serving(torch, rate_scale=scale)
+            extra["serving"]["at_0.8x_capacity"] = serving(torch, n_req=600, rate_scale=scale)
         log(f"serving: {extra['serving']}")
-        extra["chan256_m16"] = solve_pair(torch, "chan256", 16, 1)
-        L = configs.MATRICES["chan256"]()
-        extra["gspmv_chan256"] = gspmv_sweep(torch, L, list(range(1, 17)), ("f64", "f32"))
-        log("gspmv chan256 done")
-        del L
+        if not args.no_cpu:
+            extra["chan128"]["error_vs_oracle_first4"] = oracle_error(A2, Bh2, Xs2, 4, 4)
     if not args.no_cpu:
-        result["cpu_baseline"], Xo = cpu_baseline(A, Bh, 4)
+        result["cpu_baseline"] = cpu_baseline(A, Bh, iters, min(host_cores(), m))
         result["cpu_baseline"]["host"] = host_info()
-        # per-RHS relative error of the GPU solutions against the oracle's
-        rel = lambda Xg: [float(np.linalg.norm(Xg[:, l] - Xo[:, l]) / np.linalg.norm(Xo[:, l])) for l in range(4)]
-        extra["error_vs_oracle_first4"] = {"fp64": rel(X_f64)}
-        if not args.quick:
-            extra["error_vs_oracle_first4"]["mixed"] = rel(X_mix)
-        if not args.quick:
-            extra["cpu_gspmv_chan128"] = cpu_gspmv(A, 16, min(16, os.cpu_count() or 1))
     result["extra"] = extra
     print(json.dumps(result), flush=True)
     return 0

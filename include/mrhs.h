@@ -147,8 +147,8 @@ mrhs_status gspmv_ex(mrhs_csr A, int32_t dtype, const void *X, void *Y,
  * 0) of the SplitMix64 generator seeded with MRHS_SHADOW_SEED, i.e. of
  * mix(MRHS_SHADOW_SEED + (i + 1) * 0x9E3779B97F4A7C15).  It is generated
  * where it is used and never stored.  The binary32 inner solves of MRHS_MIXED
- * (short solves restarted at every refinement step) take r^ = their own
- * initial residual.
+ * (short solves restarted at every refinement step) take r^ = the signs (+1,
+ * or -1 for a negative entry) of their own initial residual.
  */
 #define MRHS_SHADOW_SEED 17110622ull
 mrhs_status block_bicgstab(mrhs_csr A, const double *B, double *X, int32_t m,
@@ -279,6 +279,32 @@ mrhs_status projection_rhs(mrhs_grid G, const double *U, const double *V, const 
  */
 mrhs_status projection_correct(mrhs_grid G, double *U, double *V, double *W,
                                const double *P, double tau, int32_t m, void *hip_stream);
+
+/*
+ * Memory ceilings.  Enqueues one streaming pass over a device buffer of
+ * `bytes` (a positive multiple of 16, 16-byte aligned buffers) on hip_stream:
+ * the attainable HBM rates against which the products and vector passes are
+ * judged, since their time is set by the bytes they move (Section 2.3).
+ *   MRHS_PROBE_READ / _READ_NT    read src (plain / nontemporal loads); dst
+ *                                 is a device word that may be written
+ *   MRHS_PROBE_WRITE / _WRITE_NT  write dst (plain / nontemporal stores);
+ *                                 src is unused
+ *   MRHS_PROBE_COPY / _COPY_NT    dst = src (plain / nontemporal loads and
+ *                                 stores); the two must not overlap
+ * EINVAL for an unknown kind, a bad size, NULL or misaligned buffers or
+ * overlapping copies.  Returns when the pass is enqueued; time it with
+ * events on the same stream.
+ */
+enum {
+    MRHS_PROBE_READ = 0,
+    MRHS_PROBE_READ_NT = 1,
+    MRHS_PROBE_WRITE = 2,
+    MRHS_PROBE_WRITE_NT = 3,
+    MRHS_PROBE_COPY = 4,
+    MRHS_PROBE_COPY_NT = 5
+};
+mrhs_status mrhs_stream_probe(int32_t kind, const void *src, void *dst, size_t bytes,
+                              void *hip_stream);
 
 /*
  * Kernel timing.  mrhs_trace_enable(k), k >= 1, clears the statistics and

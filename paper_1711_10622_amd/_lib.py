@@ -29,8 +29,9 @@ EXPORTS = (
     "solve_server_create", "solve_server_register", "solve_server_submit", "solve_server_poll",
     "solve_server_stats", "solve_server_destroy",
     "grid_create", "grid_destroy", "grid_info", "projection_rhs", "projection_correct",
-    "mrhs_trace_enable", "mrhs_trace_read",
+    "mrhs_trace_enable", "mrhs_trace_read", "mrhs_stream_probe",
 )
+PROBE_KINDS = {"read": 0, "read_nt": 1, "write": 2, "write_nt": 3, "copy": 4, "copy_nt": 5}
 
 
 class ColInfo(ctypes.Structure):
@@ -89,6 +90,7 @@ def _declare(lib):
         "projection_correct": [vp, vp, vp, vp, vp, f64, i32, vp],
         "mrhs_trace_enable": [c.c_int],
         "mrhs_trace_read": [c.c_char_p, sz, c.POINTER(sz)],
+        "mrhs_stream_probe": [i32, vp, vp, sz, vp],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)

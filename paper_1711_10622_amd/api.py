@@ -158,6 +158,16 @@ def block_bicgstab(A: CsrMatrix, B, tol=1e-10, maxit=20000, mixed=False, **kw):
     return A.solve(B, tol=tol, maxit=maxit, mixed=mixed, **kw)
 
 
+def stream_probe(kind: str, src, dst, nbytes: int, stream=None):
+    """One streaming pass (``mrhs_stream_probe``) over ``nbytes`` of device
+    tensors ``src``/``dst`` (``kind`` in read, read_nt, write, write_nt, copy,
+    copy_nt); enqueued on ``stream`` (torch's current stream by default)."""
+    lib = _lib.load()
+    sp = ctypes.c_void_p(src.data_ptr()) if src is not None else None
+    _lib.check(lib.mrhs_stream_probe(_lib.PROBE_KINDS[kind], sp, ctypes.c_void_p(dst.data_ptr()), int(nbytes),
+                                     _stream_handle(stream)), "mrhs_stream_probe")
+
+
 def trace_enable(on=True, every: int = 1):
     """Start (clearing old statistics) or stop kernel timing; when on, every
     ``every``-th launch of each kernel class is timed with HIP events."""
