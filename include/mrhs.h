@@ -171,6 +171,25 @@ mrhs_status block_bicgstab_workspace_size(mrhs_csr A, int32_t m, uint32_t flags,
                                           size_t *bytes);
 
 /*
+ * For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): block_bicgstab_ex with
+ * the workspace taken from a fixed device array of the library,
+ * MRHS_NOALLOC_SCRATCH_BYTES long, that every GPU the library runs on holds
+ * until the process ends.  The call allocates no device or pinned host memory
+ * (with kernel timing, mrhs_trace_enable, off).  B and X are caller-owned
+ * device blocks as for block_bicgstab_ex, on the current device, which must
+ * be the matrix's; flags and info as there; the call blocks until the solve
+ * is done.  EINVAL (nothing launched) when block_bicgstab_workspace_size for
+ * (A, m, flags) exceeds MRHS_NOALLOC_SCRATCH_BYTES.  Every call on one GPU
+ * uses that GPU's one array: calls that overlap in time on the same GPU (from
+ * several threads or streams) race and must be serialised by the caller.
+ */
+#define MRHS_NOALLOC_SCRATCH_BYTES 67108864u /* 64 MiB */
+mrhs_status block_bicgstab_noalloc(mrhs_csr A, const double *B, double *X, int32_t m,
+                                   double tol, int32_t maxit, uint32_t flags,
+                                   void *hip_stream, mrhs_col_info *info);
+
+/*
  * Solve server: continuous batching of pressure solves from independent
  * ensemble members (Section 2: every realization needs the same operator with
  * its own right-hand side).  Registered matrices stay resident on the device.

@@ -21,11 +21,12 @@ CSR_NULLSPACE_CONST = 1
 X0_GIVEN, MIXED = 1, 2
 SERVER_MIXED = 1
 SHADOW_SEED = 17110622  # MRHS_SHADOW_SEED: seed of the BiCGStab shadow residual
+NOALLOC_SCRATCH_BYTES = 64 << 20  # MRHS_NOALLOC_SCRATCH_BYTES
 
 # every symbol include/mrhs.h declares
 EXPORTS = (
     "mrhs_last_error", "mrhs_version", "csr_create", "csr_destroy", "csr_info", "gspmv", "gspmv_ex",
-    "block_bicgstab", "block_bicgstab_ex", "block_bicgstab_workspace_size",
+    "block_bicgstab", "block_bicgstab_ex", "block_bicgstab_workspace_size", "block_bicgstab_noalloc",
     "solve_server_create", "solve_server_register", "solve_server_submit", "solve_server_poll",
     "solve_server_stats", "solve_server_destroy",
     "grid_create", "grid_destroy", "grid_info", "projection_rhs", "projection_correct",
@@ -77,6 +78,7 @@ def _declare(lib):
         "block_bicgstab": [vp, vp, vp, i32, f64, i32],
         "block_bicgstab_ex": [vp, vp, vp, i32, f64, i32, u32, vp, sz, vp, c.POINTER(ColInfo)],
         "block_bicgstab_workspace_size": [vp, i32, u32, c.POINTER(sz)],
+        "block_bicgstab_noalloc": [vp, vp, vp, i32, f64, i32, u32, vp, c.POINTER(ColInfo)],
         "solve_server_create": [sz, u32, c.POINTER(vp)],
         "solve_server_register": [vp, vp, c.POINTER(i32)],
         "solve_server_submit": [vp, i32, vp, i32, f64, i32, c.POINTER(c.c_uint64)],

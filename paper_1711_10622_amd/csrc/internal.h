@@ -180,7 +180,10 @@ struct StepTable {
 class Engine {
   public:
     static size_t workspace_bytes(const mrhs_csr_s &A, int32_t m, uint32_t flags);
-    Engine(const mrhs_csr_s &A, int m, uint32_t flags, void *ws, const double *B, double *X, hipStream_t s);
+    // host_ctl: host memory for the mirror of the control block, or null to
+    // allocate pinned memory on the first reset()
+    Engine(const mrhs_csr_s &A, int m, uint32_t flags, void *ws, const double *B, double *X, hipStream_t s,
+           Ctl *host_ctl = nullptr);
     ~Engine();
     Engine(const Engine &) = delete;
     Engine &operator=(const Engine &) = delete;
@@ -204,6 +207,7 @@ class Engine {
     Ctx c_{};
     unsigned *tickets_ = nullptr;
     Ctl *host_ = nullptr;
+    bool own_host_ = false;
     int chunk_ = 16, ndirs_ = kGcrMax, max_outer_ = 500;
     int col_steps_[kMaxM] = {};  // refinement steps of each column since its admission (slot = steps % ndirs)
     double tol_in_ = 0.1;
@@ -227,7 +231,8 @@ struct SolveParams {
 };
 
 size_t solve_workspace_bytes(const mrhs_csr_s &A, int32_t m, uint32_t flags);
+// host_ctl as for Engine (null: pinned memory allocated by the engine)
 mrhs_status block_solve(const mrhs_csr_s &A, const double *B, double *X, const SolveParams &p,
-                        void *ws, size_t ws_bytes, hipStream_t s, mrhs_col_info *info);
+                        void *ws, size_t ws_bytes, hipStream_t s, mrhs_col_info *info, Ctl *host_ctl = nullptr);
 
 } // namespace mrhs

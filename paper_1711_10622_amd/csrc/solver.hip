@@ -348,9 +348,10 @@ size_t Engine::workspace_bytes(const mrhs_csr_s &A, int32_t m, uint32_t flags)
     return layout(A.n, m, flags).total;
 }
 
-Engine::Engine(const mrhs_csr_s &A, int m, uint32_t flags, void *ws, const double *B, double *X, hipStream_t s)
+Engine::Engine(const mrhs_csr_s &A, int m, uint32_t flags, void *ws, const double *B, double *X, hipStream_t s,
+               Ctl *host_ctl)
     : A_(A), m_(m), mixed_((flags & MRHS_MIXED) != 0), nullspace_((A.flags & MRHS_CSR_NULLSPACE_CONST) != 0),
-      s_(s), T_(&table(m))
+      s_(s), T_(&table(m)), host_(host_ctl)
 {
     const Layout L = layout(A.n, m, flags);
     char *base = static_cast<char *>(ws);
@@ -403,7 +404,7 @@ Engine::Engine(const mrhs_csr_s &A, int m, uint32_t flags, void *ws, const doubl
 
 Engine::~Engine()
 {
-    if (host_)
+    if (host_ && own_host_)
         (void)hipHostFree(host_);
 }
 
@@ -414,6 +415,7 @@ mrhs_status Engine::reset()
         if (hipHostMalloc(&q, sizeof(Ctl), hipHostMallocDefault) != hipSuccess)
             return set_error(MRHS_ENOMEM, "pinned host buffer allocation failed");
         host_ = static_cast<Ctl *>(q);
+        own_host_ = true;
     }
     std::memset(host_, 0, sizeof(Ctl));
     for (int c = 0; c < kMaxM; ++c)
@@ -539,13 +541,13 @@ size_t solve_workspace_bytes(const mrhs_csr_s &A, int32_t m, uint32_t flags)
 }
 
 mrhs_status block_solve(const mrhs_csr_s &A, const double *B, double *X, const SolveParams &p, void *ws,
-                        size_t ws_bytes, hipStream_t s, mrhs_col_info *info)
+                        size_t ws_bytes, hipStream_t s, mrhs_col_info *info, Ctl *host_ctl)
 {
     const int m = p.m;
     const size_t need = Engine::workspace_bytes(A, m, p.flags);
     if (ws_bytes < need)
         return set_error(MRHS_EINVAL, "workspace of %zu bytes is smaller than the %zu required", ws_bytes, need);
-    Engine e(A, m, p.flags, ws, B, X, s);
+    Engine e(A, m, p.flags, ws, B, X, s, host_ctl);
     mrhs_status st = e.reset();
     if (st != MRHS_OK)
         return st;
