@@ -143,6 +143,25 @@ def gspmv_part(S, X):
     return Y
 
 
+def gspmv_rect(n_rows, row_ptr, col, val, X):
+    """Y = A X for an n_rows-row CSR whose columns index the rows of X (a
+    rectangular operator: restriction or prolongation), each row summed in
+    storage order; X is an (n_cols, m) block."""
+    lib = _load()
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    if X.ndim == 1:
+        X = X[:, None]
+    m = X.shape[1]
+    Y = np.empty((n_rows, m), dtype=np.float64)
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col, dtype=np.int32)
+    va = np.ascontiguousarray(val, dtype=np.float64)
+    if n_rows:
+        lib.oracle_gspmv(n_rows, _p(rp, ctypes.c_int32), _p(ci, ctypes.c_int32), _p(va, ctypes.c_double), m,
+                         _p(X, ctypes.c_double), _p(Y, ctypes.c_double))
+    return Y
+
+
 def gspmv_rows(A, X, rows, dot2=False):
     """Rows ``rows`` of A X, for sampled checks of products too large to
     recompute whole."""
