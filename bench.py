@@ -554,6 +554,88 @@ def per_iteration(torch, M, Bh, ms, reps=1):
     return out
 
 
+OP_NAMES = {"OpXR": "xr_update", "OpSpmv2": "spmv_omega", "OpSpmv1": "spmv_sigma", "OpResid": "resid",
+            "OpScale": "scale", "OpRestart": "restart", "OpColSum": "colsum", "OpStore": "gspmv",
+            "OpCast": "cast32", "OpGcrZ": "gcr_z", "OpColDots": "gcr_dots", "OpColOrth": "gcr_orth",
+            "OpColUpdate": "gcr_update", "OpFold": "fold", "OpSpmv2P": "amg_omega", "OpXRP": "amg_xr",
+            "OpSForm": "amg_s", "OpVcRes": "vc_resid", "OpVcProl": "vc_prolong", "OpVcSmooth": "vc_smooth",
+            "OpVcStore": "vc_store"}
+
+
+def kernel_class(name):
+    """'void mrhs::k_stream<double, 16, mrhs::OpXR<double, 16> >(...)' -> 'xr_update/f64/m16'."""
+    mo = re.search(r"mrhs::k_(?:gspmv|stream)<(double|float), (\d+), mrhs::(\w+)", name)
+    if not mo:
+        return name.split("(")[0][:60]
+    return f"{OP_NAMES.get(mo.group(3), mo.group(3))}/{'f64' if mo.group(1) == 'double' else 'f32'}/m{mo.group(2)}"
+
+
+def summarize_profiles(out, workload, m):
+    """Markdown summary of the rocprofv3 runs under ``out`` (kernel trace in
+    trace/, FETCH_SIZE and WRITE_SIZE counters in fetch/ and write/, the 1 GiB
+    copy's counters in copy_fetch/ and copy_write/) for a workload of
+    configs.WORKLOADS at block width m."""
+    import csv
+    from workloads import configs
+    A = configs.MATRICES[workload]()
+
+    def rows(sub, suffix):
+        fs = glob.glob(os.path.join(out, sub, "**", f"*{suffix}"), recursive=True)
+        return list(csv.DictReader(open(fs[0]))) if fs else []
+
+    lines = []
+    st = rows("trace", "kernel_stats.csv")
+    if st:
+        lines += ["| kernel | calls | avg us | min us | max us | share % | algorithmic MB | GB/s at avg |",
+                  "|---|---|---|---|---|---|---|---|"]
+        for r in st:
+            cls = kernel_class(r["Name"])
+            parts = cls.split("/")
+            byt = kernel_bytes(parts[0], A.n, A.nnz, int(parts[2][1:]), 8 if parts[1] == "f64" else 4) \
+                if len(parts) == 3 else None
+            avg = float(r["AverageNs"]) / 1e3
+            lines.append(f"| {cls} | {r['Calls']} | {avg:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
+                         f"{float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} | "
+                         f"{byt / 1e6 if byt else '':{'.1f' if byt else ''}} | "
+                         f"{byt / (avg * 1e-6) / 1e9 if byt else '':{'.0f' if byt else ''}} |")
+    cal = {}
+    for c, sub in (("FETCH_SIZE", "copy_fetch"), ("WRITE_SIZE", "copy_write")):
+        vals = [float(r["Counter_Value"]) for r in rows(sub, "counter_collection.csv")
+                if "copyBuffer" in r["Kernel_Name"]]
+        if vals:
+            cal[c] = (1 << 20) / (sum(vals) / len(vals))   # 1 GiB = 1048576 KiB
+    per = {}
+    for c, sub in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
+        for r in rows(sub, "counter_collection.csv"):
+            per.setdefault(kernel_class(r["Kernel_Name"]), {}).setdefault(c, []).append(float(r["Counter_Value"]))
+    traffic = []
+    if per and len(cal) == 2:
+        lines += ["", f"Counter calibration: a plain 1 GiB copy reads FETCH_SIZE x {cal['FETCH_SIZE']:.3f} and "
+                      f"WRITE_SIZE x {cal['WRITE_SIZE']:.3f} = bytes / 1024.", "",
+                  "| kernel | dispatches | FETCH KiB | WRITE KiB | HBM MB (scaled) | algorithmic MB | ratio |",
+                  "|---|---|---|---|---|---|---|"]
+        for cls, d in per.items():
+            if "FETCH_SIZE" not in d or "WRITE_SIZE" not in d or not cls.count("/") == 2:
+                continue
+            f = sum(d["FETCH_SIZE"]) / len(d["FETCH_SIZE"])
+            w = sum(d["WRITE_SIZE"]) / len(d["WRITE_SIZE"])
+            hbm = (f * cal["FETCH_SIZE"] + w * cal["WRITE_SIZE"]) * 1024
+            name, dt, mt = cls.split("/")
+            byt = kernel_bytes(name, A.n, A.nnz, int(mt[1:]), 8 if dt == "f64" else 4)
+            ratio = f"{hbm / byt:.3f}" if byt else ""
+            lines.append(f"| {cls} | {len(d['FETCH_SIZE'])} | {f:.0f} | {w:.0f} | {hbm / 1e6:.1f} | "
+                         f"{byt / 1e6 if byt else '':{'.1f' if byt else ''}} | {ratio} |")
+            traffic.append((cls, int(hbm)))
+    if traffic:
+        lines += ["", "Machine-readable lines for bench.py (used only while the kernel sources hash to this value):",
+                  ""]
+        dig = kernel_sources_digest()
+        for cls, b in traffic:
+            lines.append(f"traffic: kernel={cls} bytes_per_launch={b} sources_sha256={dig}")
+    print("\n".join(lines))
+    return 0
+
+
 def chan128_legs(torch, steps):
     """The 524k-row channel (its matrix, m = 16 block and workspace fit the
     256 MB Infinity Cache): binary64 solve, solves per m with the speedup per
@@ -611,7 +693,11 @@ def main():
     ap.add_argument("--maxit", type=int, default=20000, help="with --solve-only: iteration cap")
     ap.add_argument("--gspmv-only", metavar="MATRIX",
                     help="run only five GSpMV launches per case on MATRIX (counter runs under rocprofv3)")
+    ap.add_argument("--summarize", nargs=3, metavar=("OUTDIR", "WORKLOAD", "M"),
+                    help="print the markdown summary of rocprofv3 runs under OUTDIR (no GPU needed)")
     args = ap.parse_args()
+    if args.summarize:
+        return summarize_profiles(args.summarize[0], args.summarize[1], int(args.summarize[2]))
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
