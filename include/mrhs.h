@@ -300,6 +300,82 @@ mrhs_status projection_correct(mrhs_grid G, double *U, double *V, double *W,
                                const double *P, double tau, int32_t m, void *hip_stream);
 
 /*
+ * Classical algebraic multigrid, the preconditioner of the paper's pressure
+ * solver (BiCGStab with classical AMG, Section 4.1), for blocks of m
+ * right-hand sides: every level's smoothing, restriction and prolongation is
+ * a product over an n_l x m row-interleaved block, so the m columns share
+ * every matrix read of every level.
+ *
+ * Construction (Ruge-Stueben): entries sorted and repeated columns summed;
+ * j != i is a strong connection of row i when -a_ij >= theta max_{k != i}
+ * (-a_ik) > 0; C/F splitting by the first pass of Ruge and Stueben (largest
+ * measure first, smallest index on ties); direct interpolation from the strong
+ * C neighbours; Galerkin coarse operators P^T A P; levels until at most
+ * max_coarse rows, no useful coarsening (none or more than 0.9 of the rows
+ * coarse) or max_levels levels; the coarsest level applies the dense inverse
+ * of A_c (plus s 1 1^T, s = mean diagonal / n_c, for a matrix created with
+ * MRHS_CSR_NULLSPACE_CONST).  V-cycle: one l1-Jacobi sweep
+ * (x <- x + D^-1 (b - A x), D = diag of the rows' absolute sums) before and
+ * one after the coarse correction, from x = 0.
+ */
+typedef struct mrhs_amg_s *mrhs_amg;
+
+/* what amg_level_copy copies */
+enum { MRHS_AMG_OPERATOR = 0, MRHS_AMG_PROLONGATION = 1, MRHS_AMG_SPLIT = 2 };
+
+/*
+ * Build the hierarchy of A on A's device (setup on the host, then upload).
+ * theta <= 0, max_coarse <= 0, max_levels <= 0 select the defaults 0.25,
+ * 256 and 25 (at most 25).  A must outlive the hierarchy.  EINVAL for an
+ * empty matrix, a zero diagonal entry, theta >= 1 or a singular coarsest
+ * operator; ENOMEM / EDEVICE for device failures.
+ */
+mrhs_status amg_create(mrhs_csr A, double theta, int32_t max_coarse,
+                       int32_t max_levels, mrhs_amg *out);
+mrhs_status amg_destroy(mrhs_amg H);
+/* Levels, operator complexity (sum of the levels' nonzeros over A's) and the
+ * device bytes the hierarchy holds (NULL outputs skipped). */
+mrhs_status amg_info(mrhs_amg H, int32_t *levels, double *operator_complexity,
+                     size_t *device_bytes);
+/* Rows of level l, nonzeros of its operator and of its prolongation (0 on the
+ * coarsest level). */
+mrhs_status amg_level(mrhs_amg H, int32_t level, int32_t *rows, int64_t *nnz_a,
+                      int64_t *nnz_p);
+/*
+ * Copy part of level l to host arrays sized by amg_level: MRHS_AMG_OPERATOR
+ * (row_ptr[rows+1], col[nnz_a], val[nnz_a]), MRHS_AMG_PROLONGATION
+ * (row_ptr[rows+1], col[nnz_p], val[nnz_p], columns are coarse rows) or
+ * MRHS_AMG_SPLIT (col[rows] = 1 for C rows, 0 for F rows; row_ptr and val
+ * unused).  Not for the coarsest level's prolongation or splitting (EINVAL).
+ */
+mrhs_status amg_level_copy(mrhs_amg H, int32_t level, int32_t what,
+                           int32_t *row_ptr, int32_t *col, double *val);
+/* Device workspace bytes of amg_vcycle for m columns. */
+mrhs_status amg_vcycle_workspace_size(mrhs_amg H, int32_t m, size_t *bytes);
+/*
+ * X = M^-1 B, one V-cycle from X = 0, for device blocks B, X of m columns
+ * (rows x m row-interleaved binary64), enqueued on hip_stream.  workspace:
+ * device memory of amg_vcycle_workspace_size bytes.  EINVAL when B, X and the
+ * workspace share any byte.
+ */
+mrhs_status amg_vcycle(mrhs_amg H, const double *B, double *X, int32_t m,
+                       void *workspace, size_t ws_bytes, void *hip_stream);
+/* Device workspace bytes of block_bicgstab_amg for m columns. */
+mrhs_status block_bicgstab_amg_workspace_size(mrhs_amg H, int32_t m, size_t *bytes);
+/*
+ * block_bicgstab_ex for the hierarchy's matrix with the V-cycle as right
+ * preconditioner instead of Jacobi (binary64): per column p^ = M^-1 p,
+ * v = A p^, s = r - alpha v, s^ = M^-1 s, t = A s^, x += alpha p^ + omega s^,
+ * with the same stopping tests, true-residual checks, restarts, shadow
+ * residual and per-column outcomes.  flags: MRHS_X0_GIVEN.  workspace NULL:
+ * allocated and freed by the call.
+ */
+mrhs_status block_bicgstab_amg(mrhs_amg H, const double *B, double *X, int32_t m,
+                               double tol, int32_t maxit, uint32_t flags,
+                               void *workspace, size_t ws_bytes, void *hip_stream,
+                               mrhs_col_info *info);
+
+/*
  * Memory ceilings.  Enqueues one streaming pass over a device buffer of
  * `bytes` (a positive multiple of 16, 16-byte aligned buffers) on hip_stream:
  * the attainable HBM rates against which the products and vector passes are

@@ -31,7 +31,10 @@ EXPORTS = (
     "solve_server_stats", "solve_server_destroy",
     "grid_create", "grid_destroy", "grid_info", "projection_rhs", "projection_correct",
     "mrhs_trace_enable", "mrhs_trace_read", "mrhs_stream_probe",
+    "amg_create", "amg_destroy", "amg_info", "amg_level", "amg_level_copy", "amg_vcycle_workspace_size",
+    "amg_vcycle", "block_bicgstab_amg_workspace_size", "block_bicgstab_amg",
 )
+AMG_OPERATOR, AMG_PROLONGATION, AMG_SPLIT = 0, 1, 2
 PROBE_KINDS = {"read": 0, "read_nt": 1, "write": 2, "write_nt": 3, "copy": 4, "copy_nt": 5}
 
 
@@ -93,6 +96,15 @@ def _declare(lib):
         "mrhs_trace_enable": [c.c_int],
         "mrhs_trace_read": [c.c_char_p, sz, c.POINTER(sz)],
         "mrhs_stream_probe": [i32, vp, vp, sz, vp],
+        "amg_create": [vp, f64, i32, i32, c.POINTER(vp)],
+        "amg_destroy": [vp],
+        "amg_info": [vp, c.POINTER(i32), c.POINTER(f64), c.POINTER(sz)],
+        "amg_level": [vp, i32, c.POINTER(i32), c.POINTER(i64), c.POINTER(i64)],
+        "amg_level_copy": [vp, i32, i32, vp, vp, vp],
+        "amg_vcycle_workspace_size": [vp, i32, c.POINTER(sz)],
+        "amg_vcycle": [vp, vp, vp, i32, vp, sz, vp],
+        "block_bicgstab_amg_workspace_size": [vp, i32, c.POINTER(sz)],
+        "block_bicgstab_amg": [vp, vp, vp, i32, f64, i32, u32, vp, sz, vp, c.POINTER(ColInfo)],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)

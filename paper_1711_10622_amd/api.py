@@ -150,6 +150,110 @@ class CsrMatrix:
         return (out.view(-1) if squeeze else out), [i.as_dict() for i in infos], st
 
 
+class AmgHierarchy:
+    """Classical AMG hierarchy of a resident matrix (``amg_create``)."""
+
+    def __init__(self, M: CsrMatrix, theta=0.0, max_coarse=0, max_levels=0):
+        lib = _lib.load()
+        self._lib = lib
+        self.M = M
+        h = ctypes.c_void_p()
+        _lib.check(lib.amg_create(M.handle, float(theta), int(max_coarse), int(max_levels), ctypes.byref(h)),
+                   "amg_create")
+        self._h = h
+        lv, oc, by = ctypes.c_int32(), ctypes.c_double(), ctypes.c_size_t()
+        _lib.check(lib.amg_info(h, ctypes.byref(lv), ctypes.byref(oc), ctypes.byref(by)), "amg_info")
+        self.levels, self.operator_complexity, self.device_bytes = int(lv.value), float(oc.value), int(by.value)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def level(self, l):
+        """(rows, nonzeros of A_l, nonzeros of P_l)."""
+        n, na, npz = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
+        _lib.check(self._lib.amg_level(self._h, int(l), ctypes.byref(n), ctypes.byref(na), ctypes.byref(npz)),
+                   "amg_level")
+        return int(n.value), int(na.value), int(npz.value)
+
+    def level_arrays(self, l, what="A"):
+        """Host copies of level l: ``"A"`` or ``"P"`` -> (row_ptr, col, val); ``"cf"`` -> C/F marks."""
+        n, na, npz = self.level(l)
+        if what == "cf":
+            cf = np.empty(n, dtype=np.int32)
+            _lib.check(self._lib.amg_level_copy(self._h, int(l), _lib.AMG_SPLIT, None, cf.ctypes.data, None),
+                       "amg_level_copy")
+            return cf
+        nz = na if what == "A" else npz
+        rp = np.empty(n + 1, dtype=np.int32)
+        ci = np.empty(max(nz, 1), dtype=np.int32)
+        va = np.empty(max(nz, 1), dtype=np.float64)
+        kind = _lib.AMG_OPERATOR if what == "A" else _lib.AMG_PROLONGATION
+        _lib.check(self._lib.amg_level_copy(self._h, int(l), kind, rp.ctypes.data, ci.ctypes.data, va.ctypes.data),
+                   "amg_level_copy")
+        return rp, ci[:nz], va[:nz]
+
+    def vcycle(self, B, out=None, workspace=None, stream=None):
+        """X = M^-1 B (one V-cycle) for an (n, m) float64 block."""
+        torch = _torch()
+        m = 1 if B.dim() == 1 else int(B.shape[1])
+        Bb = _check_block(B, self.M.n, m, torch.float64, "B")
+        if out is None:
+            out = torch.empty_like(Bb)
+        Xb = _check_block(out, self.M.n, m, torch.float64, "out")
+        need = ctypes.c_size_t()
+        _lib.check(self._lib.amg_vcycle_workspace_size(self._h, m, ctypes.byref(need)))
+        if workspace is None:
+            workspace = torch.empty(max(need.value, 1), dtype=torch.uint8, device=Bb.device)
+        _lib.check(self._lib.amg_vcycle(self._h, ctypes.c_void_p(Bb.data_ptr()), ctypes.c_void_p(Xb.data_ptr()), m,
+                                        ctypes.c_void_p(workspace.data_ptr()), need.value, _stream_handle(stream)),
+                   "amg_vcycle")
+        return out
+
+    def workspace_size(self, m) -> int:
+        b = ctypes.c_size_t()
+        _lib.check(self._lib.block_bicgstab_amg_workspace_size(self._h, int(m), ctypes.byref(b)))
+        return int(b.value)
+
+    def solve(self, B, tol=1e-10, maxit=1000, X0=None, out=None, workspace=None, stream=None):
+        """AMG-preconditioned block BiCGStab (``block_bicgstab_amg``); returns
+        ``(X, infos, status)`` like :meth:`CsrMatrix.solve`."""
+        torch = _torch()
+        m = 1 if B.dim() == 1 else int(B.shape[1])
+        Bb = _check_block(B, self.M.n, m, torch.float64, "B")
+        flags = 0
+        if X0 is not None:
+            X0b = _check_block(X0, self.M.n, m, torch.float64, "X0")
+            out = X0b.clone() if out is None else out.copy_(X0b)
+            flags |= _lib.X0_GIVEN
+        elif out is None:
+            out = torch.empty_like(Bb)
+        Xb = _check_block(out, self.M.n, m, torch.float64, "out")
+        need = self.workspace_size(m)
+        if workspace is None:
+            workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=Bb.device)
+        elif workspace.numel() * workspace.element_size() < need:
+            raise ValueError(f"workspace needs {need} bytes")
+        infos = (_lib.ColInfo * m)()
+        st = self._lib.block_bicgstab_amg(self._h, ctypes.c_void_p(Bb.data_ptr()), ctypes.c_void_p(Xb.data_ptr()), m,
+                                          float(tol), int(maxit), flags, ctypes.c_void_p(workspace.data_ptr()),
+                                          need, _stream_handle(stream), infos)
+        if st not in (_lib.OK, _lib.ENOCONV, _lib.EBREAKDOWN):
+            _lib.check(st, "block_bicgstab_amg")
+        return out, [i.as_dict() for i in infos], st
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.amg_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def gspmv(A: CsrMatrix, X, out=None, stream=None):
     return A.gspmv(X, out=out, stream=stream)
 

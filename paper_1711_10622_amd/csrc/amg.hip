@@ -1,0 +1,788 @@
+// Classical AMG on the device: the hierarchy built by amg_setup.hip is
+// uploaded once per matrix; a V-cycle for an n x m row-interleaved block runs
+// level by level as products over the tile loops of core.h, so the m
+// right-hand sides share every matrix read of every level; BiCGStab
+// preconditioned by it (the paper's solver, Section 4.1) reuses the block
+// engine's per-column control (ops.h).
+//
+// V-cycle at level l for right-hand side b (one l1-Jacobi sweep before and
+// after the coarse correction, x = 0 at the start, D = D_l1):
+//   r = b - (A D^-1) b          first sweep from x = 0 folded into A D^-1
+//   b_c = R r                   restriction
+//   x_c = V-cycle at level l+1  (the coarsest level applies its dense inverse)
+//   t = D^-1 b + P x_c          first sweep's x plus the coarse correction
+//   x = t + D^-1 (b - A t)      post-smoothing
+// Four products per level, each reading its matrix once for all m columns.
+//
+// Preconditioned iteration (right preconditioning, M^-1 = V-cycle): for every
+// running column
+//   p^ = M^-1 p;  v = A p^;  sigma = (r^, v);  alpha = rho / sigma
+//   s = r - alpha v;  s^ = M^-1 s;  t = A s^;  omega = (t, s) / (t, t)
+//   x += alpha p^ + omega s^;  r = s - omega t;  p = r + beta (p - omega v)
+// with the same fused dots, device-side scalars, stopping tests, true-residual
+// checks and restarts as the Jacobi-preconditioned block solve.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <vector>
+
+#include "amg.h"
+#include "internal.h"
+
+#define MRHS_API extern "C" __attribute__((visibility("default")))
+
+namespace mrhs {
+namespace {
+
+// Lanes on in a V-cycle product: every column (ctl null) or the running ones.
+template <int M>
+__device__ __forceinline__ bool lane_running(const Ctl *ctl, int g)
+{
+    using S = Shape<double, M>;
+    if (!ctl)
+        return true;
+    bool on = false;
+#pragma unroll
+    for (int q = 0; q < S::VW; ++q) {
+        const int c = g * S::VW + q;
+        on = on || (c < M && ctl->status[c] == COL_RUN);
+    }
+    return on;
+}
+
+struct VcLane {
+    bool on;
+};
+
+// Y = sum (restriction, coarsest dense inverse)
+template <int M>
+struct OpVcStore {
+    static constexpr const char *kName = "vc_store";
+    using S = Shape<double, M>;
+    static constexpr int NDOT = 0;
+    const double *X;
+    double *Y;
+    const Ctl *ctl;
+    using Lane = VcLane;
+    __device__ Lane lane(int g) const { return {lane_running<M>(ctl, g)}; }
+    __device__ __forceinline__ void gather(const Lane &, int32_t c, int g, double *x) const { ld<double, M>(X, c, g, x); }
+    __device__ __forceinline__ void row(const Lane &, int32_t i, int g, const double *sum,
+                                        Acc<double, S::VW, NDOT> &) const
+    {
+        st<double, M>(Y, i, g, sum);
+    }
+    __device__ void finish(const double *) const {}
+};
+
+// Y = U - sum (residual; with A D^-1 and X = U the residual after the first
+// sweep from zero)
+template <int M>
+struct OpVcRes {
+    static constexpr const char *kName = "vc_resid";
+    using S = Shape<double, M>;
+    static constexpr int NDOT = 0;
+    const double *X, *U;
+    double *Y;
+    const Ctl *ctl;
+    using Lane = VcLane;
+    __device__ Lane lane(int g) const { return {lane_running<M>(ctl, g)}; }
+    __device__ __forceinline__ void gather(const Lane &, int32_t c, int g, double *x) const { ld<double, M>(X, c, g, x); }
+    __device__ __forceinline__ void row(const Lane &, int32_t i, int g, const double *sum,
+                                        Acc<double, S::VW, NDOT> &) const
+    {
+        double u[S::VW];
+        ld<double, M>(U, i, g, u);
+#pragma unroll
+        for (int q = 0; q < S::VW; ++q)
+            u[q] = u[q] - sum[q];
+        st<double, M>(Y, i, g, u);
+    }
+    __device__ void finish(const double *) const {}
+};
+
+// Y = dinv_i U_i + sum (the first sweep's x plus the prolongated correction)
+template <int M>
+struct OpVcProl {
+    static constexpr const char *kName = "vc_prolong";
+    using S = Shape<double, M>;
+    static constexpr int NDOT = 0;
+    const double *X, *U, *dinv;
+    double *Y;
+    const Ctl *ctl;
+    using Lane = VcLane;
+    __device__ Lane lane(int g) const { return {lane_running<M>(ctl, g)}; }
+    __device__ __forceinline__ void gather(const Lane &, int32_t c, int g, double *x) const { ld<double, M>(X, c, g, x); }
+    __device__ __forceinline__ void row(const Lane &, int32_t i, int g, const double *sum,
+                                        Acc<double, S::VW, NDOT> &) const
+    {
+        double u[S::VW];
+        ld<double, M>(U, i, g, u);
+        const double d = dinv[i];
+#pragma unroll
+        for (int q = 0; q < S::VW; ++q)
+            u[q] = d * u[q] + sum[q];
+        st<double, M>(Y, i, g, u);
+    }
+    __device__ void finish(const double *) const {}
+};
+
+// Y = T_i + dinv_i (U_i - sum), sum = (A T)_i (post-smoothing sweep)
+template <int M>
+struct OpVcSmooth {
+    static constexpr const char *kName = "vc_smooth";
+    using S = Shape<double, M>;
+    static constexpr int NDOT = 0;
+    const double *T, *U, *dinv;
+    double *Y;
+    const Ctl *ctl;
+    using Lane = VcLane;
+    __device__ Lane lane(int g) const { return {lane_running<M>(ctl, g)}; }
+    __device__ __forceinline__ void gather(const Lane &, int32_t c, int g, double *x) const { ld<double, M>(T, c, g, x); }
+    __device__ __forceinline__ void row(const Lane &, int32_t i, int g, const double *sum,
+                                        Acc<double, S::VW, NDOT> &) const
+    {
+        double t[S::VW], u[S::VW];
+        ld<double, M>(T, i, g, t);
+        ld<double, M>(U, i, g, u);
+        const double d = dinv[i];
+#pragma unroll
+        for (int q = 0; q < S::VW; ++q)
+            t[q] = t[q] + d * (u[q] - sum[q]);
+        st<double, M>(Y, i, g, t);
+    }
+    __device__ void finish(const double *) const {}
+};
+
+// s = r - alpha v for the running columns (the V-cycle's input)
+template <int M>
+struct OpSForm {
+    static constexpr const char *kName = "amg_s";
+    using S = Shape<double, M>;
+    static constexpr int NDOT = 0;
+    const double *r, *v;
+    double *s;
+    Ctl *ctl;
+    Kry<double> *kry;
+    int32_t ldp;  // row stride of r and v
+    struct Lane {
+        bool on;
+        double alpha[S::VW];
+    };
+    __device__ Lane lane(int g) const
+    {
+        Lane ln;
+        const RunLane<double, M> rl = run_lane<double, M>(ctl, g);
+        ln.on = rl.on;
+#pragma unroll
+        for (int q = 0; q < S::VW; ++q)
+            ln.alpha[q] = g * S::VW + q < M ? kry->alpha[g * S::VW + q] : 0.0;
+        return ln;
+    }
+    __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, Acc<double, S::VW, NDOT> &) const
+    {
+        double rr[S::VW], vv[S::VW];
+        ld<double, M>(r, i, g, rr, ldp);
+        ld<double, M>(v, i, g, vv, ldp);
+#pragma unroll
+        for (int q = 0; q < S::VW; ++q)
+            rr[q] = rr[q] - ln.alpha[q] * vv[q];
+        st<double, M>(s, i, g, rr);
+    }
+    __device__ void finish(const double *) const {}
+};
+
+// t = A s^ with s^ = M^-1 s gathered, s read from its block; sums and the
+// per-column decisions of the Jacobi iteration's omega pass.
+template <int M>
+struct OpSpmv2P : OpSpmv2<double, M> {
+    static constexpr const char *kName = "amg_omega";
+    static constexpr int GATHERED = 1;
+    using Base = OpSpmv2<double, M>;
+    using S = Shape<double, M>;
+    using Lane = typename Base::Lane;
+    const double *sh;  // M^-1 s, gathered
+    const double *sv;  // s
+    __device__ __forceinline__ void gather(const Lane &, int32_t c, int g, double *x) const { ld<double, M>(sh, c, g, x); }
+    __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, const double *sum,
+                                        Acc<double, S::VW, Base::NDOT> &acc) const
+    {
+        double s[S::VW], h[S::VW];
+        ld<double, M>(sv, i, g, s);
+        shadow_row<double, M>(nullptr, i, g, h);
+        st<double, M>(this->t, i, g, sum);
+#pragma unroll
+        for (int q = 0; q < S::VW; ++q) {
+            if (ln.act[q]) {
+                acc.a[0][q] += sum[q] * s[q];
+                acc.a[1][q] += sum[q] * sum[q];
+                acc.a[2][q] += s[q] * s[q];
+                acc.a[3][q] += h[q] * sum[q];
+            }
+        }
+    }
+};
+
+// x += alpha p^ + omega s^;  r = s - omega t;  p = r + beta (p - omega v);
+// sums (r^, r), (r, r); the per-column decisions of the Jacobi update pass.
+template <int M>
+struct OpXRP : OpXR<double, M> {
+    static constexpr const char *kName = "amg_xr";
+    using Base = OpXR<double, M>;
+    using S = Shape<double, M>;
+    using Lane = typename Base::Lane;
+    const double *ph, *sh, *sv;
+    __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, Acc<double, S::VW, Base::NDOT> &acc) const
+    {
+        double xx[S::VW], rr[S::VW], pp[S::VW], vv[S::VW], tt[S::VW], a[S::VW], b[S::VW], s[S::VW], hh[S::VW];
+        ld<double, M>(this->y, i, g, xx);
+        ld<double, M>(this->r, i, g, rr, this->ldp);
+        ld<double, M>(this->p, i, g, pp);
+        ld<double, M>(this->v, i, g, vv, this->ldp);
+        ld<double, M>(this->t, i, g, tt);
+        ld<double, M>(ph, i, g, a);
+        ld<double, M>(sh, i, g, b);
+        ld<double, M>(sv, i, g, s);
+        shadow_row<double, M>(nullptr, i, g, hh);
+#pragma unroll
+        for (int q = 0; q < S::VW; ++q) {
+            if (ln.act[q]) {
+                rr[q] = s[q];
+                if (ln.use_w[q]) {
+                    xx[q] = xx[q] + (ln.alpha[q] * a[q] + ln.omega[q] * b[q]);
+                    rr[q] = s[q] - ln.omega[q] * tt[q];
+                    pp[q] = rr[q] + ln.beta[q] * (pp[q] - ln.omega[q] * vv[q]);
+                } else {
+                    xx[q] = xx[q] + ln.alpha[q] * a[q];
+                }
+                acc.a[0][q] += hh[q] * rr[q];
+                acc.a[1][q] += rr[q] * rr[q];
+            }
+        }
+        st<double, M>(this->y, i, g, xx);
+        st<double, M>(this->r, i, g, rr, this->ldp);
+        st<double, M>(this->p, i, g, pp);
+    }
+};
+
+// ---- V-cycle buffers: for every level but the coarsest r_l and t_l, for
+// every level but the finest b_l and x_l, each n_l x m binary64
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct VcBufs {
+    double *r[kAmgMaxLevels], *t[kAmgMaxLevels], *b[kAmgMaxLevels], *x[kAmgMaxLevels];
+};
+
+size_t vc_layout(const AmgDev &H, int32_t m, char *base, VcBufs *out)
+{
+    size_t off = 0;
+    auto take = [&](int32_t n) {
+        double *p = base ? reinterpret_cast<double *>(base + off) : nullptr;
+        off = align_up(off + sizeof(double) * static_cast<size_t>(n) * m);
+        return p;
+    };
+    VcBufs v{};
+    for (int l = 0; l < H.nlev; ++l) {
+        const int32_t n = H.lev[l].n;
+        if (l + 1 < H.nlev) {
+            v.r[l] = take(n);
+            v.t[l] = take(n);
+        }
+        if (l > 0) {
+            v.b[l] = take(n);
+            v.x[l] = take(n);
+        }
+    }
+    if (out)
+        *out = v;
+    return off;
+}
+
+template <int M>
+hipError_t vcycle(const AmgDev &H, const double *b, double *x, char *ws, const Ctl *ctl, hipStream_t s)
+{
+    VcBufs v;
+    vc_layout(H, M, ws, &v);
+    const RedBufs<double> none{nullptr, nullptr, nullptr};
+    const int L = H.nlev;
+    v.b[0] = const_cast<double *>(b);
+    v.x[0] = x;
+    hipError_t e;
+    for (int l = 0; l + 1 < L; ++l) {
+        const AmgLevelDev &lv = H.lev[l];
+        if ((e = launch_gspmv<double, M>(lv.Ah, OpVcRes<M>{v.b[l], v.b[l], v.r[l], ctl}, none, s)) != hipSuccess)
+            return e;
+        if ((e = launch_gspmv<double, M>(lv.R, OpVcStore<M>{v.r[l], v.b[l + 1], ctl}, none, s)) != hipSuccess)
+            return e;
+    }
+    if ((e = launch_gspmv<double, M>(H.cinv, OpVcStore<M>{v.b[L - 1], v.x[L - 1], ctl}, none, s)) != hipSuccess)
+        return e;
+    for (int l = L - 2; l >= 0; --l) {
+        const AmgLevelDev &lv = H.lev[l];
+        if ((e = launch_gspmv<double, M>(lv.P, OpVcProl<M>{v.x[l + 1], v.b[l], lv.dl1_inv, v.t[l], ctl}, none, s)) !=
+            hipSuccess)
+            return e;
+        if ((e = launch_gspmv<double, M>(lv.A, OpVcSmooth<M>{v.t[l], v.b[l], lv.dl1_inv, v.x[l], ctl}, none, s)) !=
+            hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
+#define AMG_TRY(expr)           \
+    do {                        \
+        hipError_t e_ = (expr); \
+        if (e_ != hipSuccess)   \
+            return e_;          \
+    } while (0)
+
+template <int M>
+struct AmgSteps {
+    static CsrView<double> A(const Ctx &c) { return c.amg->lev[0].A; }
+    static hipError_t start(Ctx &c, uint32_t cmask, bool x0)
+    {
+        if (!x0)
+            AMG_TRY((launch_stream<double, M>(
+                c.n, OpScale<M>{c.X, c.A->diag, c.A->dinv, c.ctl, SC_ZERO, cmask}, c.rb64, c.s)));
+        return launch_gspmv<double, M>(A(c), OpResid<M>{c.X, c.B, c.r, c.p, nullptr, c.ctl, c.kry64, RES_SETUP, 0u, 0, c.ldp64},
+                                       c.rb64, c.s);
+    }
+    static hipError_t iterate(Ctx &c, int k)
+    {
+        for (int it = 0; it < k; ++it) {
+            AMG_TRY(vcycle<M>(*c.amg, c.p, c.ph, c.vcws, c.ctl, c.s));
+            AMG_TRY((launch_gspmv<double, M>(A(c), OpSpmv1<double, M>{c.ph, c.v, nullptr, c.ctl, c.kry64, c.ldp64},
+                                              c.rb64, c.s)));
+            AMG_TRY((launch_stream<double, M>(c.n, OpSForm<M>{c.r, c.v, c.sv, c.ctl, c.kry64, c.ldp64}, c.rb64, c.s)));
+            AMG_TRY(vcycle<M>(*c.amg, c.sv, c.sh, c.vcws, c.ctl, c.s));
+            OpSpmv2P<M> om{};
+            om.r = c.r;
+            om.v = c.v;
+            om.sgn = nullptr;
+            om.t = c.t;
+            om.ctl = c.ctl;
+            om.kry = c.kry64;
+            om.ldp = c.ldp64;
+            om.sh = c.sh;
+            om.sv = c.sv;
+            AMG_TRY((launch_gspmv<double, M>(A(c), om, c.rb64, c.s)));
+            OpXRP<M> up{};
+            up.y = c.X;
+            up.r = c.r;
+            up.p = c.p;
+            up.v = c.v;
+            up.t = c.t;
+            up.sgn = nullptr;
+            up.ctl = c.ctl;
+            up.kry = c.kry64;
+            up.ldp = c.ldp64;
+            up.ph = c.ph;
+            up.sh = c.sh;
+            up.sv = c.sv;
+            AMG_TRY((launch_stream<double, M>(c.n, up, c.rb64, c.s)));
+        }
+        return hipSuccess;
+    }
+    static hipError_t check(Ctx &c)
+    {
+        AMG_TRY((launch_gspmv<double, M>(A(c), OpResid<M>{c.X, c.B, c.t, nullptr, nullptr, c.ctl, c.kry64, RES_CHECK, 0u},
+                                          c.rb64, c.s)));
+        return launch_stream<double, M>(c.n, OpRestart<double, M>{c.t, c.r, c.p, c.ctl, c.ldp64}, c.rb64, c.s);
+    }
+    static hipError_t finish(Ctx &c, uint32_t cmask, bool nullspace)
+    {
+        AMG_TRY((launch_stream<double, M>(
+            c.n, OpScale<M>{c.X, c.A->diag, c.A->dinv, c.ctl, SC_FIX_ZERO, cmask}, c.rb64, c.s)));
+        if (nullspace) {
+            AMG_TRY((launch_stream<double, M>(c.n, OpColSum<M>{c.X, c.ctl, cmask}, c.rb64, c.s)));
+            AMG_TRY((launch_stream<double, M>(
+                c.n, OpScale<M>{c.X, c.A->diag, c.A->dinv, c.ctl, SC_SUB_MEAN, cmask}, c.rb64, c.s)));
+        }
+        return launch_gspmv<double, M>(A(c), OpResid<M>{c.X, c.B, nullptr, nullptr, nullptr, c.ctl, c.kry64, RES_FINAL, cmask},
+                                       c.rb64, c.s);
+    }
+};
+
+struct MakeAmgTable {
+    template <int M>
+    AmgStepTable operator()() const
+    {
+        return {&AmgSteps<M>::start, &AmgSteps<M>::iterate, &AmgSteps<M>::check, &AmgSteps<M>::finish};
+    }
+};
+
+struct VcLaunch {
+    const AmgDev *H;
+    const double *b;
+    double *x;
+    char *ws;
+    hipStream_t s;
+    template <int M>
+    hipError_t operator()() const
+    {
+        return vcycle<M>(*H, b, x, ws, nullptr, s);
+    }
+};
+
+} // namespace
+
+const AmgStepTable &amg_table(int m)
+{
+    static const AmgStepTable tables[kMaxM + 1] = {
+        {},
+        MakeAmgTable{}.operator()<1>(),  MakeAmgTable{}.operator()<2>(),  MakeAmgTable{}.operator()<3>(),
+        MakeAmgTable{}.operator()<4>(),  MakeAmgTable{}.operator()<5>(),  MakeAmgTable{}.operator()<6>(),
+        MakeAmgTable{}.operator()<7>(),  MakeAmgTable{}.operator()<8>(),  MakeAmgTable{}.operator()<9>(),
+        MakeAmgTable{}.operator()<10>(), MakeAmgTable{}.operator()<11>(), MakeAmgTable{}.operator()<12>(),
+        MakeAmgTable{}.operator()<13>(), MakeAmgTable{}.operator()<14>(), MakeAmgTable{}.operator()<15>(),
+        MakeAmgTable{}.operator()<16>(),
+    };
+    return tables[m];
+}
+
+size_t amg_vcycle_bytes(const AmgDev &H, int32_t m) { return vc_layout(H, m, nullptr, nullptr); }
+
+} // namespace mrhs
+
+// ---- the hierarchy handle ---------------------------------------------------
+struct mrhs_amg_s {
+    mrhs_csr A = nullptr;
+    int device = 0;
+    mrhs::AmgDev dev;
+    std::vector<std::vector<int8_t>> cf;  // C/F marks of every level but the coarsest
+    std::vector<void *> allocs;
+    size_t bytes = 0;
+    double op_complexity = 0.0;
+};
+
+namespace mrhs {
+namespace {
+
+constexpr size_t kPadElems = 4;  // zero padding past the nonzeros (whole-vector tile loads)
+
+template <typename T>
+T *upload(mrhs_amg_s *H, const T *src, size_t count, size_t pad, hipError_t *err)
+{
+    void *p = nullptr;
+    const size_t bytes = sizeof(T) * (count + pad);
+    if (*err != hipSuccess)
+        return nullptr;
+    if ((*err = hipMalloc(&p, std::max<size_t>(bytes, sizeof(T)))) != hipSuccess)
+        return nullptr;
+    H->allocs.push_back(p);
+    H->bytes += bytes;
+    if (pad && (*err = hipMemset(static_cast<T *>(p) + count, 0, sizeof(T) * pad)) != hipSuccess)
+        return nullptr;
+    if (count && (*err = hipMemcpy(p, src, sizeof(T) * count, hipMemcpyHostToDevice)) != hipSuccess)
+        return nullptr;
+    return static_cast<T *>(p);
+}
+
+int32_t median_reach(const amg::HostCsr &A)
+{
+    if (A.nr == 0)
+        return 0;
+    std::vector<int32_t> reach(A.nr, 0);
+    for (int32_t i = 0; i < A.nr; ++i)
+        for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
+            reach[i] = std::max(reach[i], A.ci[k] - i);
+    std::nth_element(reach.begin(), reach.begin() + A.nr / 2, reach.end());
+    return reach[A.nr / 2];
+}
+
+CsrView<double> upload_csr(mrhs_amg_s *H, const amg::HostCsr &C, const std::vector<double> *vals, int32_t reach,
+                           hipError_t *err)
+{
+    CsrView<double> v{};
+    v.rp = upload(H, C.rp.data(), C.rp.size(), 0, err);
+    v.ci = upload(H, C.ci.data(), C.ci.size(), kPadElems, err);
+    v.va = upload(H, (vals ? vals : &C.va)->data(), C.va.size(), kPadElems, err);
+    v.n = C.nr;
+    v.reach = reach;
+    return v;
+}
+
+void free_amg(mrhs_amg_s *H)
+{
+    if (!H)
+        return;
+    for (void *p : H->allocs)
+        (void)hipFree(p);
+    delete H;
+}
+
+} // namespace
+} // namespace mrhs
+
+using namespace mrhs;
+
+MRHS_API mrhs_status amg_create(mrhs_csr A, double theta, int32_t max_coarse, int32_t max_levels, mrhs_amg *out)
+{
+    clear_error();
+    if (!out)
+        return set_error(MRHS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!A)
+        return set_error(MRHS_EINVAL, "matrix handle is NULL");
+    if (A->n == 0)
+        return set_error(MRHS_EINVAL, "empty matrix");
+    if (A->zero_diag)
+        return set_error(MRHS_EINVAL, "the matrix has a zero diagonal entry");
+    amg::Params prm;
+    if (theta > 0.0) {
+        if (!(theta < 1.0))
+            return set_error(MRHS_EINVAL, "theta = %g outside (0, 1)", theta);
+        prm.theta = theta;
+    }
+    if (max_coarse > 0)
+        prm.max_coarse = max_coarse;
+    if (max_levels > 0)
+        prm.max_levels = std::min(max_levels, kAmgMaxLevels);
+    // the matrix as uploaded (host copy for the setup)
+    const int32_t n = A->n;
+    std::vector<int32_t> rp(static_cast<size_t>(n) + 1), ci(static_cast<size_t>(A->nnz));
+    std::vector<double> va(static_cast<size_t>(A->nnz));
+    hipError_t e = hipSuccess;
+    if ((e = hipMemcpy(rp.data(), A->rp, sizeof(int32_t) * rp.size(), hipMemcpyDeviceToHost)) != hipSuccess ||
+        (A->nnz && (e = hipMemcpy(ci.data(), A->ci, sizeof(int32_t) * ci.size(), hipMemcpyDeviceToHost)) != hipSuccess) ||
+        (A->nnz && (e = hipMemcpy(va.data(), A->val, sizeof(double) * va.size(), hipMemcpyDeviceToHost)) != hipSuccess))
+        return set_error(MRHS_EDEVICE, "matrix download failed: %s", hipGetErrorString(e));
+    amg::HostHierarchy HH;
+    const char *why = nullptr;
+    if (!amg::setup(n, rp.data(), ci.data(), va.data(), (A->flags & MRHS_CSR_NULLSPACE_CONST) != 0, prm, &HH, &why))
+        return set_error(MRHS_EINVAL, "%s", why ? why : "AMG setup failed");
+    rp.clear();
+    ci.clear();
+    va.clear();
+    auto *H = new (std::nothrow) mrhs_amg_s();
+    if (!H)
+        return set_error(MRHS_ENOMEM, "host allocation failed");
+    H->A = A;
+    H->device = A->device;
+    const int L = static_cast<int>(HH.levels.size());
+    H->dev.nlev = L;
+    int64_t nz_all = 0;
+    for (int l = 0; l < L; ++l) {
+        const amg::HostLevel &hl = HH.levels[l];
+        AmgLevelDev &d = H->dev.lev[l];
+        d.n = hl.A.nr;
+        d.nnz_a = hl.A.nnz();
+        nz_all += d.nnz_a;
+        const int32_t reach = median_reach(hl.A);
+        d.A = upload_csr(H, hl.A, nullptr, reach, &e);
+        d.dl1_inv = upload(H, hl.dl1_inv.data(), hl.dl1_inv.size(), 0, &e);
+        if (l + 1 < L) {
+            std::vector<double> vah(hl.A.va.size());
+            for (int32_t i = 0; i < hl.A.nr; ++i)
+                for (int32_t k = hl.A.rp[i]; k < hl.A.rp[i + 1]; ++k)
+                    vah[k] = hl.A.va[k] * hl.dl1_inv[hl.A.ci[k]];
+            d.Ah = upload_csr(H, hl.A, &vah, reach, &e);
+            d.P = upload_csr(H, hl.P, nullptr, 0, &e);
+            d.R = upload_csr(H, hl.R, nullptr, 0, &e);
+            d.nnext = hl.P.nc;
+            d.nnz_p = hl.P.nnz();
+            H->cf.push_back(hl.cf);
+        }
+        if (e != hipSuccess)
+            break;
+    }
+    if (e == hipSuccess) {
+        const int32_t nc = HH.levels.back().A.nr;
+        amg::HostCsr C;
+        C.nr = C.nc = nc;
+        C.rp.resize(static_cast<size_t>(nc) + 1);
+        C.ci.resize(static_cast<size_t>(nc) * nc);
+        for (int32_t i = 0; i <= nc; ++i)
+            C.rp[i] = i * nc;
+        for (int32_t i = 0; i < nc; ++i)
+            for (int32_t j = 0; j < nc; ++j)
+                C.ci[static_cast<size_t>(i) * nc + j] = j;
+        C.va = HH.coarse_inv;
+        H->dev.cinv = upload_csr(H, C, nullptr, 0, &e);
+    }
+    if (e != hipSuccess) {
+        free_amg(H);
+        (void)hipGetLastError();
+        return set_error(e == hipErrorOutOfMemory ? MRHS_ENOMEM : MRHS_EDEVICE, "AMG upload failed: %s",
+                         hipGetErrorString(e));
+    }
+    H->op_complexity = static_cast<double>(nz_all) / static_cast<double>(std::max<int64_t>(HH.levels[0].A.nnz(), 1));
+    *out = H;
+    return MRHS_OK;
+}
+
+MRHS_API mrhs_status amg_destroy(mrhs_amg H)
+{
+    clear_error();
+    if (H) {
+        (void)hipDeviceSynchronize();
+        free_amg(H);
+    }
+    return MRHS_OK;
+}
+
+MRHS_API mrhs_status amg_info(mrhs_amg H, int32_t *levels, double *operator_complexity, size_t *device_bytes)
+{
+    clear_error();
+    if (!H)
+        return set_error(MRHS_EINVAL, "AMG handle is NULL");
+    if (levels)
+        *levels = H->dev.nlev;
+    if (operator_complexity)
+        *operator_complexity = H->op_complexity;
+    if (device_bytes)
+        *device_bytes = H->bytes;
+    return MRHS_OK;
+}
+
+MRHS_API mrhs_status amg_level(mrhs_amg H, int32_t level, int32_t *rows, int64_t *nnz_a, int64_t *nnz_p)
+{
+    clear_error();
+    if (!H)
+        return set_error(MRHS_EINVAL, "AMG handle is NULL");
+    if (level < 0 || level >= H->dev.nlev)
+        return set_error(MRHS_EINVAL, "level %d outside [0, %d)", level, H->dev.nlev);
+    const AmgLevelDev &d = H->dev.lev[level];
+    if (rows)
+        *rows = d.n;
+    if (nnz_a)
+        *nnz_a = d.nnz_a;
+    if (nnz_p)
+        *nnz_p = d.nnz_p;
+    return MRHS_OK;
+}
+
+MRHS_API mrhs_status amg_level_copy(mrhs_amg H, int32_t level, int32_t what, int32_t *row_ptr, int32_t *col,
+                                    double *val)
+{
+    clear_error();
+    if (!H)
+        return set_error(MRHS_EINVAL, "AMG handle is NULL");
+    if (level < 0 || level >= H->dev.nlev)
+        return set_error(MRHS_EINVAL, "level %d outside [0, %d)", level, H->dev.nlev);
+    const AmgLevelDev &d = H->dev.lev[level];
+    const bool coarsest = level == H->dev.nlev - 1;
+    if (what == MRHS_AMG_SPLIT) {
+        if (coarsest)
+            return set_error(MRHS_EINVAL, "the coarsest level has no C/F splitting");
+        if (!col)
+            return set_error(MRHS_EINVAL, "col is NULL");
+        const std::vector<int8_t> &cf = H->cf[level];
+        for (int32_t i = 0; i < d.n; ++i)
+            col[i] = cf[i];
+        return MRHS_OK;
+    }
+    if (what != MRHS_AMG_OPERATOR && what != MRHS_AMG_PROLONGATION)
+        return set_error(MRHS_EINVAL, "unknown part %d", what);
+    if (what == MRHS_AMG_PROLONGATION && coarsest)
+        return set_error(MRHS_EINVAL, "the coarsest level has no prolongation");
+    if (!row_ptr || !col || !val)
+        return set_error(MRHS_EINVAL, "NULL output array");
+    const CsrView<double> &v = what == MRHS_AMG_OPERATOR ? d.A : d.P;
+    const int64_t nnz = what == MRHS_AMG_OPERATOR ? d.nnz_a : d.nnz_p;
+    hipError_t e = hipSuccess;
+    if ((e = hipMemcpy(row_ptr, v.rp, sizeof(int32_t) * (static_cast<size_t>(d.n) + 1), hipMemcpyDeviceToHost)) !=
+            hipSuccess ||
+        (nnz && (e = hipMemcpy(col, v.ci, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost)) != hipSuccess) ||
+        (nnz && (e = hipMemcpy(val, v.va, sizeof(double) * nnz, hipMemcpyDeviceToHost)) != hipSuccess))
+        return set_error(MRHS_EDEVICE, "copy failed: %s", hipGetErrorString(e));
+    return MRHS_OK;
+}
+
+MRHS_API mrhs_status amg_vcycle_workspace_size(mrhs_amg H, int32_t m, size_t *bytes)
+{
+    clear_error();
+    if (!H || !bytes)
+        return set_error(MRHS_EINVAL, "NULL argument");
+    if (m < 1 || m > kMaxM)
+        return set_error(MRHS_EINVAL, "m = %d outside [1, 16]", m);
+    *bytes = amg_vcycle_bytes(H->dev, m);
+    return MRHS_OK;
+}
+
+MRHS_API mrhs_status amg_vcycle(mrhs_amg H, const double *B, double *X, int32_t m, void *workspace, size_t ws_bytes,
+                                void *hip_stream)
+{
+    clear_error();
+    if (!H)
+        return set_error(MRHS_EINVAL, "AMG handle is NULL");
+    if (m < 1 || m > kMaxM)
+        return set_error(MRHS_EINVAL, "m = %d outside [1, 16]", m);
+    if (!B || !X)
+        return set_error(MRHS_EINVAL, "B or X is NULL");
+    const size_t need = amg_vcycle_bytes(H->dev, m);
+    if (need && (!workspace || ws_bytes < need))
+        return set_error(MRHS_EINVAL, "workspace of %zu bytes is smaller than the %zu required", ws_bytes, need);
+    const size_t blk = sizeof(double) * static_cast<size_t>(H->dev.lev[0].n) * m;
+    const uintptr_t b = reinterpret_cast<uintptr_t>(B), x = reinterpret_cast<uintptr_t>(X),
+                    w = reinterpret_cast<uintptr_t>(workspace);
+    if ((b < x + blk && x < b + blk) || (need && ((w < b + blk && b < w + need) || (w < x + blk && x < w + need))))
+        return set_error(MRHS_EINVAL, "B, X and the workspace must not overlap");
+    if ((b & 15u) || (x & 15u) || (w & 15u))
+        return set_error(MRHS_EINVAL, "B, X and the workspace must be 16-byte aligned");
+    const hipError_t e = dispatch_m(m, VcLaunch{&H->dev, B, X, static_cast<char *>(workspace),
+                                                static_cast<hipStream_t>(hip_stream)});
+    if (e != hipSuccess)
+        return set_error(MRHS_EDEVICE, "V-cycle launch failed: %s", hipGetErrorString(e));
+    return MRHS_OK;
+}
+
+MRHS_API mrhs_status block_bicgstab_amg_workspace_size(mrhs_amg H, int32_t m, size_t *bytes)
+{
+    clear_error();
+    if (!H || !bytes)
+        return set_error(MRHS_EINVAL, "NULL argument");
+    if (m < 1 || m > kMaxM)
+        return set_error(MRHS_EINVAL, "m = %d outside [1, 16]", m);
+    *bytes = solve_workspace_bytes(*H->A, m, 0u, &H->dev);
+    return MRHS_OK;
+}
+
+MRHS_API mrhs_status block_bicgstab_amg(mrhs_amg H, const double *B, double *X, int32_t m, double tol, int32_t maxit,
+                                        uint32_t flags, void *workspace, size_t ws_bytes, void *hip_stream,
+                                        mrhs_col_info *info)
+{
+    clear_error();
+    if (!H)
+        return set_error(MRHS_EINVAL, "AMG handle is NULL");
+    const mrhs_csr_s &A = *H->A;
+    if (m < 1 || m > kMaxM)
+        return set_error(MRHS_EINVAL, "m = %d outside [1, 16]", m);
+    if (!(tol > 0.0) || !std::isfinite(tol))
+        return set_error(MRHS_EINVAL, "tol must be positive and finite");
+    if (maxit < 1)
+        return set_error(MRHS_EINVAL, "maxit must be at least 1");
+    if (flags & ~MRHS_X0_GIVEN)
+        return set_error(MRHS_EINVAL, "unknown flags 0x%x", flags);
+    if (!B || !X)
+        return set_error(MRHS_EINVAL, "B or X is NULL");
+    const size_t blk = static_cast<size_t>(A.n) * m * sizeof(double);
+    const uintptr_t b = reinterpret_cast<uintptr_t>(B), x = reinterpret_cast<uintptr_t>(X),
+                    w = reinterpret_cast<uintptr_t>(workspace);
+    if (b < x + blk && x < b + blk)
+        return set_error(MRHS_EINVAL, "B and X overlap");
+    if (workspace && ((w < b + blk && b < w + ws_bytes) || (w < x + blk && x < w + ws_bytes)))
+        return set_error(MRHS_EINVAL, "the workspace overlaps B or X");
+    if ((b & 15u) || (x & 15u) || (w & 15u))
+        return set_error(MRHS_EINVAL, "B, X and the workspace must be 16-byte aligned");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const size_t need = solve_workspace_bytes(A, m, 0u, &H->dev);
+    void *ws = workspace;
+    bool own = false;
+    if (!ws) {
+        if (hipMalloc(&ws, need) != hipSuccess) {
+            (void)hipGetLastError();
+            return set_error(MRHS_ENOMEM, "workspace allocation of %zu bytes failed", need);
+        }
+        own = true;
+        ws_bytes = need;
+    }
+    const mrhs_status st =
+        block_solve(A, B, X, SolveParams{m, tol, maxit, flags}, ws, ws_bytes, s, info, nullptr, &H->dev);
+    if (own) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(ws);
+    }
+    return st;
+}

@@ -140,6 +140,36 @@ inline auto dispatch_m(int m, F &&f)
     }
 }
 
+// ---- classical AMG on the device (amg.hip) ------------------------------------
+constexpr int kAmgMaxLevels = 25;
+
+// One level of the hierarchy in device memory: A_l, A_l D_l1^-1 (the first
+// smoothing sweep from x = 0 folded into the values), the l1-Jacobi
+// reciprocals, and the transfers P_l (n_l x n_{l+1}) and R_l = P_l^T.
+struct AmgLevelDev {
+    int32_t n = 0, nnext = 0;
+    int64_t nnz_a = 0, nnz_p = 0;
+    CsrView<double> A{}, Ah{}, P{}, R{};
+    double *dl1_inv = nullptr;
+};
+
+struct AmgDev {
+    int nlev = 0;
+    AmgLevelDev lev[kAmgMaxLevels];
+    CsrView<double> cinv{};  // dense inverse of the coarsest operator, as a full CRS matrix
+};
+
+struct Ctx;
+struct AmgStepTable {
+    hipError_t (*start)(Ctx &, uint32_t, bool);
+    hipError_t (*iterate)(Ctx &, int);
+    hipError_t (*check)(Ctx &);
+    hipError_t (*finish)(Ctx &, uint32_t, bool);
+};
+const AmgStepTable &amg_table(int m);
+// device bytes of the V-cycle's level buffers for an m-column block
+size_t amg_vcycle_bytes(const AmgDev &H, int32_t m);
+
 // ---- block solver engine (solver.hip) ---------------------------------------
 struct Ctx {
     const mrhs_csr_s *A;
@@ -158,6 +188,9 @@ struct Ctx {
     float *r32, *p32, *v32, *t32, *y32;
     int32_t ldp64 = 0, ldp32 = 0;  // row stride of the r/v blocks: 2m interleaved, else m
     uint8_t *sgn32;
+    const AmgDev *amg = nullptr;           // AMG-preconditioned iteration (else Jacobi)
+    double *sv = nullptr, *ph = nullptr, *sh = nullptr;  // AMG: s, M^-1 p, M^-1 s
+    char *vcws = nullptr;                  // AMG: V-cycle level buffers
 };
 
 struct StepTable {
@@ -179,11 +212,12 @@ struct StepTable {
 // finished columns.  Not thread-safe; one engine per host thread.
 class Engine {
   public:
-    static size_t workspace_bytes(const mrhs_csr_s &A, int32_t m, uint32_t flags);
+    static size_t workspace_bytes(const mrhs_csr_s &A, int32_t m, uint32_t flags, const AmgDev *amg = nullptr);
     // host_ctl: host memory for the mirror of the control block, or null to
-    // allocate pinned memory on the first reset()
+    // allocate pinned memory on the first reset(); amg: precondition with
+    // this hierarchy's V-cycle instead of Jacobi (binary64 only)
     Engine(const mrhs_csr_s &A, int m, uint32_t flags, void *ws, const double *B, double *X, hipStream_t s,
-           Ctl *host_ctl = nullptr);
+           Ctl *host_ctl = nullptr, const AmgDev *amg = nullptr);
     ~Engine();
     Engine(const Engine &) = delete;
     Engine &operator=(const Engine &) = delete;
@@ -204,11 +238,13 @@ class Engine {
     bool mixed_, nullspace_;
     hipStream_t s_;
     const StepTable *T_;
+    const AmgStepTable *AT_ = nullptr;
     Ctx c_{};
     unsigned *tickets_ = nullptr;
     Ctl *host_ = nullptr;
     bool own_host_ = false;
     int chunk_ = 16, ndirs_ = kGcrMax, max_outer_ = 500;
+    int amg_chunk_ = 2;  // iterations between polls with the AMG preconditioner
     int col_steps_[kMaxM] = {};  // refinement steps of each column since its admission (slot = steps % ndirs)
     double tol_in_ = 0.1;
     double outer_batch_ = 1.0;  // share of a block's active columns that triggers a refinement step
@@ -230,9 +266,10 @@ struct SolveParams {
     uint32_t flags;
 };
 
-size_t solve_workspace_bytes(const mrhs_csr_s &A, int32_t m, uint32_t flags);
-// host_ctl as for Engine (null: pinned memory allocated by the engine)
+size_t solve_workspace_bytes(const mrhs_csr_s &A, int32_t m, uint32_t flags, const AmgDev *amg = nullptr);
+// host_ctl and amg as for Engine
 mrhs_status block_solve(const mrhs_csr_s &A, const double *B, double *X, const SolveParams &p,
-                        void *ws, size_t ws_bytes, hipStream_t s, mrhs_col_info *info, Ctl *host_ctl = nullptr);
+                        void *ws, size_t ws_bytes, hipStream_t s, mrhs_col_info *info, Ctl *host_ctl = nullptr,
+                        const AmgDev *amg = nullptr);
 
 } // namespace mrhs

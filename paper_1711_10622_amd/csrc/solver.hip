@@ -40,6 +40,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
     size_t ctl, kry64, kry32, tickets, part, gpart;
     size_t rv64, p64, t64;  // r and v (one region, see pair_rv), p, t (binary64 solve)
+    size_t sv64, ph64, sh64, vc;  // s, M^-1 p, M^-1 s, V-cycle buffers (AMG preconditioner)
     size_t r64;         // refinement residual             (mixed)
     size_t z[kGcrMax];  // stored directions z_j           (mixed)
     size_t w[kGcrMax];  // and w_j = A z_j                 (mixed)
@@ -71,7 +72,7 @@ bool pair_rv(const mrhs_csr_s &A, int32_t m, size_t elem)
     return !planes || m * elem >= 128;
 }
 
-Layout layout(int32_t n, int32_t m, uint32_t flags)
+Layout layout(int32_t n, int32_t m, uint32_t flags, const AmgDev *amg = nullptr)
 {
     Layout L{};
     size_t off = 0;
@@ -117,6 +118,12 @@ Layout layout(int32_t n, int32_t m, uint32_t flags)
         L.rv64 = take_blk(2 * blk64 + kPairGap);
         L.p64 = take_blk(blk64);
         L.t64 = take_blk(blk64);
+        if (amg) {
+            L.sv64 = take_blk(blk64);
+            L.ph64 = take_blk(blk64);
+            L.sh64 = take_blk(blk64);
+            L.vc = take(amg_vcycle_bytes(*amg, m));
+        }
     }
     L.total = off;
     return L;
@@ -343,17 +350,17 @@ mrhs_status column_status(int32_t st)
     }
 }
 
-size_t Engine::workspace_bytes(const mrhs_csr_s &A, int32_t m, uint32_t flags)
+size_t Engine::workspace_bytes(const mrhs_csr_s &A, int32_t m, uint32_t flags, const AmgDev *amg)
 {
-    return layout(A.n, m, flags).total;
+    return layout(A.n, m, flags, amg).total;
 }
 
 Engine::Engine(const mrhs_csr_s &A, int m, uint32_t flags, void *ws, const double *B, double *X, hipStream_t s,
-               Ctl *host_ctl)
+               Ctl *host_ctl, const AmgDev *amg)
     : A_(A), m_(m), mixed_((flags & MRHS_MIXED) != 0), nullspace_((A.flags & MRHS_CSR_NULLSPACE_CONST) != 0),
       s_(s), T_(&table(m)), host_(host_ctl)
 {
-    const Layout L = layout(A.n, m, flags);
+    const Layout L = layout(A.n, m, flags, amg);
     char *base = static_cast<char *>(ws);
     c_.A = &A;
     c_.B = B;
@@ -392,6 +399,14 @@ Engine::Engine(const mrhs_csr_s &A, int m, uint32_t flags, void *ws, const doubl
         c_.ldp64 = pair ? 2 * m_ : m_;
         c_.p = reinterpret_cast<double *>(base + L.p64);
         c_.t = reinterpret_cast<double *>(base + L.t64);
+        if (amg) {
+            AT_ = &amg_table(m);
+            c_.amg = amg;
+            c_.sv = reinterpret_cast<double *>(base + L.sv64);
+            c_.ph = reinterpret_cast<double *>(base + L.ph64);
+            c_.sh = reinterpret_cast<double *>(base + L.sh64);
+            c_.vcws = base + L.vc;
+        }
     }
     chunk_ = env_int("MRHS_POLL_ITERS", 16, 1, 1024);
     tol_in_ = env_double("MRHS_INNER_TOL", 0.1);
@@ -400,6 +415,7 @@ Engine::Engine(const mrhs_csr_s &A, int m, uint32_t flags, void *ws, const doubl
     outer_wait_ = env_int("MRHS_OUTER_WAIT", 0, 0, 100000);
     mixed_chunk_ = env_int("MRHS_MIXED_POLL", 4, 1, 1024);
     stag_window_ = env_int("MRHS_STAG_WINDOW", kStagWindow, 4, 100000);
+    amg_chunk_ = env_int("MRHS_AMG_POLL", 2, 1, 1024);
 }
 
 Engine::~Engine()
@@ -441,7 +457,8 @@ mrhs_status Engine::start(uint32_t cmask, const double *tol, const int32_t *maxi
             col_steps_[c] = 0;  // the device resets kcol[c] to slot 0
     hipLaunchKernelGGL(k_slot_init, dim3(1), dim3(64), 0, s_, c_.ctl, cmask, si);
     MRHS_HIP(hipGetLastError());
-    MRHS_HIP(mixed_ ? T_->mixed_start(c_, cmask, x0) : T_->f64_start(c_, cmask, x0));
+    MRHS_HIP(mixed_ ? T_->mixed_start(c_, cmask, x0)
+                    : (AT_ ? AT_->start(c_, cmask, x0) : T_->f64_start(c_, cmask, x0)));
     return MRHS_OK;
 }
 
@@ -488,8 +505,8 @@ mrhs_status Engine::advance(bool *busy)
         return MRHS_OK;
     if (!mixed_) {
         if (pend)
-            MRHS_HIP(T_->f64_check(c_));
-        MRHS_HIP(T_->f64_iterate(c_, chunk_));
+            MRHS_HIP(AT_ ? AT_->check(c_) : T_->f64_check(c_));
+        MRHS_HIP(AT_ ? AT_->iterate(c_, amg_chunk_) : T_->f64_iterate(c_, chunk_));
         return MRHS_OK;
     }
     uint32_t pend_mask = 0, done_mask = 0;
@@ -531,23 +548,23 @@ mrhs_status Engine::advance(bool *busy)
 
 mrhs_status Engine::finish(uint32_t cmask)
 {
-    MRHS_HIP(T_->finish(c_, cmask, mixed_, nullspace_));
+    MRHS_HIP(AT_ ? AT_->finish(c_, cmask, nullspace_) : T_->finish(c_, cmask, mixed_, nullspace_));
     return MRHS_OK;
 }
 
-size_t solve_workspace_bytes(const mrhs_csr_s &A, int32_t m, uint32_t flags)
+size_t solve_workspace_bytes(const mrhs_csr_s &A, int32_t m, uint32_t flags, const AmgDev *amg)
 {
-    return Engine::workspace_bytes(A, m, flags);
+    return Engine::workspace_bytes(A, m, flags, amg);
 }
 
 mrhs_status block_solve(const mrhs_csr_s &A, const double *B, double *X, const SolveParams &p, void *ws,
-                        size_t ws_bytes, hipStream_t s, mrhs_col_info *info, Ctl *host_ctl)
+                        size_t ws_bytes, hipStream_t s, mrhs_col_info *info, Ctl *host_ctl, const AmgDev *amg)
 {
     const int m = p.m;
-    const size_t need = Engine::workspace_bytes(A, m, p.flags);
+    const size_t need = Engine::workspace_bytes(A, m, p.flags, amg);
     if (ws_bytes < need)
         return set_error(MRHS_EINVAL, "workspace of %zu bytes is smaller than the %zu required", ws_bytes, need);
-    Engine e(A, m, p.flags, ws, B, X, s, host_ctl);
+    Engine e(A, m, p.flags, ws, B, X, s, host_ctl, amg);
     mrhs_status st = e.reset();
     if (st != MRHS_OK)
         return st;

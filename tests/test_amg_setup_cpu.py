@@ -1,0 +1,112 @@
+"""The library's AMG setup (host code) against the oracle's, on the CPU: the
+host part of the library is built with g++ into a driver, and the hierarchy
+it builds must equal the oracle's bit for bit (C/F splitting, every level's
+operator, l1-Jacobi reciprocals, prolongation), since both follow the same
+construction with the same order of every floating-point sum (BiCGStab with
+classical AMG, Section 4.1); the coarsest dense inverses, computed by
+different elimination codes, agree to rounding."""
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import amg
+from workloads import grids, rng
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1711_10622_amd", "csrc")
+
+
+@pytest.fixture(scope="module")
+def driver(tmp_path_factory):
+    cxx = shutil.which("g++")
+    if cxx is None:
+        pytest.skip("g++ not available")
+    exe = str(tmp_path_factory.mktemp("amg") / "amg_setup_driver")
+    cmd = [cxx, "-std=c++17", "-O2", "-ffp-contract=off", "-Wno-unknown-pragmas", f"-I{CSRC}",
+           "-x", "c++", os.path.join(CSRC, "amg_setup.hip"), "-x", "none",
+           os.path.join(ROOT, "tests", "amg_setup_driver.cpp"), "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-4000:]
+    return exe
+
+
+def run_driver(exe, tmp, A, ns):
+    fin, fout = os.path.join(tmp, "in.bin"), os.path.join(tmp, "out.bin")
+    with open(fin, "wb") as f:
+        np.array([A.n], np.int32).tofile(f)
+        np.array([len(A.col)], np.int64).tofile(f)
+        np.array([1 if ns else 0], np.int32).tofile(f)
+        np.asarray(A.row_ptr, np.int32).tofile(f)
+        np.asarray(A.col, np.int32).tofile(f)
+        np.asarray(A.val, np.float64).tofile(f)
+    r = subprocess.run([exe, fin, fout], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    buf = open(fout, "rb").read()
+    pos = 0
+
+    def take(dt, count):
+        nonlocal pos
+        a = np.frombuffer(buf, dtype=dt, count=count, offset=pos)
+        pos += a.nbytes
+        return a
+    L = int(take(np.int32, 1)[0])
+    levels = []
+    for l in range(L):
+        n = int(take(np.int32, 1)[0])
+        na = int(take(np.int64, 1)[0])
+        lev = {"n": n, "rp": take(np.int32, n + 1), "ci": take(np.int32, na), "va": take(np.float64, na),
+               "dl1": take(np.float64, n)}
+        if l + 1 < L:
+            lev["cf"] = take(np.int8, n)
+            nc = int(take(np.int32, 1)[0])
+            npz = int(take(np.int64, 1)[0])
+            lev["P"] = (nc, take(np.int32, n + 1), take(np.int32, npz), take(np.float64, npz))
+        levels.append(lev)
+    nc = int(take(np.int32, 1)[0])
+    cinv = take(np.float64, nc * nc).reshape(nc, nc)
+    return levels, cinv
+
+
+def cases():
+    yield "dir16", grids.dirichlet7(16), False
+    yield "dir13x11x7", grids.dirichlet7(13, 11, 7), False
+    yield "chan24x16x20", grids.channel7(24, 16, 20, beta=2.0), True
+    solid = grids.cube_array_solid(48, 24, 32, ncube=2, h=4, pitch_x=24, pitch_z=16, off_x=4, off_z=4)
+    C = grids.channel7(48, 24, 32, beta=2.0, lx=3.0, ly=1.5, lz=2.0, solid=solid)
+    yield "cube48_perm", grids.permute_symmetric(C, rng.permutation(C.n, 10622)), True
+    # duplicates and unsorted columns: the canonical form sums them
+    D = grids.dirichlet7(9, 8, 7)
+    r = np.random.default_rng(3)
+    rows = np.repeat(np.arange(D.n), np.diff(D.row_ptr))
+    order = np.lexsort((r.random(len(D.col)), rows))
+    col, val = D.col[order], D.val[order]
+    dup = r.random(len(col)) < 0.1
+    col2 = np.concatenate([col, col[dup]])
+    val2 = np.concatenate([val * np.where(dup, 0.5, 1.0), val[dup] * 0.5])
+    rows2 = np.concatenate([rows, rows[dup]])
+    o2 = np.argsort(rows2, kind="stable")
+    rp = np.concatenate([[0], np.cumsum(np.bincount(rows2, minlength=D.n))]).astype(np.int32)
+    yield "dir9_dups", grids.CSRMatrix(D.n, rp, col2[o2].astype(np.int32), val2[o2]), False
+
+
+@pytest.mark.parametrize("case", list(range(5)))
+def test_library_hierarchy_equals_oracle(driver, tmp_path, case):
+    name, A, ns = list(cases())[case]
+    levels, cinv = run_driver(driver, str(tmp_path), A, ns)
+    H = amg.setup(A.n, A.row_ptr, A.col, A.val, nullspace_const=ns)
+    assert len(levels) == len(H.levels), name
+    for l, (got, ref) in enumerate(zip(levels, H.levels)):
+        assert got["n"] == ref.A.n_rows
+        assert np.array_equal(got["rp"], ref.A.rp) and np.array_equal(got["ci"], ref.A.ci), (name, l)
+        assert np.array_equal(got["va"], ref.A.va), (name, l)
+        assert np.array_equal(got["dl1"], ref.dl1_inv), (name, l)
+        if l + 1 < len(levels):
+            assert np.array_equal(got["cf"], ref.cf), (name, l)
+            nc, prp, pci, pva = got["P"]
+            assert nc == ref.P.n_cols
+            assert np.array_equal(prp, ref.P.rp) and np.array_equal(pci, ref.P.ci) and np.array_equal(pva, ref.P.va)
+    scale = np.abs(H.coarse_inv).max()
+    assert np.abs(cinv - H.coarse_inv).max() <= 1e-12 * scale, name
