@@ -88,14 +88,22 @@ struct OpVcRes {
     using Lane = VcLane;
     __device__ Lane lane(int g) const { return {lane_running<M>(ctl, g)}; }
     __device__ __forceinline__ void gather(const Lane &, int32_t c, int g, double *x) const { ld<double, M>(X, c, g, x); }
+    struct Pre {
+        double u[S::VW];
+    };
+    __device__ __forceinline__ Pre pre(const Lane &, int32_t i, int g) const
+    {
+        Pre pr;
+        ld<double, M>(U, i, g, pr.u);
+        return pr;
+    }
     __device__ __forceinline__ void row(const Lane &, int32_t i, int g, const double *sum,
-                                        Acc<double, S::VW, NDOT> &) const
+                                        Acc<double, S::VW, NDOT> &, const Pre &pr) const
     {
         double u[S::VW];
-        ld<double, M>(U, i, g, u);
 #pragma unroll
         for (int q = 0; q < S::VW; ++q)
-            u[q] = u[q] - sum[q];
+            u[q] = pr.u[q] - sum[q];
         st<double, M>(Y, i, g, u);
     }
     __device__ void finish(const double *) const {}
@@ -113,15 +121,24 @@ struct OpVcProl {
     using Lane = VcLane;
     __device__ Lane lane(int g) const { return {lane_running<M>(ctl, g)}; }
     __device__ __forceinline__ void gather(const Lane &, int32_t c, int g, double *x) const { ld<double, M>(X, c, g, x); }
+    struct Pre {
+        double u[S::VW];
+        double d;
+    };
+    __device__ __forceinline__ Pre pre(const Lane &, int32_t i, int g) const
+    {
+        Pre pr;
+        ld<double, M>(U, i, g, pr.u);
+        pr.d = dinv[i];
+        return pr;
+    }
     __device__ __forceinline__ void row(const Lane &, int32_t i, int g, const double *sum,
-                                        Acc<double, S::VW, NDOT> &) const
+                                        Acc<double, S::VW, NDOT> &, const Pre &pr) const
     {
         double u[S::VW];
-        ld<double, M>(U, i, g, u);
-        const double d = dinv[i];
 #pragma unroll
         for (int q = 0; q < S::VW; ++q)
-            u[q] = d * u[q] + sum[q];
+            u[q] = pr.d * pr.u[q] + sum[q];
         st<double, M>(Y, i, g, u);
     }
     __device__ void finish(const double *) const {}
@@ -139,16 +156,25 @@ struct OpVcSmooth {
     using Lane = VcLane;
     __device__ Lane lane(int g) const { return {lane_running<M>(ctl, g)}; }
     __device__ __forceinline__ void gather(const Lane &, int32_t c, int g, double *x) const { ld<double, M>(T, c, g, x); }
-    __device__ __forceinline__ void row(const Lane &, int32_t i, int g, const double *sum,
-                                        Acc<double, S::VW, NDOT> &) const
-    {
+    struct Pre {
         double t[S::VW], u[S::VW];
-        ld<double, M>(T, i, g, t);
-        ld<double, M>(U, i, g, u);
-        const double d = dinv[i];
+        double d;
+    };
+    __device__ __forceinline__ Pre pre(const Lane &, int32_t i, int g) const
+    {
+        Pre pr;
+        ld<double, M>(T, i, g, pr.t);
+        ld<double, M>(U, i, g, pr.u);
+        pr.d = dinv[i];
+        return pr;
+    }
+    __device__ __forceinline__ void row(const Lane &, int32_t i, int g, const double *sum,
+                                        Acc<double, S::VW, NDOT> &, const Pre &pr) const
+    {
+        double t[S::VW];
 #pragma unroll
         for (int q = 0; q < S::VW; ++q)
-            t[q] = t[q] + d * (u[q] - sum[q]);
+            t[q] = pr.t[q] + pr.d * (pr.u[q] - sum[q]);
         st<double, M>(Y, i, g, t);
     }
     __device__ void finish(const double *) const {}
@@ -204,11 +230,20 @@ struct OpSpmv2P : OpSpmv2<double, M> {
     const double *sh;  // M^-1 s, gathered
     const double *sv;  // s
     __device__ __forceinline__ void gather(const Lane &, int32_t c, int g, double *x) const { ld<double, M>(sh, c, g, x); }
-    __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, const double *sum,
-                                        Acc<double, S::VW, Base::NDOT> &acc) const
+    struct Pre {
+        double s[S::VW];
+    };
+    __device__ __forceinline__ Pre pre(const Lane &, int32_t i, int g) const
     {
-        double s[S::VW], h[S::VW];
-        ld<double, M>(sv, i, g, s);
+        Pre pr;
+        ld<double, M>(sv, i, g, pr.s);
+        return pr;
+    }
+    __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, const double *sum,
+                                        Acc<double, S::VW, Base::NDOT> &acc, const Pre &pr) const
+    {
+        const double *s = pr.s;
+        double h[S::VW];
         shadow_row<double, M>(nullptr, i, g, h);
         st<double, M>(this->t, i, g, sum);
 #pragma unroll

@@ -422,6 +422,15 @@ struct gathered_blocks<Op, std::void_t<decltype(Op::GATHERED)>> {
     static constexpr int value = Op::GATHERED;
 };
 
+// Ops whose epilogue reads the row's own entries of other blocks may declare
+// a type Pre and a method pre(lane, row, g) returning them; the tile loop then
+// issues those loads before the row's gathers, so both come back in one
+// memory round trip, and passes them to row(..., pre).
+template <class Op, class = void>
+struct has_pre : std::false_type {};
+template <class Op>
+struct has_pre<Op, std::void_t<typename Op::Pre>> : std::true_type {};
+
 // Y-side of a generalized SpMV over every tile of this workgroup.  The
 // tile's row offsets, column indices and values are first staged in LDS with
 // coalesced streaming loads (one pass over HBM, no reuse in cache needed), then
@@ -511,11 +520,20 @@ __device__ __forceinline__ void gspmv_tiles(const CsrView<T> &A, const Op &op,
 #pragma unroll
                 for (int v = 0; v < S::VW; ++v)
                     sum[v] = T(0);
-                if (staged)
-                    row_product<T, S::VW>(lci, lva, j0, j1, g, op, ln, sum);
-                else
-                    row_product<T, S::VW>(A.ci + z0, A.va + z0, j0, j1, g, op, ln, sum);
-                op.row(ln, r0 + row_l, g, sum, acc);
+                if constexpr (has_pre<Op>::value) {
+                    const typename Op::Pre pr = op.pre(ln, r0 + row_l, g);
+                    if (staged)
+                        row_product<T, S::VW>(lci, lva, j0, j1, g, op, ln, sum);
+                    else
+                        row_product<T, S::VW>(A.ci + z0, A.va + z0, j0, j1, g, op, ln, sum);
+                    op.row(ln, r0 + row_l, g, sum, acc, pr);
+                } else {
+                    if (staged)
+                        row_product<T, S::VW>(lci, lva, j0, j1, g, op, ln, sum);
+                    else
+                        row_product<T, S::VW>(A.ci + z0, A.va + z0, j0, j1, g, op, ln, sum);
+                    op.row(ln, r0 + row_l, g, sum, acc);
+                }
             }
         }
         __syncthreads();

@@ -263,12 +263,22 @@ struct OpResid {
     {
         ld<double, M>(X, c, g, x);
     }
+    // the row's own b, loaded before its gathers
+    struct Pre {
+        double b[S::VW];
+    };
+    __device__ __forceinline__ Pre pre(const Lane &, int32_t i, int g) const
+    {
+        Pre pr;
+        ld<double, M>(B, i, g, pr.b);
+        return pr;
+    }
     __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, const double *sum,
-                                        Acc<double, S::VW, NDOT> &acc) const
+                                        Acc<double, S::VW, NDOT> &acc, const Pre &pr) const
     {
         const size_t o = static_cast<size_t>(i) * M + g * S::VW;
-        double b[S::VW], r[S::VW];
-        ld<double, M>(B, i, g, b);
+        const double *b = pr.b;
+        double r[S::VW];
         const bool restart = kind == RES_SETUP || kind == RES_CHECK;
         const double h = restart ? shadow<double>(i) : 0.0;
 #pragma unroll
@@ -524,12 +534,21 @@ struct OpSpmv2 {
         for (int q = 0; q < S::VW; ++q)
             x[q] = rr[q] - ln.alpha[q] * vv[q];
     }
-    __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, const T *sum,
-                                        Acc<T, S::VW, NDOT> &acc) const
+    // the row's own s = r - alpha v, loaded before its gathers
+    struct Pre {
+        T s[S::VW];
+    };
+    __device__ __forceinline__ Pre pre(const Lane &ln, int32_t i, int g) const
     {
-        const size_t o = static_cast<size_t>(i) * M + g * S::VW;
-        T s[S::VW], h[S::VW];
-        gather(ln, i, g, s);
+        Pre pr;
+        gather(ln, i, g, pr.s);
+        return pr;
+    }
+    __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, const T *sum,
+                                        Acc<T, S::VW, NDOT> &acc, const Pre &pr) const
+    {
+        const T *s = pr.s;
+        T h[S::VW];
         shadow_row<T, M>(sgn, i, g, h);
         st<T, M>(t, i, g, sum);
 #pragma unroll
