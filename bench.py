@@ -271,7 +271,6 @@ def solve_pair(torch, name, m, steps):
     Bh = wl.rhs(A.n, m)
     M = mrhs.CsrMatrix.from_csr(A)
     B = torch.from_numpy(Bh).to("cuda")
-    del Bh
     X = torch.empty_like(B)
     ws = torch.empty(max(M.workspace_size(m, mixed=True), M.workspace_size(m)), dtype=torch.uint8, device="cuda")
     res = {"n": A.n, "nnz": A.nnz, "m": m}
@@ -283,6 +282,8 @@ def solve_pair(torch, name, m, steps):
         log(f"{name} m={m} {'mixed' if mixed else 'fp64'}: {t * 1e3:.1f} ms")
     res["mixed_speedup"] = round(res["fp64"]["s_per_rhs"] / res["mixed"]["s_per_rhs"], 3)
     del M, B, X, ws
+    torch.cuda.empty_cache()
+    res["amg"] = amg_legs(torch, A, Bh, m, res["fp64"]["s_per_rhs"] * m, per_iter_ms=(1, m), steps=2)
     torch.cuda.empty_cache()
     return res
 
@@ -636,6 +637,67 @@ def summarize_profiles(out, workload, m):
     return 0
 
 
+def amg_legs(torch, A, Bh, m, t_jacobi, per_iter_ms=(1, 2, 4, 8, 16), steps=1):
+    """BiCGStab with the classical AMG preconditioner (the paper's solver,
+    Section 4.1) on the same block: host setup time and hierarchy, the solve
+    to 1e-10 against the Jacobi solve's time, its top kernels, and the time
+    per iteration at a fixed count for several m with m t_1 / t_m (the
+    quantity of Tables 2-3)."""
+    import numpy as np
+    import paper_1711_10622_amd as mrhs
+    from paper_1711_10622_amd import estimates as est
+    M = mrhs.CsrMatrix.from_csr(A)
+    t0 = time.perf_counter()
+    H = mrhs.AmgHierarchy(M)
+    setup = time.perf_counter() - t0
+    out = {"setup_s": round(setup, 2), "levels": H.levels, "operator_complexity": round(H.operator_complexity, 3),
+           "device_GB": round(H.device_bytes / 1e9, 3), "rows_per_level": [H.level(l)[0] for l in range(H.levels)]}
+    B = torch.from_numpy(np.ascontiguousarray(Bh[:, :m])).to("cuda")
+    X = torch.empty_like(B)
+    ws = torch.empty(H.workspace_size(m), dtype=torch.uint8, device="cuda")
+    H.solve(B, out=X, workspace=ws)
+    torch.cuda.synchronize()
+    mrhs.trace_enable(True, every=TRACE_EVERY)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, infos, st = H.solve(B, out=X, workspace=ws)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    tr = mrhs.trace_read()
+    mrhs.trace_enable(False)
+    assert st == 0, infos
+    out.update({"m": m, "s_per_rhs": round(t / m, 6), "speedup_vs_jacobi": round(t_jacobi / t, 3),
+                "iters": [i["iters"] for i in infos], "max_relres": max(i["relres"] for i in infos),
+                "top_kernels": {k: {"launches": v["seen"], "avg_us": round(v["total_ms"] / v["launches"] * 1e3, 1)}
+                                for k, v in sorted(tr.items(), key=lambda kv: -kv[1]["total_ms"] / kv[1]["launches"]
+                                                   * kv[1]["seen"])[:8]}})
+    del X, B, ws
+    per = {}
+    for mm in per_iter_ms:
+        Bm = torch.from_numpy(np.ascontiguousarray(Bh[:, :mm])).to("cuda")
+        Xm = torch.empty_like(Bm)
+        wsm = torch.empty(H.workspace_size(mm), dtype=torch.uint8, device="cuda")
+        tt = {}
+        for k in (10, 20):
+            H.solve(Bm, tol=1e-300, maxit=k, out=Xm, workspace=wsm)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            H.solve(Bm, tol=1e-300, maxit=k, out=Xm, workspace=wsm)
+            torch.cuda.synchronize()
+            tt[k] = time.perf_counter() - t0
+        per[mm] = {"ms_per_iter": round((tt[20] - tt[10]) / 10 * 1e3, 4)}
+        del Bm, Xm, wsm
+    if 1 in per:
+        for mm, d in per.items():
+            d["iter_gain_vs_m1"] = round(mm * per[1]["ms_per_iter"] / d["ms_per_iter"], 3)
+            d["paper_compact_5m_2m3"] = round(est.gain_compact(mm), 3)
+    out["per_iter"] = per
+    H.close()
+    M.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def chan128_legs(torch, steps):
     """The 524k-row channel (its matrix, m = 16 block and workspace fit the
     256 MB Infinity Cache): binary64 solve, solves per m with the speedup per
@@ -666,6 +728,7 @@ def chan128_legs(torch, steps):
             mixed = {"s_per_rhs": tm / 16, "speedup_vs_fp64": round(t / tm, 3),
                      "iters_max": max(i["iters"] for i in im), "outer_max": max(i["outer"] for i in im),
                      "max_relres": max(i["relres"] for i in im)}
+    amg = amg_legs(torch, A, Bh, 16, per_m[16]["s_per_rhs"] * 16, per_iter_ms=(1, 16), steps=3)
     t1 = per_m[1]["s_per_rhs"]
     for mm, d in per_m.items():
         d["gain_vs_m1"] = round(t1 / d["s_per_rhs"], 3)
@@ -675,7 +738,7 @@ def chan128_legs(torch, steps):
     M.close()
     del ws
     torch.cuda.empty_cache()
-    return {"per_m_fp64": per_m, "mixed_m16": mixed}, A, Bh, Xs
+    return {"per_m_fp64": per_m, "mixed_m16": mixed, "amg_m16": amg}, A, Bh, Xs
 
 
 def main():
@@ -779,6 +842,8 @@ def main():
         extra["per_iter_fp64"] = per_iteration(torch, M, Bh, (1, 2, 4, 8, 16))
         log(f"per iteration: {extra['per_iter_fp64']}")
         M.close()
+        extra["amg"] = amg_legs(torch, A, Bh, m, step_s)
+        log(f"amg: {extra['amg']}")
         extra["gspmv_chan256"] = gspmv_sweep(torch, A, list(range(1, 17)), ("f64", "f32"), reps=20)
         log("gspmv sweep done")
         legs, A2, Bh2, Xs2 = chan128_legs(torch, 2)

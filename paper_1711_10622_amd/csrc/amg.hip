@@ -59,6 +59,7 @@ struct VcLane {
 template <int M>
 struct OpVcStore {
     static constexpr const char *kName = "vc_store";
+    static constexpr bool kLongRows = true;
     using S = Shape<double, M>;
     static constexpr int NDOT = 0;
     const double *X;
@@ -80,6 +81,7 @@ struct OpVcStore {
 template <int M>
 struct OpVcRes {
     static constexpr const char *kName = "vc_resid";
+    static constexpr bool kLongRows = true;
     using S = Shape<double, M>;
     static constexpr int NDOT = 0;
     const double *X, *U;
@@ -113,6 +115,7 @@ struct OpVcRes {
 template <int M>
 struct OpVcProl {
     static constexpr const char *kName = "vc_prolong";
+    static constexpr bool kLongRows = true;
     using S = Shape<double, M>;
     static constexpr int NDOT = 0;
     const double *X, *U, *dinv;
@@ -148,6 +151,7 @@ struct OpVcProl {
 template <int M>
 struct OpVcSmooth {
     static constexpr const char *kName = "vc_smooth";
+    static constexpr bool kLongRows = true;
     using S = Shape<double, M>;
     static constexpr int NDOT = 0;
     const double *T, *U, *dinv;
@@ -526,6 +530,15 @@ int32_t median_reach(const amg::HostCsr &A)
     return reach[A.nr / 2];
 }
 
+// Small levels with long rows (the coarse Galerkin levels, 30-90 nonzeros
+// per row, and the coarsest dense inverse) take the one-wave-per-row product:
+// the tiled one would run them on a few workgroups with long serial row
+// chains.  Large levels keep the tiled product: with ~15 nonzeros per row one
+// row per wave leaves most gather slots empty (measured on the 12.6M-row
+// channel's first coarse level, 6.3M rows: 1070 -> 1371 us per sweep).
+constexpr double kSplitRowNnz = 12.0;
+constexpr int32_t kSplitMaxRows = 131072;
+
 CsrView<double> upload_csr(mrhs_amg_s *H, const amg::HostCsr &C, const std::vector<double> *vals, int32_t reach,
                            hipError_t *err)
 {
@@ -535,6 +548,7 @@ CsrView<double> upload_csr(mrhs_amg_s *H, const amg::HostCsr &C, const std::vect
     v.va = upload(H, (vals ? vals : &C.va)->data(), C.va.size(), kPadElems, err);
     v.n = C.nr;
     v.reach = reach;
+    v.split = C.nr > 0 && C.nr < kSplitMaxRows && static_cast<double>(C.nnz()) >= kSplitRowNnz * C.nr;
     return v;
 }
 

@@ -363,6 +363,7 @@ struct CsrView {
     const T *__restrict__ va;
     int32_t n;
     int32_t reach;  // median over rows of the largest forward column offset
+    int32_t split;  // nonzero: long rows, one wave per row (gspmv_rows_split)
 };
 
 // One row of the product: sum over the row's entries in storage order of
@@ -430,6 +431,22 @@ template <class Op, class = void>
 struct has_pre : std::false_type {};
 template <class Op>
 struct has_pre<Op, std::void_t<typename Op::Pre>> : std::true_type {};
+template <class Op, bool = has_pre<Op>::value>
+struct pre_of {
+    using type = int;
+};
+template <class Op>
+struct pre_of<Op, true> {
+    using type = typename Op::Pre;
+};
+
+// Ops that set kLongRows = true may run on the one-wave-per-row product
+// (gspmv_rows_split) when their matrix has long rows; the others always use
+// the tiled one, which is correct for any matrix.
+template <class Op, class = void>
+struct long_rows_ok : std::false_type {};
+template <class Op>
+struct long_rows_ok<Op, std::void_t<decltype(Op::kLongRows)>> : std::integral_constant<bool, Op::kLongRows> {};
 
 // Y-side of a generalized SpMV over every tile of this workgroup.  The
 // tile's row offsets, column indices and values are first staged in LDS with
@@ -537,6 +554,80 @@ __device__ __forceinline__ void gspmv_tiles(const CsrView<T> &A, const Op &op,
             }
         }
         __syncthreads();
+    }
+}
+
+// Products over matrices with long rows (the Galerkin operators of coarse
+// multigrid levels carry 30-90 nonzeros per row): a wave takes one row at a
+// time, its RW row slots of L lanes take every RW-th entry of the row (NB at
+// a time, all gathers in flight together), a butterfly over the slots adds the
+// partial sums, and slot 0 runs the op's epilogue.  Workgroup b belongs to
+// XCD group b % 8, which owns a contiguous eighth of the rows.  Only for row
+// layouts whose lanes fill the wave (L a power of two).
+template <typename T, int M, class Op>
+__device__ __forceinline__ void gspmv_rows_split(const CsrView<T> &A, const Op &op,
+                                                 Acc<T, Shape<T, M>::VW, Op::NDOT> &acc)
+{
+    using S = Shape<T, M>;
+    static_assert(S::POW2 && S::RW * S::L == 64, "row slots must fill the wave");
+    constexpr int NB = MRHS_GATHER_BATCH;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int g = lane % S::L;
+    const int slot = lane / S::L;
+    const typename Op::Lane ln = op.lane(g < S::G ? g : 0);
+    const bool lane_on = g < S::G && ln.on;
+    const int grp = blockIdx.x % kGroups;
+    const int32_t q = blockIdx.x / kGroups, gx = gridDim.x / kGroups;
+    const int32_t lo = static_cast<int32_t>(static_cast<int64_t>(A.n) * grp / kGroups);
+    const int32_t hi = static_cast<int32_t>(static_cast<int64_t>(A.n) * (grp + 1) / kGroups);
+    const int32_t waves = kBlock / 64;
+    for (int32_t row = lo + q * waves + (tid >> 6); row < hi; row += gx * waves) {
+        const int32_t j0 = A.rp[row], j1 = A.rp[row + 1];
+        T sum[S::VW];
+#pragma unroll
+        for (int v = 0; v < S::VW; ++v)
+            sum[v] = T(0);
+        [[maybe_unused]] typename pre_of<Op>::type pr{};
+        if (lane_on) {
+            if constexpr (has_pre<Op>::value) {
+                if (slot == 0)
+                    pr = op.pre(ln, row, g);
+            }
+            for (int32_t jb = j0 + slot; jb < j1; jb += S::RW * NB) {
+                int32_t c[NB];
+                T a[NB], x[NB][S::VW];
+                bool ok[NB];
+#pragma unroll
+                for (int k = 0; k < NB; ++k) {
+                    const int32_t j = jb + k * S::RW;
+                    ok[k] = j < j1;
+                    const int32_t jj = ok[k] ? j : jb;
+                    c[k] = A.ci[jj];
+                    a[k] = A.va[jj];
+                }
+#pragma unroll
+                for (int k = 0; k < NB; ++k)
+                    op.gather(ln, c[k], g, x[k]);
+#pragma unroll
+                for (int k = 0; k < NB; ++k)
+#pragma unroll
+                    for (int v = 0; v < S::VW; ++v)
+                        if (ok[k])
+                            sum[v] += a[k] * x[k][v];
+            }
+        }
+#pragma unroll
+        for (int off = S::L; off < 64; off <<= 1)
+#pragma unroll
+            for (int v = 0; v < S::VW; ++v)
+                sum[v] += __shfl_xor(sum[v], off);
+        if (lane_on && slot == 0) {
+            if constexpr (has_pre<Op>::value)
+                op.row(ln, row, g, sum, acc, pr);
+            else
+                op.row(ln, row, g, sum, acc);
+        }
     }
 }
 

@@ -54,13 +54,13 @@ inline CsrView<T> view(const mrhs_csr_s &A, bool scaled);
 template <>
 inline CsrView<double> view<double>(const mrhs_csr_s &A, bool scaled)
 {
-    return {A.rp, A.ci, scaled ? A.valh : A.val, A.n, A.reach};
+    return {A.rp, A.ci, scaled ? A.valh : A.val, A.n, A.reach, 0};
 }
 
 template <>
 inline CsrView<float> view<float>(const mrhs_csr_s &A, bool scaled)
 {
-    return {A.rp, A.ci, scaled ? A.valh32 : A.val32, A.n, A.reach};
+    return {A.rp, A.ci, scaled ? A.valh32 : A.val32, A.n, A.reach, 0};
 }
 
 template <typename T, int M, class Op>
@@ -69,6 +69,16 @@ __global__ void __launch_bounds__(kBlock) k_gspmv(CsrView<T> A, Op op, RedBufs<T
     Acc<T, Shape<T, M>::VW, Op::NDOT> acc;
     acc.zero();
     gspmv_tiles<T, M>(A, op, acc);
+    if constexpr (Op::NDOT > 0)
+        grid_reduce<T, M, Op::NDOT>(acc, rb, op);
+}
+
+template <typename T, int M, class Op>
+__global__ void __launch_bounds__(kBlock) k_gspmv_split(CsrView<T> A, Op op, RedBufs<T> rb)
+{
+    Acc<T, Shape<T, M>::VW, Op::NDOT> acc;
+    acc.zero();
+    gspmv_rows_split<T, M>(A, op, acc);
     if constexpr (Op::NDOT > 0)
         grid_reduce<T, M, Op::NDOT>(acc, rb, op);
 }
@@ -95,6 +105,17 @@ void trace_end(int slot, hipStream_t s);
 template <typename T, int M, class Op>
 inline hipError_t launch_gspmv(const CsrView<T> &A, const Op &op, const RedBufs<T> &rb, hipStream_t s)
 {
+    if constexpr (Shape<T, M>::POW2 && long_rows_ok<Op>::value) {
+        if (A.split) {  // long rows: one wave per row
+            const void *fn = reinterpret_cast<const void *>(&k_gspmv_split<T, M, Op>);
+            const int grid = grid_for(fn, A.n, kBlock / 64);
+            const int slot = g_trace_every ? trace_begin(s, Op::kName, static_cast<int>(sizeof(T)), M, grid) : -1;
+            hipLaunchKernelGGL((k_gspmv_split<T, M, Op>), dim3(grid), dim3(kBlock), 0, s, A, op, rb);
+            if (slot >= 0)
+                trace_end(slot, s);
+            return hipGetLastError();
+        }
+    }
     const void *fn = reinterpret_cast<const void *>(&k_gspmv<T, M, Op>);
     const int grid = grid_for(fn, A.n, Shape<T, M>::TR);
     const int slot = g_trace_every ? trace_begin(s, Op::kName, static_cast<int>(sizeof(T)), M, grid) : -1;
@@ -246,10 +267,10 @@ class Engine {
     int chunk_ = 16, ndirs_ = kGcrMax, max_outer_ = 500;
     int amg_chunk_ = 2;  // iterations between polls with the AMG preconditioner
     int col_steps_[kMaxM] = {};  // refinement steps of each column since its admission (slot = steps % ndirs)
-    double tol_in_ = 0.1;
+    double tol_in_ = 0.2;
     double outer_batch_ = 1.0;  // share of a block's active columns that triggers a refinement step
     int outer_wait_ = 0;        // ... or this many iterations waited by a column, whichever first
-    int mixed_chunk_ = 4;       // inner iterations between polls (mixed precision)
+    int mixed_chunk_ = 8;       // inner iterations between polls (mixed precision)
     int stag_window_ = kStagWindow;
     int waited_ = 0;
 };

@@ -409,11 +409,11 @@ Engine::Engine(const mrhs_csr_s &A, int m, uint32_t flags, void *ws, const doubl
         }
     }
     chunk_ = env_int("MRHS_POLL_ITERS", 16, 1, 1024);
-    tol_in_ = env_double("MRHS_INNER_TOL", 0.1);
+    tol_in_ = env_double("MRHS_INNER_TOL", 0.2);
     max_outer_ = env_int("MRHS_MAX_OUTER", 500, 1, 100000);
     outer_batch_ = env_double("MRHS_OUTER_BATCH", 1.0);
     outer_wait_ = env_int("MRHS_OUTER_WAIT", 0, 0, 100000);
-    mixed_chunk_ = env_int("MRHS_MIXED_POLL", 4, 1, 1024);
+    mixed_chunk_ = env_int("MRHS_MIXED_POLL", 8, 1, 1024);
     stag_window_ = env_int("MRHS_STAG_WINDOW", kStagWindow, 4, 100000);
     amg_chunk_ = env_int("MRHS_AMG_POLL", 2, 1, 1024);
 }
