@@ -552,19 +552,74 @@ mrhs_status Engine::finish(uint32_t cmask)
     return MRHS_OK;
 }
 
+namespace {
+
+// Block width the solver runs at for m right-hand sides.  In binary64 an odd
+// m >= 3 runs at m + 1, so every lane moves 16-byte vectors of two columns
+// instead of single elements (12.6M-row channel, time per iteration: m = 7
+// 3.20 -> 2.83 ms, m = 15 6.42 -> 5.46 ms, m = 9 unchanged); mixed precision
+// widens only when m + 1 is a multiple of 4 (binary32 lanes of four columns;
+// its m = 10 products are slower than m = 9).  The extra column has a zero
+// right-hand side and is finished at admission.  MRHS_PAD_ODD=0 keeps m.
+int solve_width(int m, uint32_t flags)
+{
+    const int pad = env_int("MRHS_PAD_ODD", 1, 0, 1);
+    if (!pad || m % 2 == 0 || m < 3 || m >= kMaxM)
+        return m;
+    if ((flags & MRHS_MIXED) && (m + 1) % 4 != 0)
+        return m;
+    return m + 1;
+}
+
+// out (n x mo) = in (n x mi) in its first min(mi, mo) columns, zero in the others
+__global__ void k_rewidth(double *__restrict__ out, const double *__restrict__ in, int32_t n, int mo, int mi)
+{
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= static_cast<int64_t>(n) * mo)
+        return;
+    const int64_t i = k / mo;
+    const int c = static_cast<int>(k - i * mo);
+    out[k] = c < mi ? in[i * mi + c] : 0.0;
+}
+
+hipError_t rewidth(double *out, const double *in, int32_t n, int mo, int mi, hipStream_t s)
+{
+    const int64_t count = static_cast<int64_t>(n) * mo;
+    hipLaunchKernelGGL(k_rewidth, dim3(static_cast<unsigned>((count + 255) / 256)), dim3(256), 0, s, out, in, n, mo,
+                       mi);
+    return hipGetLastError();
+}
+
+size_t padded_block_bytes(int32_t n, int w) { return align_up(sizeof(double) * static_cast<size_t>(n) * w); }
+
+} // namespace
+
 size_t solve_workspace_bytes(const mrhs_csr_s &A, int32_t m, uint32_t flags, const AmgDev *amg)
 {
-    return Engine::workspace_bytes(A, m, flags, amg);
+    const int w = solve_width(m, flags);
+    const size_t eng = align_up(Engine::workspace_bytes(A, w, flags, amg));
+    return w == m ? eng : eng + 2 * padded_block_bytes(A.n, w);
 }
 
 mrhs_status block_solve(const mrhs_csr_s &A, const double *B, double *X, const SolveParams &p, void *ws,
                         size_t ws_bytes, hipStream_t s, mrhs_col_info *info, Ctl *host_ctl, const AmgDev *amg)
 {
-    const int m = p.m;
-    const size_t need = Engine::workspace_bytes(A, m, p.flags, amg);
+    const size_t need = solve_workspace_bytes(A, p.m, p.flags, amg);
     if (ws_bytes < need)
         return set_error(MRHS_EINVAL, "workspace of %zu bytes is smaller than the %zu required", ws_bytes, need);
-    Engine e(A, m, p.flags, ws, B, X, s, host_ctl, amg);
+    const int m = solve_width(p.m, p.flags);
+    double *Xw = X;
+    const double *Bw = B;
+    if (m != p.m) {  // widened copies of B and X after the engine's workspace
+        char *tail = static_cast<char *>(ws) + align_up(Engine::workspace_bytes(A, m, p.flags, amg));
+        double *Bp = reinterpret_cast<double *>(tail);
+        Xw = reinterpret_cast<double *>(tail + padded_block_bytes(A.n, m));
+        MRHS_HIP(rewidth(Bp, B, A.n, m, p.m, s));
+        if (p.flags & MRHS_X0_GIVEN)
+            MRHS_HIP(rewidth(Xw, X, A.n, m, p.m, s));
+        Bw = Bp;
+    }
+    Engine e(A, m, p.flags, ws, Bw, Xw, s, host_ctl, amg);
     mrhs_status st = e.reset();
     if (st != MRHS_OK)
         return st;
@@ -581,12 +636,16 @@ mrhs_status block_solve(const mrhs_csr_s &A, const double *B, double *X, const S
     while (busy)
         if ((st = e.advance(&busy)) != MRHS_OK)
             return st;
-    if ((st = e.finish(all)) != MRHS_OK || (st = e.read_ctl()) != MRHS_OK)
+    if ((st = e.finish(all)) != MRHS_OK)
+        return st;
+    if (m != p.m)
+        MRHS_HIP(rewidth(X, Xw, A.n, p.m, m, s));
+    if ((st = e.read_ctl()) != MRHS_OK)
         return st;
     const Ctl &h = e.host();
     const bool mixed = (p.flags & MRHS_MIXED) != 0;
     mrhs_status worst = MRHS_OK;
-    for (int i = 0; i < m; ++i) {
+    for (int i = 0; i < p.m; ++i) {
         const mrhs_status cs = column_status(h.status[i]);
         if (info) {
             info[i].iters = mixed ? h.total_iters[i] : h.iters[i];
