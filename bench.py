@@ -261,29 +261,34 @@ def gspmv_sweep(torch, A, ms, dtypes, flush=False, reps=50):
     return out
 
 
-def solve_pair(torch, name, m, steps):
-    """binary64 and mixed block solves of one workload, its own matrix."""
+def solve_pair(torch, name, m, steps, reorder=False, amg_per_iter=None):
+    """binary64 and mixed block solves of one workload, its own matrix
+    (renumbered by reverse Cuthill-McKee when ``reorder``), then the AMG legs."""
     import numpy as np
     import paper_1711_10622_amd as mrhs
     from workloads import configs
     wl = configs.WORKLOADS[name]
     A = wl.matrix()
     Bh = wl.rhs(A.n, m)
-    M = mrhs.CsrMatrix.from_csr(A)
+    t0 = time.perf_counter()
+    M = mrhs.CsrMatrix.from_csr(A, reorder=reorder)
+    torch.cuda.synchronize()
+    create_s = time.perf_counter() - t0
     B = torch.from_numpy(Bh).to("cuda")
     X = torch.empty_like(B)
     ws = torch.empty(max(M.workspace_size(m, mixed=True), M.workspace_size(m)), dtype=torch.uint8, device="cuda")
-    res = {"n": A.n, "nnz": A.nnz, "m": m}
+    res = {"n": A.n, "nnz": A.nnz, "m": m, "reorder": bool(reorder), "csr_create_s": round(create_s, 3)}
     for mixed in (False, True):
         t, inf, _ = timed_solves(torch, M, B, X, ws, steps, mixed=mixed)
         res["mixed" if mixed else "fp64"] = {
             "s_per_rhs": round(t / m, 6), "iters_max": max(i["iters"] for i in inf),
             "outer_max": max(i["outer"] for i in inf), "max_relres": max(i["relres"] for i in inf)}
-        log(f"{name} m={m} {'mixed' if mixed else 'fp64'}: {t * 1e3:.1f} ms")
+        log(f"{name} m={m} {'mixed' if mixed else 'fp64'}{' rcm' if reorder else ''}: {t * 1e3:.1f} ms")
     res["mixed_speedup"] = round(res["fp64"]["s_per_rhs"] / res["mixed"]["s_per_rhs"], 3)
     del M, B, X, ws
     torch.cuda.empty_cache()
-    res["amg"] = amg_legs(torch, A, Bh, m, res["fp64"]["s_per_rhs"] * m, per_iter_ms=(1, m), steps=2)
+    res["amg"] = amg_legs(torch, A, Bh, m, res["fp64"]["s_per_rhs"] * m,
+                          per_iter_ms=amg_per_iter if amg_per_iter is not None else (1, m), steps=2, reorder=reorder)
     torch.cuda.empty_cache()
     return res
 
@@ -637,7 +642,7 @@ def summarize_profiles(out, workload, m):
     return 0
 
 
-def amg_legs(torch, A, Bh, m, t_jacobi, per_iter_ms=(1, 2, 4, 8, 16), steps=1):
+def amg_legs(torch, A, Bh, m, t_jacobi, per_iter_ms=(1, 2, 4, 8, 16), steps=1, reorder=False):
     """BiCGStab with the classical AMG preconditioner (the paper's solver,
     Section 4.1) on the same block: host setup time and hierarchy, the solve
     to 1e-10 against the Jacobi solve's time, its top kernels, and the time
@@ -646,7 +651,7 @@ def amg_legs(torch, A, Bh, m, t_jacobi, per_iter_ms=(1, 2, 4, 8, 16), steps=1):
     import numpy as np
     import paper_1711_10622_amd as mrhs
     from paper_1711_10622_amd import estimates as est
-    M = mrhs.CsrMatrix.from_csr(A)
+    M = mrhs.CsrMatrix.from_csr(A, reorder=reorder)
     t0 = time.perf_counter()
     H = mrhs.AmgHierarchy(M)
     setup = time.perf_counter() - t0
@@ -850,6 +855,7 @@ def main():
         extra["chan128"] = legs
         log(f"chan128: {legs}")
         extra["cube192_m8"] = solve_pair(torch, "cube192", 8, 1)
+        extra["cube192_m8_rcm"] = solve_pair(torch, "cube192", 8, 1, reorder=True, amg_per_iter=(8,))
         extra["projection_chan128"] = projection_step(torch)
         extra["serving"] = {"offered_5ms_gaps": serving(torch, n_req=300)}
         cap = extra["serving"]["offered_5ms_gaps"]["served_rhs_per_s"]

@@ -57,6 +57,9 @@ enum { MRHS_F64 = 0, MRHS_F32 = 1 };
 /* csr_create flags */
 #define MRHS_CSR_NULLSPACE_CONST 1u /* A*1 = 0 (pure Neumann/periodic): solves
                                        return x with its mean removed */
+#define MRHS_CSR_REORDER 2u         /* the solvers work on P A P^T, P the
+                                       permutation of csr_reorder_permutation;
+                                       every call keeps the caller's numbering */
 
 /* block_bicgstab_ex flags */
 #define MRHS_X0_GIVEN 1u   /* X holds the initial guess on entry */
@@ -100,7 +103,10 @@ const char *mrhs_version(void);
  * row_ptr, col_idx and val, plus what the solvers derive from them: the
  * diagonal and its inverse, the column-scaled matrix A D^-1 (the right
  * Jacobi preconditioner folded into the values) and binary32 roundings
- * (round-to-nearest-even) of val and of A D^-1.
+ * (round-to-nearest-even) of val and of A D^-1.  With MRHS_CSR_REORDER the
+ * solvers' arrays hold P A P^T and the handle also keeps the caller's arrays
+ * (gspmv uses those) and the permutation; solves copy B into the solver's
+ * numbering and X back (two extra n x m blocks of workspace).
  * EINVAL: n < 0, nnz out of range, a NULL array with n > 0, row_ptr[0] != 0,
  * decreasing row_ptr, row_ptr[n] != nnz, a column outside [0, n), or a
  * non-finite value.  A zero diagonal is accepted here and rejected by the
@@ -109,6 +115,19 @@ const char *mrhs_version(void);
 mrhs_status csr_create(int32_t n, int64_t nnz, const int32_t *row_ptr,
                        const int32_t *col_idx, const double *val,
                        uint32_t flags, mrhs_csr *out);
+
+/*
+ * The row renumbering MRHS_CSR_REORDER applies, computed on the host with no
+ * device involved: reverse Cuthill-McKee on the pattern of A + A^T (each
+ * connected component from a pseudo-peripheral row, neighbours by increasing
+ * degree, then index; the order reversed).  perm (host, n entries) receives
+ * perm[new] = old.  A numbering without locality (randomly permuted rows)
+ * makes every gather of a product fetch a cache line of its own; a banded
+ * one lets the rows gathered by one tile share lines.  EINVAL for an invalid
+ * pattern (as csr_create) or NULL arrays.
+ */
+mrhs_status csr_reorder_permutation(int32_t n, const int32_t *row_ptr,
+                                    const int32_t *col_idx, int32_t *perm);
 
 /* Free the handle and its device memory.  NULL is accepted. */
 mrhs_status csr_destroy(mrhs_csr A);
@@ -146,7 +165,8 @@ mrhs_status gspmv_ex(mrhs_csr A, int32_t dtype, const void *X, void *Y,
  * 2 u_i 2^-53 - 1 with u_i the top 53 bits of output number i (counting from
  * 0) of the SplitMix64 generator seeded with MRHS_SHADOW_SEED, i.e. of
  * mix(MRHS_SHADOW_SEED + (i + 1) * 0x9E3779B97F4A7C15).  It is generated
- * where it is used and never stored.  The binary32 inner solves of MRHS_MIXED
+ * where it is used and never stored; i counts the rows the solver works on
+ * (those of P A P^T for a matrix created with MRHS_CSR_REORDER).  The binary32 inner solves of MRHS_MIXED
  * (short solves restarted at every refinement step) take r^ = the signs (+1,
  * or -1 for a negative entry) of their own initial residual.
  */
@@ -326,7 +346,11 @@ enum { MRHS_AMG_OPERATOR = 0, MRHS_AMG_PROLONGATION = 1, MRHS_AMG_SPLIT = 2 };
 /*
  * Build the hierarchy of A on A's device (setup on the host, then upload).
  * theta <= 0, max_coarse <= 0, max_levels <= 0 select the defaults 0.25,
- * 256 and 25 (at most 25).  A must outlive the hierarchy.  EINVAL for an
+ * 256 and 25 (at most 25).  A must outlive the hierarchy.  For a matrix
+ * created with MRHS_CSR_REORDER the hierarchy is that of P A P^T (its levels,
+ * as amg_level_copy returns them, are in that numbering); amg_vcycle and
+ * block_bicgstab_amg still take and return blocks in the caller's numbering.
+ * EINVAL for an
  * empty matrix, a zero diagonal entry, theta >= 1 or a singular coarsest
  * operator; ENOMEM / EDEVICE for device failures.
  */

@@ -8,5 +8,5 @@ iterations built on the generalized sparse matrix-vector product Y = A X
 C ABI, include/mrhs.h); this package only marshals arguments.
 """
 from ._lib import SHADOW_SEED, MrhsError, load  # noqa: F401
-from .api import (AmgHierarchy, ChannelGrid, CsrMatrix, SolveServer, block_bicgstab, gspmv, stream_probe,  # noqa: F401
-                  trace_enable, trace_read)
+from .api import (AmgHierarchy, ChannelGrid, CsrMatrix, SolveServer, block_bicgstab, gspmv,  # noqa: F401
+                  reorder_permutation, stream_probe, trace_enable, trace_read)

@@ -17,7 +17,7 @@ OK, EAGAIN, EINVAL, ENOMEM, EDEVICE, ENOCONV, EBREAKDOWN, EBUDGET, ESHUTDOWN, EN
 STATUS_NAMES = {0: "OK", 1: "EAGAIN", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOCONV",
                 -5: "EBREAKDOWN", -6: "EBUDGET", -7: "ESHUTDOWN", -8: "ENOTFOUND"}
 F64, F32 = 0, 1
-CSR_NULLSPACE_CONST = 1
+CSR_NULLSPACE_CONST, CSR_REORDER = 1, 2
 X0_GIVEN, MIXED = 1, 2
 SERVER_MIXED = 1
 SHADOW_SEED = 17110622  # MRHS_SHADOW_SEED: seed of the BiCGStab shadow residual
@@ -25,7 +25,8 @@ NOALLOC_SCRATCH_BYTES = 64 << 20  # MRHS_NOALLOC_SCRATCH_BYTES
 
 # every symbol include/mrhs.h declares
 EXPORTS = (
-    "mrhs_last_error", "mrhs_version", "csr_create", "csr_destroy", "csr_info", "gspmv", "gspmv_ex",
+    "mrhs_last_error", "mrhs_version", "csr_create", "csr_destroy", "csr_info", "csr_reorder_permutation",
+    "gspmv", "gspmv_ex",
     "block_bicgstab", "block_bicgstab_ex", "block_bicgstab_workspace_size", "block_bicgstab_noalloc",
     "solve_server_create", "solve_server_register", "solve_server_submit", "solve_server_poll",
     "solve_server_stats", "solve_server_destroy",
@@ -76,6 +77,7 @@ def _declare(lib):
         "csr_create": [i32, i64, vp, vp, vp, u32, c.POINTER(vp)],
         "csr_destroy": [vp],
         "csr_info": [vp, c.POINTER(i32), c.POINTER(i64), c.POINTER(sz)],
+        "csr_reorder_permutation": [i32, vp, vp, vp],
         "gspmv": [vp, vp, vp, i32],
         "gspmv_ex": [vp, i32, vp, vp, i32, vp],
         "block_bicgstab": [vp, vp, vp, i32, f64, i32],

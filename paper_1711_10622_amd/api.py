@@ -42,7 +42,7 @@ def _check_block(t, n, m, dtype, name):
 class CsrMatrix:
     """A CRS matrix resident on the current GPU (``csr_create``)."""
 
-    def __init__(self, n, row_ptr, col_idx, val, nullspace_const=False):
+    def __init__(self, n, row_ptr, col_idx, val, nullspace_const=False, reorder=False):
         lib = _lib.load()
         self._lib = lib
         self.n = int(n)
@@ -52,7 +52,8 @@ class CsrMatrix:
         self.nnz = int(ci.shape[0])
         self.nullspace_const = bool(nullspace_const)
         h = ctypes.c_void_p()
-        flags = _lib.CSR_NULLSPACE_CONST if nullspace_const else 0
+        flags = (_lib.CSR_NULLSPACE_CONST if nullspace_const else 0) | (_lib.CSR_REORDER if reorder else 0)
+        self.reorder = bool(reorder)
         _lib.check(lib.csr_create(self.n, self.nnz, rp.ctypes.data if rp.size else None,
                                   ci.ctypes.data if ci.size else None,
                                   va.ctypes.data if va.size else None, flags, ctypes.byref(h)),
@@ -60,11 +61,11 @@ class CsrMatrix:
         self._h = h
 
     @classmethod
-    def from_csr(cls, A, nullspace_const=None):
+    def from_csr(cls, A, nullspace_const=None, reorder=False):
         """From any object with ``n, row_ptr, col, val`` (e.g. the workload generators)."""
         if nullspace_const is None:
             nullspace_const = bool(getattr(A, "nullspace_const", False))
-        return cls(A.n, A.row_ptr, A.col, A.val, nullspace_const)
+        return cls(A.n, A.row_ptr, A.col, A.val, nullspace_const, reorder)
 
     @property
     def handle(self):
@@ -252,6 +253,17 @@ class AmgHierarchy:
             self.close()
         except Exception:
             pass
+
+
+def reorder_permutation(A):
+    """perm[new] = old of the renumbering MRHS_CSR_REORDER applies
+    (``csr_reorder_permutation``, host only) for an object with ``n, row_ptr, col``."""
+    rp = np.ascontiguousarray(A.row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(A.col, dtype=np.int32)
+    perm = np.empty(int(A.n), dtype=np.int32)
+    _lib.check(_lib.load().csr_reorder_permutation(int(A.n), rp.ctypes.data, ci.ctypes.data if ci.size else None,
+                                                   perm.ctypes.data), "csr_reorder_permutation")
+    return perm
 
 
 def gspmv(A: CsrMatrix, X, out=None, stream=None):

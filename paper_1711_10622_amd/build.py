@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmrhs.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["mrhs.hip", "solver.hip", "server.hip", "projection.hip", "probe.hip", "noalloc.hip", "amg_setup.hip", "amg.hip"]
+SOURCES = ["mrhs.hip", "solver.hip", "server.hip", "projection.hip", "probe.hip", "noalloc.hip", "amg_setup.hip", "amg.hip", "reorder.hip"]
 ARCH = "gfx950"
 
 

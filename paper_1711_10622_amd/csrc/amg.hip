@@ -498,6 +498,14 @@ struct mrhs_amg_s {
 namespace mrhs {
 namespace {
 
+// workspace of one amg_vcycle call: the V-cycle's, plus renumbered copies of
+// B and X when the matrix was renumbered
+size_t vcycle_call_bytes(const mrhs_amg_s &H, int32_t m)
+{
+    const size_t v = amg_vcycle_bytes(H.dev, m);
+    return H.A->perm ? align_up(v) + 2 * padded_block_bytes(H.A->n, m) : v;
+}
+
 constexpr size_t kPadElems = 4;  // zero padding past the nonzeros (whole-vector tile loads)
 
 template <typename T>
@@ -746,7 +754,7 @@ MRHS_API mrhs_status amg_vcycle_workspace_size(mrhs_amg H, int32_t m, size_t *by
         return set_error(MRHS_EINVAL, "NULL argument");
     if (m < 1 || m > kMaxM)
         return set_error(MRHS_EINVAL, "m = %d outside [1, 16]", m);
-    *bytes = amg_vcycle_bytes(H->dev, m);
+    *bytes = vcycle_call_bytes(*H, m);
     return MRHS_OK;
 }
 
@@ -760,7 +768,7 @@ MRHS_API mrhs_status amg_vcycle(mrhs_amg H, const double *B, double *X, int32_t 
         return set_error(MRHS_EINVAL, "m = %d outside [1, 16]", m);
     if (!B || !X)
         return set_error(MRHS_EINVAL, "B or X is NULL");
-    const size_t need = amg_vcycle_bytes(H->dev, m);
+    const size_t need = vcycle_call_bytes(*H, m);
     if (need && (!workspace || ws_bytes < need))
         return set_error(MRHS_EINVAL, "workspace of %zu bytes is smaller than the %zu required", ws_bytes, need);
     const size_t blk = sizeof(double) * static_cast<size_t>(H->dev.lev[0].n) * m;
@@ -770,8 +778,19 @@ MRHS_API mrhs_status amg_vcycle(mrhs_amg H, const double *B, double *X, int32_t 
         return set_error(MRHS_EINVAL, "B, X and the workspace must not overlap");
     if ((b & 15u) || (x & 15u) || (w & 15u))
         return set_error(MRHS_EINVAL, "B, X and the workspace must be 16-byte aligned");
-    const hipError_t e = dispatch_m(m, VcLaunch{&H->dev, B, X, static_cast<char *>(workspace),
-                                                static_cast<hipStream_t>(hip_stream)});
+    const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const int32_t *perm = H->A->perm;
+    hipError_t e = hipSuccess;
+    if (perm) {  // the hierarchy is of the renumbered matrix: renumber B in, X out
+        char *tail = static_cast<char *>(workspace) + align_up(amg_vcycle_bytes(H->dev, m));
+        double *Bp = reinterpret_cast<double *>(tail);
+        double *Xp = reinterpret_cast<double *>(tail + padded_block_bytes(H->A->n, m));
+        if ((e = to_solver(Bp, B, perm, H->A->n, m, m, s)) == hipSuccess &&
+            (e = dispatch_m(m, VcLaunch{&H->dev, Bp, Xp, static_cast<char *>(workspace), s})) == hipSuccess)
+            e = to_user(X, Xp, perm, H->A->n, m, m, s);
+    } else {
+        e = dispatch_m(m, VcLaunch{&H->dev, B, X, static_cast<char *>(workspace), s});
+    }
     if (e != hipSuccess)
         return set_error(MRHS_EDEVICE, "V-cycle launch failed: %s", hipGetErrorString(e));
     return MRHS_OK;

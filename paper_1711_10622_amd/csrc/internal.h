@@ -27,6 +27,13 @@ struct mrhs_csr_s {
     double *dinv = nullptr;   // [n]
     int32_t reach = 0;        // median over rows of max(col - row), >= 0
     size_t bytes = 0;
+    // MRHS_CSR_REORDER: the arrays above hold P A P^T (solver row i is the
+    // caller's row perm[i]); the caller's own numbering is kept for gspmv
+    int32_t *perm = nullptr;  // [n] device, null without reordering
+    int32_t *urp = nullptr, *uci = nullptr;
+    double *uval = nullptr;
+    float *uval32 = nullptr;
+    int32_t ureach = 0;
 };
 
 namespace mrhs {
@@ -62,6 +69,27 @@ inline CsrView<float> view<float>(const mrhs_csr_s &A, bool scaled)
 {
     return {A.rp, A.ci, scaled ? A.valh32 : A.val32, A.n, A.reach, 0};
 }
+
+// The matrix in the caller's numbering (gspmv): the handle's own arrays, or
+// the kept originals of a reordered handle.
+template <typename T>
+inline CsrView<T> user_view(const mrhs_csr_s &A);
+
+template <>
+inline CsrView<double> user_view<double>(const mrhs_csr_s &A)
+{
+    return A.perm ? CsrView<double>{A.urp, A.uci, A.uval, A.n, A.ureach, 0} : view<double>(A, false);
+}
+
+template <>
+inline CsrView<float> user_view<float>(const mrhs_csr_s &A)
+{
+    return A.perm ? CsrView<float>{A.urp, A.uci, A.uval32, A.n, A.ureach, 0} : view<float>(A, false);
+}
+
+// Reverse Cuthill-McKee permutation of the symmetrized pattern (reorder.hip):
+// perm[new] = old.
+void rcm_permutation(int32_t n, const int32_t *rp, const int32_t *ci, int32_t *perm);
 
 template <typename T, int M, class Op>
 __global__ void __launch_bounds__(kBlock) k_gspmv(CsrView<T> A, Op op, RedBufs<T> rb)
@@ -286,6 +314,14 @@ struct SolveParams {
     int32_t maxit;
     uint32_t flags;
 };
+
+// Copies between a caller's n x m block (caller's row numbering) and an
+// n x w solver block (w >= m; row i is the caller's row perm[i], or row i
+// when perm is NULL; columns m..w-1 zero), and the bytes of such a block
+// rounded up to the workspace alignment.
+hipError_t to_solver(double *sv, const double *us, const int32_t *perm, int32_t n, int w, int m, hipStream_t s);
+hipError_t to_user(double *us, const double *sv, const int32_t *perm, int32_t n, int w, int m, hipStream_t s);
+size_t padded_block_bytes(int32_t n, int w);
 
 size_t solve_workspace_bytes(const mrhs_csr_s &A, int32_t m, uint32_t flags, const AmgDev *amg = nullptr);
 // host_ctl and amg as for Engine

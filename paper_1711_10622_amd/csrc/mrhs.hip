@@ -206,7 +206,8 @@ void free_csr(mrhs_csr_s *A)
 {
     if (!A)
         return;
-    void *ptrs[] = {A->rp, A->ci, A->val, A->valh, A->val32, A->valh32, A->diag, A->dinv};
+    void *ptrs[] = {A->rp,   A->ci,   A->val, A->valh, A->val32, A->valh32, A->diag,
+                    A->dinv, A->perm, A->urp, A->uci, A->uval, A->uval32};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -246,7 +247,7 @@ struct StoreLaunch {
     template <int M>
     hipError_t operator()() const
     {
-        return launch_gspmv<T, M>(view<T>(*A, false),
+        return launch_gspmv<T, M>(user_view<T>(*A),
                                   OpStore<T, M>{static_cast<const T *>(X), static_cast<T *>(Y)},
                                   RedBufs<T>{nullptr, nullptr, nullptr}, s);
     }
@@ -272,7 +273,7 @@ MRHS_API mrhs_status csr_create(int32_t n, int64_t nnz, const int32_t *row_ptr, 
         return set_error(MRHS_EINVAL, "n = %d < 0", n);
     if (nnz < 0 || nnz > INT32_MAX)
         return set_error(MRHS_EINVAL, "nnz = %lld outside [0, 2^31)", static_cast<long long>(nnz));
-    if (flags & ~MRHS_CSR_NULLSPACE_CONST)
+    if (flags & ~(MRHS_CSR_NULLSPACE_CONST | MRHS_CSR_REORDER))
         return set_error(MRHS_EINVAL, "unknown flags 0x%x", flags);
     if (n > 0 && !row_ptr)
         return set_error(MRHS_EINVAL, "row_ptr is NULL");
@@ -325,6 +326,51 @@ MRHS_API mrhs_status csr_create(int32_t n, int64_t nnz, const int32_t *row_ptr, 
         *out = A;
         return MRHS_OK;
     }
+    // MRHS_CSR_REORDER: the solvers get P A P^T (rows and columns renumbered
+    // by reverse Cuthill-McKee), the caller's arrays are kept for gspmv
+    std::vector<int32_t> perm, prp, pci;
+    std::vector<double> pval, pdiag;
+    const int32_t *user_rp = row_ptr, *user_ci = col_idx;  // the caller's numbering
+    if (flags & MRHS_CSR_REORDER) {
+        perm.resize(n);
+        rcm_permutation(n, row_ptr, col_idx, perm.data());
+        std::vector<int32_t> iperm(n);
+        for (int32_t k = 0; k < n; ++k)
+            iperm[perm[k]] = k;
+        prp.assign(static_cast<size_t>(n) + 1, 0);
+        pci.resize(static_cast<size_t>(nnz));
+        pval.resize(static_cast<size_t>(nnz));
+        pdiag.resize(n);
+        std::vector<int32_t> preach(n, 0);
+        std::vector<std::pair<int32_t, double>> row;
+        for (int32_t k = 0; k < n; ++k) {
+            const int32_t i = perm[k];
+            row.clear();
+            for (int32_t j = row_ptr[i]; j < row_ptr[i + 1]; ++j)
+                row.emplace_back(iperm[col_idx[j]], val[j]);
+            // entries of a row keep their relative order among equal columns
+            std::stable_sort(row.begin(), row.end(),
+                             [](const std::pair<int32_t, double> &a, const std::pair<int32_t, double> &b) {
+                                 return a.first < b.first;
+                             });
+            int32_t w = prp[k];
+            for (const auto &e : row) {
+                pci[w] = e.first;
+                pval[w] = e.second;
+                preach[k] = std::max(preach[k], e.first - k);
+                ++w;
+            }
+            prp[k + 1] = w;
+            pdiag[k] = diag[i];
+        }
+        A->ureach = A->reach;
+        std::nth_element(preach.begin(), preach.begin() + n / 2, preach.end());
+        A->reach = preach[n / 2];
+        row_ptr = prp.data();
+        col_idx = pci.data();
+        diag.swap(pdiag);
+    }
+    const double *sval = (flags & MRHS_CSR_REORDER) ? pval.data() : val;
     size_t total = 0;
     mrhs_status st = MRHS_OK;
     if ((st = dev_alloc(&A->rp, static_cast<size_t>(n) + 1, total)) ||
@@ -351,10 +397,37 @@ MRHS_API mrhs_status csr_create(int32_t n, int64_t nnz, const int32_t *row_ptr, 
     }
     if ((e = hipMemcpy(A->rp, row_ptr, sizeof(int32_t) * (static_cast<size_t>(n) + 1), hipMemcpyHostToDevice)) ||
         (nnz > 0 && (e = hipMemcpy(A->ci, col_idx, sizeof(int32_t) * nnz, hipMemcpyHostToDevice))) ||
-        (nnz > 0 && (e = hipMemcpy(A->val, val, sizeof(double) * nnz, hipMemcpyHostToDevice))) ||
+        (nnz > 0 && (e = hipMemcpy(A->val, sval, sizeof(double) * nnz, hipMemcpyHostToDevice))) ||
         (e = hipMemcpy(A->diag, diag.data(), sizeof(double) * n, hipMemcpyHostToDevice))) {
         free_csr(A);
         return set_error(MRHS_EDEVICE, "upload failed: %s", hipGetErrorString(e));
+    }
+    if (flags & MRHS_CSR_REORDER) {
+        // the caller's numbering, for gspmv: row offsets, columns, binary64
+        // values and their binary32 rounding
+        std::vector<float> v32(static_cast<size_t>(nnz));
+        for (int64_t j = 0; j < nnz; ++j)
+            v32[j] = static_cast<float>(val[j]);  // round to nearest even
+        if ((st = dev_alloc(&A->perm, static_cast<size_t>(n), total)) ||
+            (st = dev_alloc(&A->urp, static_cast<size_t>(n) + 1, total)) ||
+            (st = dev_alloc(&A->uci, static_cast<size_t>(nnz) + kPad, total)) ||
+            (st = dev_alloc(&A->uval, static_cast<size_t>(nnz) + kPad, total)) ||
+            (st = dev_alloc(&A->uval32, static_cast<size_t>(nnz) + kPad, total))) {
+            free_csr(A);
+            return st;
+        }
+        A->bytes = total;
+        if ((e = hipMemset(A->uci + nnz, 0, sizeof(int32_t) * kPad)) ||
+            (e = hipMemset(A->uval + nnz, 0, sizeof(double) * kPad)) ||
+            (e = hipMemset(A->uval32 + nnz, 0, sizeof(float) * kPad)) ||
+            (e = hipMemcpy(A->perm, perm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice)) ||
+            (e = hipMemcpy(A->urp, user_rp, sizeof(int32_t) * (static_cast<size_t>(n) + 1), hipMemcpyHostToDevice)) ||
+            (nnz > 0 && (e = hipMemcpy(A->uci, user_ci, sizeof(int32_t) * nnz, hipMemcpyHostToDevice))) ||
+            (nnz > 0 && (e = hipMemcpy(A->uval, val, sizeof(double) * nnz, hipMemcpyHostToDevice))) ||
+            (nnz > 0 && (e = hipMemcpy(A->uval32, v32.data(), sizeof(float) * nnz, hipMemcpyHostToDevice)))) {
+            free_csr(A);
+            return set_error(MRHS_EDEVICE, "upload failed: %s", hipGetErrorString(e));
+        }
     }
     hipLaunchKernelGGL(k_derive_rows, dim3((n + 255) / 256), dim3(256), 0, 0, n, A->diag, A->dinv);
     if (nnz > 0)

@@ -26,18 +26,22 @@ namespace {
 constexpr int kSlots = sched::kSlots;
 static_assert(kSlots == kMaxM, "a lane's slots are the columns of one engine block");
 
-__global__ void k_scatter_col(double *__restrict__ blk, const double *__restrict__ v, int32_t n, int c)
+// column c of the engine's block (solver numbering: row i is the caller's
+// row perm[i], or row i) from / to an n-vector in the caller's numbering
+__global__ void k_scatter_col(double *__restrict__ blk, const double *__restrict__ v, const int32_t *__restrict__ perm,
+                              int32_t n, int c)
 {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n)
-        blk[i * kSlots + c] = v[i];
+        blk[i * kSlots + c] = v[perm ? perm[i] : i];
 }
 
-__global__ void k_gather_col(double *__restrict__ v, const double *__restrict__ blk, int32_t n, int c)
+__global__ void k_gather_col(double *__restrict__ v, const double *__restrict__ blk, const int32_t *__restrict__ perm,
+                             int32_t n, int c)
 {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n)
-        v[i] = blk[i * kSlots + c];
+        v[perm ? perm[i] : i] = blk[i * kSlots + c];
 }
 
 size_t engine_bytes(const mrhs_csr_s &A, uint32_t flags)
@@ -115,7 +119,7 @@ class HipDevice final : public sched::Device {
                 ok = hipMemcpyAsync(stage_ + static_cast<size_t>(c) * n, host_ + static_cast<size_t>(c) * n, vbytes,
                                     hipMemcpyHostToDevice, s_) == hipSuccess;
                 hipLaunchKernelGGL(k_scatter_col, dim3(grid), dim3(256), 0, s_, B_,
-                                   stage_ + static_cast<size_t>(c) * n, n, c);
+                                   stage_ + static_cast<size_t>(c) * n, A_.perm, n, c);
                 ok = ok && hipGetLastError() == hipSuccess;
             }
             ok = ok && eng_->start(admit, tol, maxit, false) == MRHS_OK;
@@ -132,7 +136,7 @@ class HipDevice final : public sched::Device {
             if (!((done >> c) & 1u))
                 continue;
             hipLaunchKernelGGL(k_gather_col, dim3(grid), dim3(256), 0, s_, stage_ + static_cast<size_t>(c) * n, X_,
-                               n, c);
+                               A_.perm, n, c);
             ok = hipGetLastError() == hipSuccess &&
                  hipMemcpyAsync(host_ + static_cast<size_t>(c) * n, stage_ + static_cast<size_t>(c) * n, vbytes,
                                 hipMemcpyDeviceToHost, s_) == hipSuccess;

@@ -571,34 +571,59 @@ int solve_width(int m, uint32_t flags)
     return m + 1;
 }
 
-// out (n x mo) = in (n x mi) in its first min(mi, mo) columns, zero in the others
-__global__ void k_rewidth(double *__restrict__ out, const double *__restrict__ in, int32_t n, int mo, int mi)
+} // namespace
+
+// Between the caller's blocks (n x m, caller's row numbering) and the
+// solver's (n x w, w >= m, row i = the caller's row perm[i], or row i without
+// a permutation).  to_solver: sv[i][c] = us[perm[i]][c] for c < m, 0 for
+// m <= c < w.  to_user: us[perm[i]][c] = sv[i][c] for c < m.
+__global__ void k_to_solver(double *__restrict__ sv, const double *__restrict__ us, const int32_t *__restrict__ perm,
+                            int32_t n, int w, int m)
 {
     const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (k >= static_cast<int64_t>(n) * mo)
+    if (k >= static_cast<int64_t>(n) * w)
         return;
-    const int64_t i = k / mo;
-    const int c = static_cast<int>(k - i * mo);
-    out[k] = c < mi ? in[i * mi + c] : 0.0;
+    const int64_t i = k / w;
+    const int c = static_cast<int>(k - i * w);
+    const int64_t u = perm ? perm[i] : i;
+    sv[k] = c < m ? us[u * m + c] : 0.0;
 }
 
-hipError_t rewidth(double *out, const double *in, int32_t n, int mo, int mi, hipStream_t s)
+__global__ void k_to_user(double *__restrict__ us, const double *__restrict__ sv, const int32_t *__restrict__ perm,
+                          int32_t n, int w, int m)
 {
-    const int64_t count = static_cast<int64_t>(n) * mo;
-    hipLaunchKernelGGL(k_rewidth, dim3(static_cast<unsigned>((count + 255) / 256)), dim3(256), 0, s, out, in, n, mo,
-                       mi);
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= static_cast<int64_t>(n) * m)
+        return;
+    const int64_t i = k / m;
+    const int c = static_cast<int>(k - i * m);
+    const int64_t u = perm ? perm[i] : i;
+    us[u * m + c] = sv[i * w + c];
+}
+
+hipError_t to_solver(double *sv, const double *us, const int32_t *perm, int32_t n, int w, int m, hipStream_t s)
+{
+    const int64_t count = static_cast<int64_t>(n) * w;
+    hipLaunchKernelGGL(k_to_solver, dim3(static_cast<unsigned>((count + 255) / 256)), dim3(256), 0, s, sv, us, perm,
+                       n, w, m);
+    return hipGetLastError();
+}
+
+hipError_t to_user(double *us, const double *sv, const int32_t *perm, int32_t n, int w, int m, hipStream_t s)
+{
+    const int64_t count = static_cast<int64_t>(n) * m;
+    hipLaunchKernelGGL(k_to_user, dim3(static_cast<unsigned>((count + 255) / 256)), dim3(256), 0, s, us, sv, perm, n,
+                       w, m);
     return hipGetLastError();
 }
 
 size_t padded_block_bytes(int32_t n, int w) { return align_up(sizeof(double) * static_cast<size_t>(n) * w); }
 
-} // namespace
-
 size_t solve_workspace_bytes(const mrhs_csr_s &A, int32_t m, uint32_t flags, const AmgDev *amg)
 {
     const int w = solve_width(m, flags);
     const size_t eng = align_up(Engine::workspace_bytes(A, w, flags, amg));
-    return w == m ? eng : eng + 2 * padded_block_bytes(A.n, w);
+    return (w == m && !A.perm) ? eng : eng + 2 * padded_block_bytes(A.n, w);
 }
 
 mrhs_status block_solve(const mrhs_csr_s &A, const double *B, double *X, const SolveParams &p, void *ws,
@@ -608,15 +633,16 @@ mrhs_status block_solve(const mrhs_csr_s &A, const double *B, double *X, const S
     if (ws_bytes < need)
         return set_error(MRHS_EINVAL, "workspace of %zu bytes is smaller than the %zu required", ws_bytes, need);
     const int m = solve_width(p.m, p.flags);
+    const bool copy = m != p.m || A.perm;
     double *Xw = X;
     const double *Bw = B;
-    if (m != p.m) {  // widened copies of B and X after the engine's workspace
+    if (copy) {  // widened and/or renumbered copies of B and X after the engine's workspace
         char *tail = static_cast<char *>(ws) + align_up(Engine::workspace_bytes(A, m, p.flags, amg));
         double *Bp = reinterpret_cast<double *>(tail);
         Xw = reinterpret_cast<double *>(tail + padded_block_bytes(A.n, m));
-        MRHS_HIP(rewidth(Bp, B, A.n, m, p.m, s));
+        MRHS_HIP(to_solver(Bp, B, A.perm, A.n, m, p.m, s));
         if (p.flags & MRHS_X0_GIVEN)
-            MRHS_HIP(rewidth(Xw, X, A.n, m, p.m, s));
+            MRHS_HIP(to_solver(Xw, X, A.perm, A.n, m, p.m, s));
         Bw = Bp;
     }
     Engine e(A, m, p.flags, ws, Bw, Xw, s, host_ctl, amg);
@@ -638,8 +664,8 @@ mrhs_status block_solve(const mrhs_csr_s &A, const double *B, double *X, const S
             return st;
     if ((st = e.finish(all)) != MRHS_OK)
         return st;
-    if (m != p.m)
-        MRHS_HIP(rewidth(X, Xw, A.n, p.m, m, s));
+    if (copy)
+        MRHS_HIP(to_user(X, Xw, A.perm, A.n, m, p.m, s));
     if ((st = e.read_ctl()) != MRHS_OK)
         return st;
     const Ctl &h = e.host();
