@@ -570,7 +570,7 @@ OP_NAMES = {"OpXR": "xr_update", "OpSpmv2": "spmv_omega", "OpSpmv1": "spmv_sigma
 
 def kernel_class(name):
     """'void mrhs::k_stream<double, 16, mrhs::OpXR<double, 16> >(...)' -> 'xr_update/f64/m16'."""
-    mo = re.search(r"mrhs::k_(?:gspmv|stream)<(double|float), (\d+), mrhs::(\w+)", name)
+    mo = re.search(r"mrhs::k_(?:gspmv_march|gspmv|stream)<(double|float), (\d+), mrhs::(\w+)", name)
     if not mo:
         return name.split("(")[0][:60]
     return f"{OP_NAMES.get(mo.group(3), mo.group(3))}/{'f64' if mo.group(1) == 'double' else 'f32'}/m{mo.group(2)}"

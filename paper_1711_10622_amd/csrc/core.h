@@ -448,6 +448,72 @@ struct long_rows_ok : std::false_type {};
 template <class Op>
 struct long_rows_ok<Op, std::void_t<decltype(Op::kLongRows)>> : std::integral_constant<bool, Op::kLongRows> {};
 
+// Stages the row offsets of rows r0 .. r0 + nr of A in s_rp, then (when
+// they fit NZCAP) the rows' column indices and values in s_ci / s_va with
+// coalesced streaming loads.  16-byte loads start at the 4-aligned index
+// zb <= z0 = row_ptr[r0] (the matrix arrays carry 4 elements of padding, so
+// whole vectors stay in bounds), and every thread issues all of its loads
+// before writing any of them to LDS.  Entry z0 + k is then at s_ci[lead + k].
+// The caller synchronizes before reading the indices and values.
+struct Staged {
+    int32_t z0;
+    int lead;
+    bool staged;
+};
+
+template <typename T, int NZCAP>
+__device__ __forceinline__ Staged stage_csr(const CsrView<T> &A, int32_t r0, int nr, int32_t *s_rp, int32_t *s_ci,
+                                            T *s_va)
+{
+    const int tid = threadIdx.x;
+    for (int k = tid; k <= nr; k += kBlock)
+        s_rp[k] = A.rp[r0 + k];
+    __syncthreads();
+    const int32_t z0 = s_rp[0];
+    const int cnt = s_rp[nr] - z0;
+    const int32_t zb = z0 & ~3;
+    const int lead = z0 - zb;
+    const bool staged = cnt + lead <= NZCAP;
+    if (staged) {
+        using I4 = int __attribute__((ext_vector_type(4)));
+        constexpr int VV = 16 / static_cast<int>(sizeof(T));
+        using TV = T __attribute__((ext_vector_type(VV)));
+        constexpr int CI_PT = ((NZCAP + 4) / 4 + kBlock - 1) / kBlock;
+        constexpr int VA_PT = ((NZCAP + 4) / VV + kBlock - 1) / kBlock;
+        const int nci = (cnt + lead + 3) / 4;
+        const int nva = (cnt + lead + VV - 1) / VV;
+        const I4 *gci = reinterpret_cast<const I4 *>(A.ci + zb);
+        const TV *gva = reinterpret_cast<const TV *>(A.va + zb);
+        I4 bci[CI_PT];
+        TV bva[VA_PT];
+#pragma unroll
+        for (int u = 0; u < CI_PT; ++u) {
+            const int k = tid + u * kBlock;
+            if (k < nci)
+                bci[u] = __builtin_nontemporal_load(gci + k);
+        }
+#pragma unroll
+        for (int u = 0; u < VA_PT; ++u) {
+            const int k = tid + u * kBlock;
+            if (k < nva)
+                bva[u] = __builtin_nontemporal_load(gva + k);
+        }
+#pragma unroll
+        for (int u = 0; u < CI_PT; ++u) {
+            const int k = tid + u * kBlock;
+            if (k < nci)
+                reinterpret_cast<I4 *>(s_ci)[k] = bci[u];
+        }
+#pragma unroll
+        for (int u = 0; u < VA_PT; ++u) {
+            const int k = tid + u * kBlock;
+            if (k < nva)
+                reinterpret_cast<TV *>(s_va)[k] = bva[u];
+        }
+    }
+    return {z0, lead, staged};
+}
+
 // Y-side of a generalized SpMV over every tile of this workgroup.  The
 // tile's row offsets, column indices and values are first staged in LDS with
 // coalesced streaming loads (one pass over HBM, no reuse in cache needed), then
@@ -476,54 +542,10 @@ __device__ __forceinline__ void gspmv_tiles(const CsrView<T> &A, const Op &op,
             continue;
         const int32_t r0 = tile * S::TR;
         const int nr = min(S::TR, A.n - r0);
-        for (int k = tid; k <= nr; k += kBlock)
-            s_rp[k] = A.rp[r0 + k];
-        __syncthreads();
-        const int32_t z0 = s_rp[0];
-        const int cnt = s_rp[nr] - z0;
-        // 16-byte loads from the 4-aligned index zb <= z0 (the matrix arrays
-        // carry 4 elements of padding, so whole vectors stay in bounds); every
-        // thread issues all of its loads before writing any of them to LDS
-        const int32_t zb = z0 & ~3;
-        const int lead = z0 - zb;
-        const bool staged = cnt + lead <= S::NZCAP;
-        if (staged) {
-            using I4 = int __attribute__((ext_vector_type(4)));
-            constexpr int VV = 16 / static_cast<int>(sizeof(T));
-            using TV = T __attribute__((ext_vector_type(VV)));
-            constexpr int CI_PT = ((S::NZCAP + 4) / 4 + kBlock - 1) / kBlock;
-            constexpr int VA_PT = ((S::NZCAP + 4) / VV + kBlock - 1) / kBlock;
-            const int nci = (cnt + lead + 3) / 4;
-            const int nva = (cnt + lead + VV - 1) / VV;
-            const I4 *gci = reinterpret_cast<const I4 *>(A.ci + zb);
-            const TV *gva = reinterpret_cast<const TV *>(A.va + zb);
-            I4 bci[CI_PT];
-            TV bva[VA_PT];
-#pragma unroll
-            for (int u = 0; u < CI_PT; ++u) {
-                const int k = tid + u * kBlock;
-                if (k < nci)
-                    bci[u] = __builtin_nontemporal_load(gci + k);
-            }
-#pragma unroll
-            for (int u = 0; u < VA_PT; ++u) {
-                const int k = tid + u * kBlock;
-                if (k < nva)
-                    bva[u] = __builtin_nontemporal_load(gva + k);
-            }
-#pragma unroll
-            for (int u = 0; u < CI_PT; ++u) {
-                const int k = tid + u * kBlock;
-                if (k < nci)
-                    reinterpret_cast<I4 *>(s_ci)[k] = bci[u];
-            }
-#pragma unroll
-            for (int u = 0; u < VA_PT; ++u) {
-                const int k = tid + u * kBlock;
-                if (k < nva)
-                    reinterpret_cast<TV *>(s_va)[k] = bva[u];
-            }
-        }
+        const Staged st = stage_csr<T, S::NZCAP>(A, r0, nr, s_rp, s_ci, s_va);
+        const int32_t z0 = st.z0;
+        const int lead = st.lead;
+        const bool staged = st.staged;
         __syncthreads();
         const int32_t *lci = s_ci + lead;
         const T *lva = s_va + lead;
@@ -554,6 +576,269 @@ __device__ __forceinline__ void gspmv_tiles(const CsrView<T> &A, const Op &op,
             }
         }
         __syncthreads();
+    }
+}
+
+// Ops that set kMarch = true take the plane march (gspmv_march) on grid
+// operators by default; the others only when MRHS_MARCH=2.
+template <class Op, class = void>
+struct march_ok : std::false_type {};
+template <class Op>
+struct march_ok<Op, std::void_t<decltype(Op::kMarch)>> : std::integral_constant<bool, Op::kMarch> {};
+
+// ---- plane march: gathered block rows staged in LDS -------------------------
+// For a grid operator in natural order (forward reach R = a whole number of
+// march tiles, the plane), a row of plane z gathers from its own tile, the
+// tiles next to it in the same plane and the same tile of planes z - 1 and
+// z + 1.  A workgroup of the march owns one tile column t of the planes and a
+// run of consecutive planes; it walks them in order and keeps the gathered
+// block rows of its tile for planes z - 1, z and z + 1 in a ring of three LDS
+// windows, each loaded once (with the op's own gather, so a window holds
+// exactly the values a gather would return, e.g. s = r - alpha v).  Entries
+// whose column falls in a window read LDS; the others (the neighbouring tiles
+// of the same plane) gather through the cache as in gspmv_tiles.  Every row's
+// sum is formed in the same order from the same values, so the products are
+// bitwise those of gspmv_tiles; only the rows' assignment to workgroups (and
+// so the order of the per-workgroup partial dot products) differs.
+//
+// Schedule: group x = b % 8 owns the x-th eighth of the tile columns; its
+// workgroups take units u = (run, column) in turn, the columns of one run of
+// planes first, so the tiles beside a column are walked by the group's other
+// workgroups at about the same time.
+#ifndef MRHS_MARCH_ROWS
+#define MRHS_MARCH_ROWS 64
+#endif
+template <typename T, int M>
+struct MarchShape {
+    using S = Shape<T, M>;
+    static constexpr int PASSES = S::RPP >= MRHS_MARCH_ROWS ? 1 : MRHS_MARCH_ROWS / S::RPP;
+    static constexpr int TR = S::RPP * PASSES;         // rows per march tile
+    static constexpr int LDW = S::G * S::VW;            // LDS row stride of a window (elements)
+    static constexpr int WIN = TR * LDW;                // elements per window
+    static constexpr int NZCAP = TR * MRHS_NZ_PER_ROW;  // staged nonzeros per tile
+};
+
+// The three windows of the ring (planes z - 1, z, z + 1): first row, row
+// count (0 for a plane that does not exist) and element offset in LDS.
+struct MarchWin {
+    int32_t bp, np, op;
+    int32_t bc, nc, oc;
+    int32_t bn, nn, on;
+};
+
+template <typename T, int M, class Op>
+__device__ __forceinline__ void march_load(const CsrView<T> &A, const Op &op, const typename Op::Lane &ln,
+                                           bool lane_on, int g, int rl, int32_t base, int cnt, T *w)
+{
+    using S = Shape<T, M>;
+    using MS = MarchShape<T, M>;
+#pragma unroll
+    for (int p = 0; p < MS::PASSES; ++p) {
+        const int row_l = p * S::RPP + rl;
+        if (lane_on && row_l < cnt) {
+            T x[S::VW];
+            op.gather(ln, base + row_l, g, x);
+            Vec<T, S::VW>::store(w + row_l * MS::LDW + g * S::VW, x);
+        }
+    }
+}
+
+// The same rows loaded into registers (issued early, written to LDS a step
+// later so their latency hides behind the step's own loads).
+template <typename T, int M, class Op>
+__device__ __forceinline__ void march_fetch(const Op &op, const typename Op::Lane &ln, bool lane_on, int g, int rl,
+                                            int32_t base, int cnt, T (&xr)[MarchShape<T, M>::PASSES][Shape<T, M>::VW])
+{
+    using S = Shape<T, M>;
+    using MS = MarchShape<T, M>;
+#pragma unroll
+    for (int p = 0; p < MS::PASSES; ++p) {
+        const int row_l = p * S::RPP + rl;
+        if (lane_on && row_l < cnt)
+            op.gather(ln, base + row_l, g, xr[p]);
+    }
+}
+
+template <typename T, int M>
+__device__ __forceinline__ void march_put(bool lane_on, int g, int rl, int cnt,
+                                          const T (&xr)[MarchShape<T, M>::PASSES][Shape<T, M>::VW], T *w)
+{
+    using S = Shape<T, M>;
+    using MS = MarchShape<T, M>;
+#pragma unroll
+    for (int p = 0; p < MS::PASSES; ++p) {
+        const int row_l = p * S::RPP + rl;
+        if (lane_on && row_l < cnt)
+            Vec<T, S::VW>::store(w + row_l * MS::LDW + g * S::VW, xr[p]);
+    }
+}
+
+// Workgroup barrier that waits for this thread's LDS operations only, so
+// global loads issued before it stay in flight across it.
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// row_product with the windows of the ring: entries in a window read LDS,
+// the others gather; all of a batch's loads are issued before any is used.
+template <typename T, int M, class Op, typename PI, typename PV>
+__device__ __forceinline__ void row_product_march(PI cis, PV vas, int j0, int j1, int g, const Op &op,
+                                                  const typename Op::Lane &ln, const T *s_x, const MarchWin &mw,
+                                                  T *sum)
+{
+    using S = Shape<T, M>;
+    using MS = MarchShape<T, M>;
+    constexpr int NB = MRHS_GATHER_BATCH;
+    for (int j = j0; j < j1; j += NB) {
+        int32_t c[NB];
+        T a[NB], x[NB][S::VW];
+        bool ok[NB];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            ok[k] = j + k < j1;
+            const int jj = ok[k] ? j + k : j1 - 1;
+            c[k] = cis[jj];
+            a[k] = vas[jj];
+        }
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            int off = -1;
+            const int32_t dc = c[k] - mw.bc, dp = c[k] - mw.bp, dn = c[k] - mw.bn;
+            if (static_cast<uint32_t>(dc) < static_cast<uint32_t>(mw.nc))
+                off = mw.oc + dc * MS::LDW;
+            else if (static_cast<uint32_t>(dp) < static_cast<uint32_t>(mw.np))
+                off = mw.op + dp * MS::LDW;
+            else if (static_cast<uint32_t>(dn) < static_cast<uint32_t>(mw.nn))
+                off = mw.on + dn * MS::LDW;
+            if (off >= 0)
+                Vec<T, S::VW>::load(s_x + off + g * S::VW, x[k]);
+            else
+                op.gather(ln, c[k], g, x[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < NB; ++k)
+#pragma unroll
+            for (int v = 0; v < S::VW; ++v)
+                if (ok[k])
+                    sum[v] += a[k] * x[k][v];
+    }
+}
+
+// Rows per plane R = A.reach (a multiple of MS::TR), P = R / MS::TR tile
+// columns, runs of ceil(planes / zc) planes.
+template <typename T, int M, class Op>
+__device__ __forceinline__ void gspmv_march(const CsrView<T> &A, const Op &op,
+                                            Acc<T, Shape<T, M>::VW, Op::NDOT> &acc, int32_t zc)
+{
+    using S = Shape<T, M>;
+    using MS = MarchShape<T, M>;
+    __shared__ int32_t s_rp[MS::TR + 1];
+    __shared__ __align__(16) int32_t s_ci[MS::NZCAP + 4];
+    __shared__ __align__(16) T s_va[MS::NZCAP + 4];
+    __shared__ __align__(16) T s_x[3 * MS::WIN];
+    const int tid = threadIdx.x;
+    const int g = S::lane_of(tid);
+    const int rl = S::row_of(tid);
+    const typename Op::Lane ln = op.lane(g < S::G ? g : 0);
+    const bool lane_on = S::used(tid) && g < S::G && ln.on;
+    const int32_t R = A.reach;
+    const int32_t P = R / MS::TR;
+    const int32_t planes = static_cast<int32_t>((static_cast<int64_t>(A.n) + R - 1) / R);
+    const int32_t zlen = (planes + zc - 1) / zc;
+    const int grp = blockIdx.x % kGroups;
+    const int32_t lo = P * grp / kGroups;
+    const int32_t cg = P * (grp + 1) / kGroups - lo;
+    const int32_t gx = gridDim.x / kGroups;
+    // window of plane z for column t: rows [z R + t TR, + TR) within [0, n)
+    auto win_base = [&](int32_t z, int32_t t) { return static_cast<int64_t>(z) * R + static_cast<int64_t>(t) * MS::TR; };
+    auto win_cnt = [&](int64_t base) {
+        return base < A.n ? static_cast<int32_t>(min(static_cast<int64_t>(MS::TR), A.n - base)) : 0;
+    };
+    for (int32_t u = blockIdx.x / kGroups; u < cg * zc; u += gx) {
+        const int32_t t = lo + u % cg;
+        const int32_t z0 = (u / cg) * zlen;
+        const int32_t z1 = min(planes, z0 + zlen);
+        // ring: planes z0 - 1 (when it exists), z0 and z0 + 1 first; at every
+        // step plane z + 2 is fetched into registers before the rows are
+        // computed and written, after the step, into the slot plane z - 1 held
+        MarchWin mw;
+        mw.op = 0;
+        mw.oc = MS::WIN;
+        mw.on = 2 * MS::WIN;
+        {
+            const int64_t b = win_base(z0 - 1, t);
+            mw.bp = z0 > 0 ? static_cast<int32_t>(min(b, static_cast<int64_t>(A.n))) : 0;
+            mw.np = z0 > 0 ? win_cnt(b) : 0;
+            march_load<T, M>(A, op, ln, lane_on, g, rl, mw.bp, mw.np, s_x + mw.op);
+            const int64_t c = win_base(z0, t);
+            mw.bc = static_cast<int32_t>(min(c, static_cast<int64_t>(A.n)));
+            mw.nc = win_cnt(c);
+            march_load<T, M>(A, op, ln, lane_on, g, rl, mw.bc, mw.nc, s_x + mw.oc);
+            const int64_t d = win_base(z0 + 1, t);
+            mw.bn = static_cast<int32_t>(min(d, static_cast<int64_t>(A.n)));
+            mw.nn = z0 + 1 < planes ? win_cnt(d) : 0;
+            march_load<T, M>(A, op, ln, lane_on, g, rl, mw.bn, mw.nn, s_x + mw.on);
+        }
+        T xr[MS::PASSES][S::VW];
+        int32_t fb = 0, fn = 0;  // rows of the plane held in xr
+        for (int32_t z = z0; z < z1; ++z) {
+            const int64_t rb = win_base(z, t);
+            if (rb >= A.n)
+                break;  // the last, partial plane ends before this column
+            const int32_t r0 = static_cast<int32_t>(rb);
+            const int nr = min(MS::TR, A.n - r0);
+            if (z > z0) {  // plane z + 1, fetched during the previous step
+                mw.bn = fb;
+                mw.nn = fn;
+                march_put<T, M>(lane_on, g, rl, fn, xr, s_x + mw.on);
+            }
+            const Staged st = stage_csr<T, MS::NZCAP>(A, r0, nr, s_rp, s_ci, s_va);
+            {
+                const int64_t b = win_base(z + 2, t);
+                fb = static_cast<int32_t>(min(b, static_cast<int64_t>(A.n)));
+                fn = z + 2 < planes ? win_cnt(b) : 0;
+                march_fetch<T, M>(op, ln, lane_on, g, rl, fb, fn, xr);
+            }
+            lds_barrier();
+            const int32_t *lci = s_ci + st.lead;
+            const T *lva = s_va + st.lead;
+#pragma unroll 1
+            for (int p = 0; p < MS::PASSES; ++p) {
+                const int row_l = p * S::RPP + rl;
+                if (lane_on && row_l < nr) {
+                    const int j0 = s_rp[row_l] - st.z0;
+                    const int j1 = s_rp[row_l + 1] - st.z0;
+                    T sum[S::VW];
+#pragma unroll
+                    for (int v = 0; v < S::VW; ++v)
+                        sum[v] = T(0);
+                    if constexpr (has_pre<Op>::value) {
+                        const typename Op::Pre pr = op.pre(ln, r0 + row_l, g);
+                        if (st.staged)
+                            row_product_march<T, M>(lci, lva, j0, j1, g, op, ln, s_x, mw, sum);
+                        else
+                            row_product_march<T, M>(A.ci + st.z0, A.va + st.z0, j0, j1, g, op, ln, s_x, mw, sum);
+                        op.row(ln, r0 + row_l, g, sum, acc, pr);
+                    } else {
+                        if (st.staged)
+                            row_product_march<T, M>(lci, lva, j0, j1, g, op, ln, s_x, mw, sum);
+                        else
+                            row_product_march<T, M>(A.ci + st.z0, A.va + st.z0, j0, j1, g, op, ln, s_x, mw, sum);
+                        op.row(ln, r0 + row_l, g, sum, acc);
+                    }
+                }
+            }
+            __syncthreads();
+            const int32_t free_slot = mw.op;
+            mw.bp = mw.bc;
+            mw.np = mw.nc;
+            mw.op = mw.oc;
+            mw.bc = mw.bn;
+            mw.nc = mw.nn;
+            mw.oc = mw.on;
+            mw.on = free_slot;
+        }
     }
 }
 

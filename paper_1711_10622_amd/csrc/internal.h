@@ -102,6 +102,28 @@ __global__ void __launch_bounds__(kBlock) k_gspmv(CsrView<T> A, Op op, RedBufs<T
 }
 
 template <typename T, int M, class Op>
+__global__ void __launch_bounds__(kBlock) k_gspmv_march(CsrView<T> A, Op op, RedBufs<T> rb, int32_t runs)
+{
+    Acc<T, Shape<T, M>::VW, Op::NDOT> acc;
+    acc.zero();
+    gspmv_march<T, M>(A, op, acc, runs);
+    if constexpr (Op::NDOT > 0)
+        grid_reduce<T, M, Op::NDOT>(acc, rb, op);
+}
+
+// Plane-march plan of a product over n rows with forward reach `reach` in
+// tiles of tile_rows rows, for a kernel whose grid_for is `grid`: the number
+// of plane runs (>= 1), or 0 when the march does not apply (no whole-tile
+// plane of at least 16 tiles, or fewer than 8 planes).  The runs are chosen
+// so that each group's (run, column) units fill whole rounds of its
+// workgroups, discounted by the extra window each run loads first.
+int32_t march_runs(int32_t n, int32_t reach, int tile_rows, int grid);
+
+// MRHS_MARCH: 0 never march, 1 (default) march the ops that set kMarch,
+// 2 march every product (measurement).
+int march_mode();
+
+template <typename T, int M, class Op>
 __global__ void __launch_bounds__(kBlock) k_gspmv_split(CsrView<T> A, Op op, RedBufs<T> rb)
 {
     Acc<T, Shape<T, M>::VW, Op::NDOT> acc;
@@ -127,7 +149,7 @@ __global__ void __launch_bounds__(kBlock) k_stream(int32_t n, Op op, RedBufs<T> 
 // aggregates the durations per class.  trace_begin returns -1 for launches
 // that are not sampled.
 extern int g_trace_every;
-int trace_begin(hipStream_t s, const char *name, int elem_bytes, int m, int grid);
+int trace_begin(hipStream_t s, const char *name, int elem_bytes, int m, int grid, bool windows = false);
 void trace_end(int slot, hipStream_t s);
 
 template <typename T, int M, class Op>
@@ -139,6 +161,19 @@ inline hipError_t launch_gspmv(const CsrView<T> &A, const Op &op, const RedBufs<
             const int grid = grid_for(fn, A.n, kBlock / 64);
             const int slot = g_trace_every ? trace_begin(s, Op::kName, static_cast<int>(sizeof(T)), M, grid) : -1;
             hipLaunchKernelGGL((k_gspmv_split<T, M, Op>), dim3(grid), dim3(kBlock), 0, s, A, op, rb);
+            if (slot >= 0)
+                trace_end(slot, s);
+            return hipGetLastError();
+        }
+    }
+    if (A.reach > 0 && A.reach % MarchShape<T, M>::TR == 0 && march_mode() >= (march_ok<Op>::value ? 1 : 2)) {
+        const void *fm = reinterpret_cast<const void *>(&k_gspmv_march<T, M, Op>);
+        const int grid = grid_for(fm, A.n, MarchShape<T, M>::TR);
+        const int32_t runs = march_runs(A.n, A.reach, MarchShape<T, M>::TR, grid);
+        if (runs > 0) {
+            const int slot =
+                g_trace_every ? trace_begin(s, Op::kName, static_cast<int>(sizeof(T)), M, grid, true) : -1;
+            hipLaunchKernelGGL((k_gspmv_march<T, M, Op>), dim3(grid), dim3(kBlock), 0, s, A, op, rb, runs);
             if (slot >= 0)
                 trace_end(slot, s);
             return hipGetLastError();

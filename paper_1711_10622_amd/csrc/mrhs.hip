@@ -82,6 +82,34 @@ int grid_for(const void *kernel, int64_t n, int tile_rows)
     return static_cast<int>(g);
 }
 
+int march_mode() { return env_int("MRHS_MARCH", 1, 0, 2); }
+
+int32_t march_runs(int32_t n, int32_t reach, int tile_rows, int grid)
+{
+    if (reach <= 0 || reach % tile_rows != 0)
+        return 0;
+    const int32_t P = reach / tile_rows;
+    const int32_t planes = static_cast<int32_t>((static_cast<int64_t>(n) + reach - 1) / reach);
+    if (P < 2 * kGroups || planes < 8)
+        return 0;
+    const int64_t cg = (P + kGroups - 1) / kGroups;  // columns of the widest group
+    const int64_t gx = std::max(grid / kGroups, 1);
+    int32_t best = 1;
+    double best_score = -1.0;
+    for (int32_t runs = 1; runs <= planes / 8; ++runs) {
+        const int64_t units = cg * runs;
+        const int64_t rounds = (units + gx - 1) / gx;
+        const double fill = static_cast<double>(units) / static_cast<double>(rounds * gx);
+        const int32_t zlen = (planes + runs - 1) / runs;
+        const double score = fill * zlen / (zlen + 1.0);
+        if (score > best_score + 1e-9) {
+            best_score = score;
+            best = runs;
+        }
+    }
+    return best;
+}
+
 // ---- launch tracing ---------------------------------------------------------
 int g_trace_every = 0;
 
@@ -138,11 +166,12 @@ void trace_drain_locked()
 
 } // namespace
 
-int trace_begin(hipStream_t s, const char *name, int elem_bytes, int m, int grid)
+int trace_begin(hipStream_t s, const char *name, int elem_bytes, int m, int grid, bool windows)
 {
     std::lock_guard<std::mutex> lk(g_trace_mu);
     char key[128];
-    std::snprintf(key, sizeof(key), "%s/%s/m%d/g%d", name, elem_bytes == 8 ? "f64" : "f32", m, grid);
+    std::snprintf(key, sizeof(key), "%s/%s/m%d/g%d%s", name, elem_bytes == 8 ? "f64" : "f32", m, grid,
+                  windows ? "w" : "");
     TraceStat &st = trace_stat(key);
     const int64_t seen = st.seen++;
     if (g_trace_every <= 0 || seen % g_trace_every != 0)

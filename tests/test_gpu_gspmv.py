@@ -256,3 +256,100 @@ def test_cube_full_sampled(torch_cuda, mrhs, dtype):
         ref = oracle.gspmv_rows(A32, X, rows)
         tol = gamma(max_row_len(A), U32) * abs_bound(A32, X, rows)
         assert np.all(np.abs(Y[rows] - ref) <= tol)
+
+
+def march_cases():
+    # planes of 64 x 63 = 4032 rows (63 march tiles of 64 rows, 48 of 84, 84 of
+    # 48, 112 of 36 rows): every lane layout's march tile divides the plane;
+    # one with a solid block in three of its planes (rows renumbered past it,
+    # a ragged last plane)
+    yield grids.channel7(64, 63, 10, beta=2.0), "chan64x63x10"
+    solid = np.zeros((10, 63, 64), dtype=bool)
+    solid[2:5, 0:7, 10:30] = True
+    yield grids.channel7(64, 63, 10, beta=2.0, solid=solid), "chan64x63x10_solid"
+
+
+def march_tile(elem, m):
+    """Rows of a march tile: whole passes of the lane layout's rows, at least 64."""
+    if elem == 8:
+        vw = 2 if m % 2 == 0 else 1
+    else:
+        vw = 4 if m % 4 == 0 else (2 if m % 2 == 0 else 1)
+    g = -(-m // vw)
+    p2 = 1
+    while p2 < g:
+        p2 *= 2
+    exact = (vw == 1 or g == 5) and 64 // g > 64 // p2
+    rpp = 4 * (64 // (g if exact else p2))
+    return rpp * (1 if rpp >= 64 else 64 // rpp)
+
+
+def _with_march(mrhs, torch, flag, fn):
+    import os
+    old = os.environ.get("MRHS_MARCH")
+    os.environ["MRHS_MARCH"] = flag
+    try:
+        mrhs.trace_enable(True)
+        out = fn()
+        torch.cuda.synchronize()
+        tr = mrhs.trace_read()
+        mrhs.trace_enable(False)
+    finally:
+        if old is None:
+            del os.environ["MRHS_MARCH"]
+        else:
+            os.environ["MRHS_MARCH"] = old
+    return out, set(tr)
+
+
+@pytest.mark.parametrize("m", list(range(1, 17)))
+def test_plane_march_bitwise_tiled(torch_cuda, mrhs, m):
+    """Products on grid operators may walk planes with the gathered block rows
+    of three planes in LDS (forced here for the plain product with
+    MRHS_MARCH=2); each row's sum must be bitwise that of the tiled product
+    (same order, same values), binary64 and binary32, and within the oracle's
+    bound."""
+    for A, label in march_cases():
+        for dt in (np.float64, np.float32):
+            X = rng.rhs_block(A.n, m, 300 + m)
+            if dt == np.float32:
+                X = round32(X)
+            Ym, km = _with_march(mrhs, torch_cuda, "2", lambda: gpu_gspmv(mrhs, torch_cuda, A, X, dtype=dt))
+            Yt, kt = _with_march(mrhs, torch_cuda, "0", lambda: gpu_gspmv(mrhs, torch_cuda, A, X, dtype=dt))
+            assert np.array_equal(Ym, Yt), (label, m, dt)
+            if dt == np.float64:
+                assert np.all(np.abs(Ym - oracle.gspmv(A, X)) <= 1e-13 * abs_bound(A, X)), (label, m)
+            # where the march tile divides the plane into at least 16 tiles
+            # the march ran: its launches carry another grid size
+            tr = march_tile(np.dtype(dt).itemsize, m)
+            assert (km != kt) == (4032 % tr == 0 and 4032 // tr >= 16), (label, m, dt, tr, km, kt)
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_plane_march_solve(torch_cuda, mrhs, mixed):
+    """A solve whose spmv_omega marches (the default on the 128x64x64 channel,
+    m = 16) and the same solve on tiled products (MRHS_MARCH=0) both reach
+    1e-10 and agree within it."""
+    from helpers import mean_free, true_relres
+    A = configs.MATRICES["chan128"]()
+    B = configs.WORKLOADS["chan128"].rhs(A.n, 16)
+
+    def solve():
+        M = mrhs.CsrMatrix.from_csr(A)
+        X, infos, st = M.solve(torch_cuda.from_numpy(B).cuda(), tol=1e-10, maxit=20000, mixed=mixed)
+        out = X.cpu().numpy(), infos, st
+        M.close()
+        return out
+
+    (Xm, im, sm), km = _with_march(mrhs, torch_cuda, "1", solve)
+    (Xt, it, stt), kt = _with_march(mrhs, torch_cuda, "0", solve)
+    assert sm == 0 and stt == 0, (im, it)
+    assert km != kt
+    for X in (Xm, Xt):
+        assert np.all(true_relres(A, X, B) <= 1e-10)
+    d = np.linalg.norm(mean_free(Xm) - mean_free(Xt), axis=0) / np.linalg.norm(mean_free(Xt), axis=0)
+    assert np.all(d <= 1e-5), d
+    # the order of the partial dot products differs; binary64 counts move
+    # by a few %, the restarted binary32 inner solves' by up to ~20 %
+    for a, b in zip(im, it):
+        assert abs(a["iters"] - b["iters"]) <= (0.3 if mixed else 0.15) * b["iters"], (a, b)
