@@ -327,9 +327,10 @@ def test_plane_march_bitwise_tiled(torch_cuda, mrhs, m):
 
 @pytest.mark.parametrize("mixed", [False, True])
 def test_plane_march_solve(torch_cuda, mrhs, mixed):
-    """A solve whose spmv_omega marches (the default on the 128x64x64 channel,
-    m = 16) and the same solve on tiled products (MRHS_MARCH=0) both reach
-    1e-10 and agree within it."""
+    """A solve whose products march (binary64: spmv_omega, the default on the
+    128x64x64 channel, m = 16; mixed: every product, MRHS_MARCH=2) and the same
+    solve on tiled products (MRHS_MARCH=0) both reach 1e-10 and agree within
+    it."""
     from helpers import mean_free, true_relres
     A = configs.MATRICES["chan128"]()
     B = configs.WORKLOADS["chan128"].rhs(A.n, 16)
@@ -341,7 +342,7 @@ def test_plane_march_solve(torch_cuda, mrhs, mixed):
         M.close()
         return out
 
-    (Xm, im, sm), km = _with_march(mrhs, torch_cuda, "1", solve)
+    (Xm, im, sm), km = _with_march(mrhs, torch_cuda, "2" if mixed else "1", solve)
     (Xt, it, stt), kt = _with_march(mrhs, torch_cuda, "0", solve)
     assert sm == 0 and stt == 0, (im, it)
     assert km != kt
