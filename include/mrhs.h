@@ -230,8 +230,12 @@ mrhs_status block_bicgstab_noalloc(mrhs_csr A, const double *B, double *X, int32
  * thread-safe.
  */
 #define MRHS_SERVER_MIXED 1u /* binary32 inner solves with binary64 refinement */
+#define MRHS_SERVER_AMG 2u   /* BiCGStab with the classical AMG preconditioner
+                                (binary64, as block_bicgstab_amg); every matrix
+                                gets its hierarchy at registration */
 
-/* Create a server.  flags: 0 (binary64 solves) or MRHS_SERVER_MIXED. */
+/* Create a server.  flags: 0 (binary64 Jacobi solves), MRHS_SERVER_MIXED or
+ * MRHS_SERVER_AMG (not both: EINVAL). */
 mrhs_status solve_server_create(size_t hbm_budget_bytes, uint32_t flags,
                                 mrhs_server *out);
 
@@ -240,7 +244,9 @@ mrhs_status solve_server_create(size_t hbm_budget_bytes, uint32_t flags,
  * the server.  EBUDGET unless all registered matrices, A, and the largest
  * engine among them (A's included) fit the budget together, which is what
  * lets every matrix run once the other engines are released; EINVAL for an
- * empty matrix or a zero diagonal entry.
+ * empty matrix or a zero diagonal entry.  With MRHS_SERVER_AMG the matrix's
+ * hierarchy is built here (amg_create defaults), counted as resident bytes
+ * and freed with the server.
  */
 mrhs_status solve_server_register(mrhs_server S, mrhs_csr A, int32_t *matrix_id);
 

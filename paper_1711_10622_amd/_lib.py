@@ -20,6 +20,7 @@ F64, F32 = 0, 1
 CSR_NULLSPACE_CONST, CSR_REORDER = 1, 2
 X0_GIVEN, MIXED = 1, 2
 SERVER_MIXED = 1
+SERVER_AMG = 2
 SHADOW_SEED = 17110622  # MRHS_SHADOW_SEED: seed of the BiCGStab shadow residual
 NOALLOC_SCRATCH_BYTES = 64 << 20  # MRHS_NOALLOC_SCRATCH_BYTES
 

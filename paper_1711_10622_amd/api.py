@@ -305,12 +305,12 @@ class SolveServer:
     """Continuous-batching solve server (``solve_server_*``): host-memory
     right-hand sides in, host-memory solutions out."""
 
-    def __init__(self, hbm_budget_bytes, mixed=False):
+    def __init__(self, hbm_budget_bytes, mixed=False, amg=False):
         lib = _lib.load()
         self._lib = lib
         h = ctypes.c_void_p()
-        _lib.check(lib.solve_server_create(int(hbm_budget_bytes), _lib.SERVER_MIXED if mixed else 0,
-                                           ctypes.byref(h)), "solve_server_create")
+        flags = (_lib.SERVER_MIXED if mixed else 0) | (_lib.SERVER_AMG if amg else 0)
+        _lib.check(lib.solve_server_create(int(hbm_budget_bytes), flags, ctypes.byref(h)), "solve_server_create")
         self._h = h
         self._n = {}
         self._k = {}

@@ -570,6 +570,10 @@ void free_amg(mrhs_amg_s *H)
 }
 
 } // namespace
+
+const AmgDev *amg_dev_of(mrhs_amg H) { return &H->dev; }
+size_t amg_bytes_of(mrhs_amg H) { return H->bytes; }
+
 } // namespace mrhs
 
 using namespace mrhs;

@@ -359,6 +359,10 @@ hipError_t to_user(double *us, const double *sv, const int32_t *perm, int32_t n,
 size_t padded_block_bytes(int32_t n, int w);
 
 size_t solve_workspace_bytes(const mrhs_csr_s &A, int32_t m, uint32_t flags, const AmgDev *amg = nullptr);
+
+// The device view and device bytes of a hierarchy (amg.hip).
+const AmgDev *amg_dev_of(mrhs_amg H);
+size_t amg_bytes_of(mrhs_amg H);
 // host_ctl and amg as for Engine
 mrhs_status block_solve(const mrhs_csr_s &A, const double *B, double *X, const SolveParams &p,
                         void *ws, size_t ws_bytes, hipStream_t s, mrhs_col_info *info, Ctl *host_ctl = nullptr,

@@ -44,26 +44,35 @@ __global__ void k_gather_col(double *__restrict__ v, const double *__restrict__ 
         v[perm ? perm[i] : i] = blk[i * kSlots + c];
 }
 
-size_t engine_bytes(const mrhs_csr_s &A, uint32_t flags)
+size_t engine_bytes(const mrhs_csr_s &A, uint32_t flags, const AmgDev *amg)
 {
     const size_t blk = sizeof(double) * static_cast<size_t>(A.n) * kSlots;
-    return Engine::workspace_bytes(A, kSlots, flags) + 3 * blk;
+    return Engine::workspace_bytes(A, kSlots, flags, amg) + 3 * blk;
 }
 
 // The engine of one lane on the GPU: a stream, the block workspace, device
 // blocks B and X of n x kSlots, a staging block (kSlots contiguous
-// n-vectors) and pinned host columns.
+// n-vectors) and pinned host columns; with an AMG hierarchy (owned by the
+// lane) the engine runs AMG-preconditioned BiCGStab.
 class HipDevice final : public sched::Device {
   public:
-    HipDevice(const mrhs_csr_s &A, uint32_t eflags) : A_(A), eflags_(eflags) {}
-    ~HipDevice() override { release(); }
+    HipDevice(const mrhs_csr_s &A, uint32_t eflags, mrhs_amg H)
+        : A_(A), eflags_(eflags), H_(H), amg_(H ? amg_dev_of(H) : nullptr)
+    {
+    }
+    ~HipDevice() override
+    {
+        release();
+        if (H_)
+            (void)amg_destroy(H_);
+    }
 
     bool acquire() override
     {
         (void)hipSetDevice(A_.device);
         const size_t blk = sizeof(double) * static_cast<size_t>(A_.n) * kSlots;
         if (hipStreamCreateWithFlags(&s_, hipStreamNonBlocking) != hipSuccess ||
-            hipMalloc(&ws_, Engine::workspace_bytes(A_, kSlots, eflags_)) != hipSuccess ||
+            hipMalloc(&ws_, Engine::workspace_bytes(A_, kSlots, eflags_, amg_)) != hipSuccess ||
             hipMalloc(reinterpret_cast<void **>(&B_), blk) != hipSuccess ||
             hipMalloc(reinterpret_cast<void **>(&X_), blk) != hipSuccess ||
             hipMalloc(reinterpret_cast<void **>(&stage_), blk) != hipSuccess ||
@@ -72,7 +81,7 @@ class HipDevice final : public sched::Device {
             release();
             return false;
         }
-        eng_.reset(new Engine(A_, kSlots, eflags_, ws_, B_, X_, s_));
+        eng_.reset(new Engine(A_, kSlots, eflags_, ws_, B_, X_, s_, nullptr, amg_));
         if (eng_->reset() != MRHS_OK) {
             release();
             return false;
@@ -157,6 +166,8 @@ class HipDevice final : public sched::Device {
   private:
     const mrhs_csr_s &A_;
     uint32_t eflags_;
+    mrhs_amg H_ = nullptr;
+    const AmgDev *amg_ = nullptr;
     hipStream_t s_ = nullptr;
     void *ws_ = nullptr;
     double *B_ = nullptr, *X_ = nullptr, *stage_ = nullptr;
@@ -181,8 +192,10 @@ MRHS_API mrhs_status solve_server_create(size_t hbm_budget_bytes, uint32_t flags
     if (!out)
         return set_error(MRHS_EINVAL, "out is NULL");
     *out = nullptr;
-    if (flags & ~MRHS_SERVER_MIXED)
+    if (flags & ~(MRHS_SERVER_MIXED | MRHS_SERVER_AMG))
         return set_error(MRHS_EINVAL, "unknown flags 0x%x", flags);
+    if ((flags & MRHS_SERVER_MIXED) && (flags & MRHS_SERVER_AMG))
+        return set_error(MRHS_EINVAL, "MRHS_SERVER_MIXED and MRHS_SERVER_AMG exclude each other");
     auto *s = new (std::nothrow) mrhs_server_s(hbm_budget_bytes);
     if (!s)
         return set_error(MRHS_ENOMEM, "host allocation failed");
@@ -201,9 +214,19 @@ MRHS_API mrhs_status solve_server_register(mrhs_server srv, mrhs_csr A, int32_t 
     if (A->zero_diag)
         return set_error(MRHS_EINVAL, "the matrix has a zero diagonal entry");
     const uint32_t eflags = (srv->flags & MRHS_SERVER_MIXED) ? MRHS_MIXED : 0u;
+    mrhs_amg H = nullptr;
+    if (srv->flags & MRHS_SERVER_AMG) {
+        const mrhs_status a = amg_create(A, 0.0, 0, 0, &H);
+        if (a != MRHS_OK)
+            return a;  // amg_create set the message
+    }
+    const AmgDev *amg = H ? amg_dev_of(H) : nullptr;
+    const size_t resident = A->bytes + (H ? amg_bytes_of(H) : 0);
+    const size_t eb = engine_bytes(*A, eflags, amg);
     std::string err;
-    const mrhs_status st = srv->impl.add_lane(std::make_unique<HipDevice>(*A, eflags), A->n, A->bytes,
-                                              engine_bytes(*A, eflags), matrix_id, &err);
+    // the lane owns the hierarchy from here (freed with it, or now if it is refused)
+    const mrhs_status st =
+        srv->impl.add_lane(std::make_unique<HipDevice>(*A, eflags, H), A->n, resident, eb, matrix_id, &err);
     return st == MRHS_OK ? st : set_error(st, "%s", err.c_str());
 }
 

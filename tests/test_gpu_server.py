@@ -195,3 +195,45 @@ def test_budget_turns_no_starvation(mrhs, mats):
             done.append(srv.wait(t, timeout=120))
     assert len(done) == 60 and all(st == 0 for _, _, st in done)
     srv.close()
+
+
+def test_amg_server(mrhs, mats):
+    """MRHS_SERVER_AMG: every request is solved by AMG-preconditioned block
+    BiCGStab (a hierarchy per registered matrix); each result meets the
+    tolerance in few iterations, equals bitwise the same request served
+    alone, and agrees with block_bicgstab_amg on the matrix."""
+    import torch
+    As, Ms = mats
+    A = As["chan"]
+    R = rhs_for(A, 3, 4343)
+    srv = mrhs.SolveServer(4 * GiB, amg=True)
+    mid = srv.register(Ms["chan"])
+    X_alone, inf_alone, st = srv.wait(srv.submit(mid, R, tol=1e-10))
+    srv.close()
+    assert st == 0, inf_alone
+    assert np.all(true_relres(A, X_alone, R) <= 1e-10)
+    assert max(i["iters"] for i in inf_alone) <= 40, inf_alone
+    H = mrhs.AmgHierarchy(Ms["chan"])
+    Xh, ih, sh = H.solve(torch.from_numpy(R).cuda(), tol=1e-10, maxit=20000)
+    H.close()
+    assert sh == 0
+    Xh = Xh.cpu().numpy()
+    assert np.linalg.norm(X_alone - Xh) <= 1e-6 * np.linalg.norm(Xh)
+    srv = mrhs.SolveServer(4 * GiB, amg=True)
+    ids = {k: srv.register(M) for k, M in Ms.items()}
+    r = np.random.default_rng(8)
+    sent = []
+    for i in range(9):
+        name = ["dir12", "dir20", "chan"][i % 3]
+        B = rhs_for(As[name], int(r.integers(1, 9)), 700 + i)
+        sent.append((name, B, srv.submit(ids[name], B, tol=1e-10)))
+    tR = srv.submit(ids["chan"], R, tol=1e-10)
+    X_mix, inf_mix, st = srv.wait(tR)
+    assert st == 0
+    for name, B, t in sent:
+        X, infs, st = srv.wait(t)
+        assert st == 0, infs
+        assert np.all(true_relres(As[name], X, B) <= 1e-10)
+        assert max(i["iters"] for i in infs) <= 40, infs
+    srv.close()
+    assert np.array_equal(X_mix, X_alone)
