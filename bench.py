@@ -299,7 +299,7 @@ def serving(torch, n_req=300, seed=1714, mean_gap_s=0.005, budget=16 << 30, rate
     32^3 / 64^3 Dirichlet operators and the 128x64x64 channel with
     probability 1/3 and k ~ U{1..16} right-hand sides, solved to 1e-10 by
     mixed-precision Jacobi-BiCGStab (or, with ``amg``, AMG-preconditioned
-    binary64 BiCGStab); HBM budget ``budget``.  Open loop: requests arrive
+    BiCGStab with the V-cycle in binary32); HBM budget ``budget``.  Open loop: requests arrive
     with exponential gaps of mean ``mean_gap_s`` (or scaled to ``rate``
     right-hand sides per second).  ``closed``: every request is submitted at
     once and the run measures the server's capacity.  Request blocks are
@@ -310,7 +310,7 @@ def serving(torch, n_req=300, seed=1714, mean_gap_s=0.005, budget=16 << 30, rate
     from workloads import configs, rng
     names = ["dir32", "dir64", "chan128"]
     mats, pools, ids = [], [], []
-    srv = mrhs.SolveServer(budget, mixed=not amg, amg=amg)
+    srv = mrhs.SolveServer(budget, mixed=True, amg=amg)
     for nm in names:
         wl = configs.WORKLOADS[nm]
         A = wl.matrix()
@@ -368,7 +368,7 @@ def serving(torch, n_req=300, seed=1714, mean_gap_s=0.005, budget=16 << 30, rate
     srv.close()
     for M in mats:
         M.close()
-    out = {"solver": "amg" if amg else "mixed", "mode": "closed" if closed else "open", "requests": n_req,
+    out = {"solver": "amg_vc32" if amg else "mixed", "mode": "closed" if closed else "open", "requests": n_req,
            "rhs": rhs, "served_rhs_per_s": round(rhs / wall, 1), "wall_s": round(wall, 3),
            "p50_ms": round(st["p50_ms"], 2), "p99_ms": round(st["p99_ms"], 2),
            "server_rhs_per_s": round(st["rhs_per_s"], 1), "max_outstanding": max_q, "not_ok": bad}
@@ -698,6 +698,18 @@ def amg_legs(torch, A, Bh, m, t_jacobi, per_iter_ms=(1, 2, 4, 8, 16), steps=1, r
                 "top_kernels": {k: {"launches": v["seen"], "avg_us": round(v["total_ms"] / v["launches"] * 1e3, 1)}
                                 for k, v in sorted(tr.items(), key=lambda kv: -kv[1]["total_ms"] / kv[1]["launches"]
                                                    * kv[1]["seen"])[:8]}})
+    # the V-cycle in binary32 (the iteration, its products and x in binary64)
+    H.solve(B, out=X, workspace=ws, mixed=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, infos32, st32 = H.solve(B, out=X, workspace=ws, mixed=True)
+    torch.cuda.synchronize()
+    t32 = (time.perf_counter() - t0) / steps
+    assert st32 == 0, infos32
+    out["vcycle_f32"] = {"s_per_rhs": round(t32 / m, 6), "speedup_vs_f64_vcycle": round(t / t32, 3),
+                         "speedup_vs_jacobi": round(t_jacobi / t32, 3), "iters": [i["iters"] for i in infos32],
+                         "max_relres": max(i["relres"] for i in infos32)}
     del X, B, ws
     per = {}
     for mm in per_iter_ms:
@@ -882,6 +894,7 @@ def main():
         srv_legs = {"offered_5ms_gaps": serving(torch, n_req=300)}
         for amg in (False, True):
             tag = "amg" if amg else "mixed"
+            # mixed: binary32 inner Jacobi solves; amg: the V-cycle in binary32
             cap = serving(torch, n_req=150, seed=1716, amg=amg, closed=True)
             srv_legs[f"{tag}_capacity"] = cap
             srv_legs[f"{tag}_at_0.8x_capacity"] = serving(torch, n_req=300, amg=amg,

@@ -231,11 +231,12 @@ mrhs_status block_bicgstab_noalloc(mrhs_csr A, const double *B, double *X, int32
  */
 #define MRHS_SERVER_MIXED 1u /* binary32 inner solves with binary64 refinement */
 #define MRHS_SERVER_AMG 2u   /* BiCGStab with the classical AMG preconditioner
-                                (binary64, as block_bicgstab_amg); every matrix
-                                gets its hierarchy at registration */
+                                (as block_bicgstab_amg); every matrix gets its
+                                hierarchy at registration; with
+                                MRHS_SERVER_MIXED the V-cycle runs in binary32 */
 
-/* Create a server.  flags: 0 (binary64 Jacobi solves), MRHS_SERVER_MIXED or
- * MRHS_SERVER_AMG (not both: EINVAL). */
+/* Create a server.  flags: 0 (binary64 Jacobi solves), MRHS_SERVER_MIXED,
+ * MRHS_SERVER_AMG or both. */
 mrhs_status solve_server_create(size_t hbm_budget_bytes, uint32_t flags,
                                 mrhs_server *out);
 
@@ -397,7 +398,11 @@ mrhs_status block_bicgstab_amg_workspace_size(mrhs_amg H, int32_t m, size_t *byt
  * preconditioner instead of Jacobi (binary64): per column p^ = M^-1 p,
  * v = A p^, s = r - alpha v, s^ = M^-1 s, t = A s^, x += alpha p^ + omega s^,
  * with the same stopping tests, true-residual checks, restarts, shadow
- * residual and per-column outcomes.  flags: MRHS_X0_GIVEN.  workspace NULL:
+ * residual and per-column outcomes.  flags: MRHS_X0_GIVEN, and MRHS_MIXED to
+ * run the V-cycle in binary32 on binary32 roundings (nearest even) of every
+ * level's values, made on the first such call and kept with the hierarchy:
+ * p and s are rounded in and M^-1 p, M^-1 s widened out, while the
+ * iteration, its products with A and x stay binary64.  workspace NULL:
  * allocated and freed by the call.
  */
 mrhs_status block_bicgstab_amg(mrhs_amg H, const double *B, double *X, int32_t m,

@@ -216,13 +216,14 @@ class AmgHierarchy:
         _lib.check(self._lib.block_bicgstab_amg_workspace_size(self._h, int(m), ctypes.byref(b)))
         return int(b.value)
 
-    def solve(self, B, tol=1e-10, maxit=1000, X0=None, out=None, workspace=None, stream=None):
+    def solve(self, B, tol=1e-10, maxit=1000, X0=None, out=None, workspace=None, stream=None, mixed=False):
         """AMG-preconditioned block BiCGStab (``block_bicgstab_amg``); returns
-        ``(X, infos, status)`` like :meth:`CsrMatrix.solve`."""
+        ``(X, infos, status)`` like :meth:`CsrMatrix.solve`.  ``mixed``: the
+        V-cycle in binary32."""
         torch = _torch()
         m = 1 if B.dim() == 1 else int(B.shape[1])
         Bb = _check_block(B, self.M.n, m, torch.float64, "B")
-        flags = 0
+        flags = _lib.MIXED if mixed else 0
         if X0 is not None:
             X0b = _check_block(X0, self.M.n, m, torch.float64, "X0")
             out = X0b.clone() if out is None else out.copy_(X0b)

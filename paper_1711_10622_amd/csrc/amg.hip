@@ -36,10 +36,10 @@ namespace mrhs {
 namespace {
 
 // Lanes on in a V-cycle product: every column (ctl null) or the running ones.
-template <int M>
+template <typename T, int M>
 __device__ __forceinline__ bool lane_running(const Ctl *ctl, int g)
 {
-    using S = Shape<double, M>;
+    using S = Shape<T, M>;
     if (!ctl)
         return true;
     bool on = false;
@@ -55,131 +55,182 @@ struct VcLane {
     bool on;
 };
 
+// The V-cycle runs in binary64, or in binary32 on binary32 roundings of
+// every level's values (MRHS_MIXED with block_bicgstab_amg): the same ops
+// over T.
+
 // Y = sum (restriction, coarsest dense inverse)
-template <int M>
+template <typename T, int M>
 struct OpVcStore {
     static constexpr const char *kName = "vc_store";
     static constexpr bool kLongRows = true;
-    using S = Shape<double, M>;
+    using S = Shape<T, M>;
     static constexpr int NDOT = 0;
-    const double *X;
-    double *Y;
+    const T *X;
+    T *Y;
     const Ctl *ctl;
     using Lane = VcLane;
-    __device__ Lane lane(int g) const { return {lane_running<M>(ctl, g)}; }
-    __device__ __forceinline__ void gather(const Lane &, int32_t c, int g, double *x) const { ld<double, M>(X, c, g, x); }
-    __device__ __forceinline__ void row(const Lane &, int32_t i, int g, const double *sum,
-                                        Acc<double, S::VW, NDOT> &) const
+    __device__ Lane lane(int g) const { return {lane_running<T, M>(ctl, g)}; }
+    __device__ __forceinline__ void gather(const Lane &, int32_t c, int g, T *x) const { ld<T, M>(X, c, g, x); }
+    __device__ __forceinline__ void row(const Lane &, int32_t i, int g, const T *sum, Acc<T, S::VW, NDOT> &) const
     {
-        st<double, M>(Y, i, g, sum);
+        st<T, M>(Y, i, g, sum);
     }
-    __device__ void finish(const double *) const {}
+    __device__ void finish(const T *) const {}
 };
 
 // Y = U - sum (residual; with A D^-1 and X = U the residual after the first
 // sweep from zero)
-template <int M>
+template <typename T, int M>
 struct OpVcRes {
     static constexpr const char *kName = "vc_resid";
     static constexpr bool kLongRows = true;
-    using S = Shape<double, M>;
+    using S = Shape<T, M>;
     static constexpr int NDOT = 0;
-    const double *X, *U;
-    double *Y;
+    const T *X, *U;
+    T *Y;
     const Ctl *ctl;
     using Lane = VcLane;
-    __device__ Lane lane(int g) const { return {lane_running<M>(ctl, g)}; }
-    __device__ __forceinline__ void gather(const Lane &, int32_t c, int g, double *x) const { ld<double, M>(X, c, g, x); }
+    __device__ Lane lane(int g) const { return {lane_running<T, M>(ctl, g)}; }
+    __device__ __forceinline__ void gather(const Lane &, int32_t c, int g, T *x) const { ld<T, M>(X, c, g, x); }
     struct Pre {
-        double u[S::VW];
+        T u[S::VW];
     };
     __device__ __forceinline__ Pre pre(const Lane &, int32_t i, int g) const
     {
         Pre pr;
-        ld<double, M>(U, i, g, pr.u);
+        ld<T, M>(U, i, g, pr.u);
         return pr;
     }
-    __device__ __forceinline__ void row(const Lane &, int32_t i, int g, const double *sum,
-                                        Acc<double, S::VW, NDOT> &, const Pre &pr) const
+    __device__ __forceinline__ void row(const Lane &, int32_t i, int g, const T *sum, Acc<T, S::VW, NDOT> &,
+                                        const Pre &pr) const
     {
-        double u[S::VW];
+        T u[S::VW];
 #pragma unroll
         for (int q = 0; q < S::VW; ++q)
             u[q] = pr.u[q] - sum[q];
-        st<double, M>(Y, i, g, u);
+        st<T, M>(Y, i, g, u);
     }
-    __device__ void finish(const double *) const {}
+    __device__ void finish(const T *) const {}
 };
 
 // Y = dinv_i U_i + sum (the first sweep's x plus the prolongated correction)
-template <int M>
+template <typename T, int M>
 struct OpVcProl {
     static constexpr const char *kName = "vc_prolong";
     static constexpr bool kLongRows = true;
-    using S = Shape<double, M>;
+    using S = Shape<T, M>;
     static constexpr int NDOT = 0;
-    const double *X, *U, *dinv;
-    double *Y;
+    const T *X, *U, *dinv;
+    T *Y;
     const Ctl *ctl;
     using Lane = VcLane;
-    __device__ Lane lane(int g) const { return {lane_running<M>(ctl, g)}; }
-    __device__ __forceinline__ void gather(const Lane &, int32_t c, int g, double *x) const { ld<double, M>(X, c, g, x); }
+    __device__ Lane lane(int g) const { return {lane_running<T, M>(ctl, g)}; }
+    __device__ __forceinline__ void gather(const Lane &, int32_t c, int g, T *x) const { ld<T, M>(X, c, g, x); }
     struct Pre {
-        double u[S::VW];
-        double d;
+        T u[S::VW];
+        T d;
     };
     __device__ __forceinline__ Pre pre(const Lane &, int32_t i, int g) const
     {
         Pre pr;
-        ld<double, M>(U, i, g, pr.u);
+        ld<T, M>(U, i, g, pr.u);
         pr.d = dinv[i];
         return pr;
     }
-    __device__ __forceinline__ void row(const Lane &, int32_t i, int g, const double *sum,
-                                        Acc<double, S::VW, NDOT> &, const Pre &pr) const
+    __device__ __forceinline__ void row(const Lane &, int32_t i, int g, const T *sum, Acc<T, S::VW, NDOT> &,
+                                        const Pre &pr) const
     {
-        double u[S::VW];
+        T u[S::VW];
 #pragma unroll
         for (int q = 0; q < S::VW; ++q)
             u[q] = pr.d * pr.u[q] + sum[q];
-        st<double, M>(Y, i, g, u);
+        st<T, M>(Y, i, g, u);
+    }
+    __device__ void finish(const T *) const {}
+};
+
+// Y = T_i + dinv_i (U_i - sum), sum = (A T)_i (post-smoothing sweep)
+template <typename T, int M>
+struct OpVcSmooth {
+    static constexpr const char *kName = "vc_smooth";
+    static constexpr bool kLongRows = true;
+    using S = Shape<T, M>;
+    static constexpr int NDOT = 0;
+    const T *Tv, *U, *dinv;
+    T *Y;
+    const Ctl *ctl;
+    using Lane = VcLane;
+    __device__ Lane lane(int g) const { return {lane_running<T, M>(ctl, g)}; }
+    __device__ __forceinline__ void gather(const Lane &, int32_t c, int g, T *x) const { ld<T, M>(Tv, c, g, x); }
+    struct Pre {
+        T t[S::VW], u[S::VW];
+        T d;
+    };
+    __device__ __forceinline__ Pre pre(const Lane &, int32_t i, int g) const
+    {
+        Pre pr;
+        ld<T, M>(Tv, i, g, pr.t);
+        ld<T, M>(U, i, g, pr.u);
+        pr.d = dinv[i];
+        return pr;
+    }
+    __device__ __forceinline__ void row(const Lane &, int32_t i, int g, const T *sum, Acc<T, S::VW, NDOT> &,
+                                        const Pre &pr) const
+    {
+        T t[S::VW];
+#pragma unroll
+        for (int q = 0; q < S::VW; ++q)
+            t[q] = pr.t[q] + pr.d * (pr.u[q] - sum[q]);
+        st<T, M>(Y, i, g, t);
+    }
+    __device__ void finish(const T *) const {}
+};
+
+// Block conversions at the binary32 V-cycle's boundary, in the binary64 lane
+// layout: dst = RN32(src) into a binary32 block, and back.
+template <int M>
+struct OpTo32 {
+    static constexpr const char *kName = "amg_to32";
+    using S = Shape<double, M>;
+    static constexpr int NDOT = 0;
+    const double *src;
+    float *dst;
+    const Ctl *ctl;
+    using Lane = VcLane;
+    __device__ Lane lane(int g) const { return {lane_running<double, M>(ctl, g)}; }
+    __device__ __forceinline__ void row(const Lane &, int32_t i, int g, Acc<double, S::VW, NDOT> &) const
+    {
+        double v[S::VW];
+        float f[S::VW];
+        ld<double, M>(src, i, g, v);
+#pragma unroll
+        for (int q = 0; q < S::VW; ++q)
+            f[q] = static_cast<float>(v[q]);
+        Vec<float, S::VW>::store(dst + static_cast<size_t>(i) * M + g * S::VW, f);
     }
     __device__ void finish(const double *) const {}
 };
 
-// Y = T_i + dinv_i (U_i - sum), sum = (A T)_i (post-smoothing sweep)
 template <int M>
-struct OpVcSmooth {
-    static constexpr const char *kName = "vc_smooth";
-    static constexpr bool kLongRows = true;
+struct OpTo64 {
+    static constexpr const char *kName = "amg_to64";
     using S = Shape<double, M>;
     static constexpr int NDOT = 0;
-    const double *T, *U, *dinv;
-    double *Y;
+    const float *src;
+    double *dst;
     const Ctl *ctl;
     using Lane = VcLane;
-    __device__ Lane lane(int g) const { return {lane_running<M>(ctl, g)}; }
-    __device__ __forceinline__ void gather(const Lane &, int32_t c, int g, double *x) const { ld<double, M>(T, c, g, x); }
-    struct Pre {
-        double t[S::VW], u[S::VW];
-        double d;
-    };
-    __device__ __forceinline__ Pre pre(const Lane &, int32_t i, int g) const
+    __device__ Lane lane(int g) const { return {lane_running<double, M>(ctl, g)}; }
+    __device__ __forceinline__ void row(const Lane &, int32_t i, int g, Acc<double, S::VW, NDOT> &) const
     {
-        Pre pr;
-        ld<double, M>(T, i, g, pr.t);
-        ld<double, M>(U, i, g, pr.u);
-        pr.d = dinv[i];
-        return pr;
-    }
-    __device__ __forceinline__ void row(const Lane &, int32_t i, int g, const double *sum,
-                                        Acc<double, S::VW, NDOT> &, const Pre &pr) const
-    {
-        double t[S::VW];
+        float f[S::VW];
+        double v[S::VW];
+        Vec<float, S::VW>::load(src + static_cast<size_t>(i) * M + g * S::VW, f);
 #pragma unroll
         for (int q = 0; q < S::VW; ++q)
-            t[q] = pr.t[q] + pr.d * (pr.u[q] - sum[q]);
-        st<double, M>(Y, i, g, t);
+            v[q] = static_cast<double>(f[q]);
+        st<double, M>(dst, i, g, v);
     }
     __device__ void finish(const double *) const {}
 };
@@ -305,30 +356,34 @@ struct OpXRP : OpXR<double, M> {
 };
 
 // ---- V-cycle buffers: for every level but the coarsest r_l and t_l, for
-// every level but the finest b_l and x_l, each n_l x m binary64
+// every level but the finest b_l and x_l, each n_l x m of T; a binary32
+// V-cycle also holds its finest level's b and x (the binary64 blocks
+// rounded in, and the result before it is widened out).
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+template <typename T>
 struct VcBufs {
-    double *r[kAmgMaxLevels], *t[kAmgMaxLevels], *b[kAmgMaxLevels], *x[kAmgMaxLevels];
+    T *r[kAmgMaxLevels], *t[kAmgMaxLevels], *b[kAmgMaxLevels], *x[kAmgMaxLevels];
 };
 
-size_t vc_layout(const AmgDev &H, int32_t m, char *base, VcBufs *out)
+template <typename T>
+size_t vc_layout(const AmgDev &H, int32_t m, char *base, VcBufs<T> *out)
 {
     size_t off = 0;
     auto take = [&](int32_t n) {
-        double *p = base ? reinterpret_cast<double *>(base + off) : nullptr;
-        off = align_up(off + sizeof(double) * static_cast<size_t>(n) * m);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off = align_up(off + sizeof(T) * static_cast<size_t>(n) * m);
         return p;
     };
-    VcBufs v{};
+    VcBufs<T> v{};
     for (int l = 0; l < H.nlev; ++l) {
         const int32_t n = H.lev[l].n;
         if (l + 1 < H.nlev) {
             v.r[l] = take(n);
             v.t[l] = take(n);
         }
-        if (l > 0) {
+        if (l > 0 || !std::is_same<T, double>::value) {
             v.b[l] = take(n);
             v.x[l] = take(n);
         }
@@ -338,35 +393,81 @@ size_t vc_layout(const AmgDev &H, int32_t m, char *base, VcBufs *out)
     return off;
 }
 
-template <int M>
-hipError_t vcycle(const AmgDev &H, const double *b, double *x, char *ws, const Ctl *ctl, hipStream_t s)
+// The level arrays of the V-cycle's precision.
+template <typename T>
+struct VcViews;
+template <>
+struct VcViews<double> {
+    static const CsrView<double> &A(const AmgLevelDev &l) { return l.A; }
+    static const CsrView<double> &Ah(const AmgLevelDev &l) { return l.Ah; }
+    static const CsrView<double> &P(const AmgLevelDev &l) { return l.P; }
+    static const CsrView<double> &R(const AmgLevelDev &l) { return l.R; }
+    static const double *dinv(const AmgLevelDev &l) { return l.dl1_inv; }
+    static const CsrView<double> &cinv(const AmgDev &H) { return H.cinv; }
+};
+template <>
+struct VcViews<float> {
+    static const CsrView<float> &A(const AmgLevelDev &l) { return l.A32; }
+    static const CsrView<float> &Ah(const AmgLevelDev &l) { return l.Ah32; }
+    static const CsrView<float> &P(const AmgLevelDev &l) { return l.P32; }
+    static const CsrView<float> &R(const AmgLevelDev &l) { return l.R32; }
+    static const float *dinv(const AmgLevelDev &l) { return l.dl1_inv32; }
+    static const CsrView<float> &cinv(const AmgDev &H) { return H.cinv32; }
+};
+
+// x = V-cycle(b) on blocks of T; b and x are the finest level's blocks
+template <typename T, int M>
+hipError_t vcycle(const AmgDev &H, const T *b, T *x, const VcBufs<T> &vb, const Ctl *ctl, hipStream_t s)
 {
-    VcBufs v;
-    vc_layout(H, M, ws, &v);
-    const RedBufs<double> none{nullptr, nullptr, nullptr};
+    using V = VcViews<T>;
+    VcBufs<T> v = vb;
+    const RedBufs<T> none{nullptr, nullptr, nullptr};
     const int L = H.nlev;
-    v.b[0] = const_cast<double *>(b);
+    v.b[0] = const_cast<T *>(b);
     v.x[0] = x;
     hipError_t e;
     for (int l = 0; l + 1 < L; ++l) {
         const AmgLevelDev &lv = H.lev[l];
-        if ((e = launch_gspmv<double, M>(lv.Ah, OpVcRes<M>{v.b[l], v.b[l], v.r[l], ctl}, none, s)) != hipSuccess)
+        if ((e = launch_gspmv<T, M>(V::Ah(lv), OpVcRes<T, M>{v.b[l], v.b[l], v.r[l], ctl}, none, s)) != hipSuccess)
             return e;
-        if ((e = launch_gspmv<double, M>(lv.R, OpVcStore<M>{v.r[l], v.b[l + 1], ctl}, none, s)) != hipSuccess)
+        if ((e = launch_gspmv<T, M>(V::R(lv), OpVcStore<T, M>{v.r[l], v.b[l + 1], ctl}, none, s)) != hipSuccess)
             return e;
     }
-    if ((e = launch_gspmv<double, M>(H.cinv, OpVcStore<M>{v.b[L - 1], v.x[L - 1], ctl}, none, s)) != hipSuccess)
+    if ((e = launch_gspmv<T, M>(V::cinv(H), OpVcStore<T, M>{v.b[L - 1], v.x[L - 1], ctl}, none, s)) != hipSuccess)
         return e;
     for (int l = L - 2; l >= 0; --l) {
         const AmgLevelDev &lv = H.lev[l];
-        if ((e = launch_gspmv<double, M>(lv.P, OpVcProl<M>{v.x[l + 1], v.b[l], lv.dl1_inv, v.t[l], ctl}, none, s)) !=
-            hipSuccess)
+        if ((e = launch_gspmv<T, M>(V::P(lv), OpVcProl<T, M>{v.x[l + 1], v.b[l], V::dinv(lv), v.t[l], ctl}, none,
+                                    s)) != hipSuccess)
             return e;
-        if ((e = launch_gspmv<double, M>(lv.A, OpVcSmooth<M>{v.t[l], v.b[l], lv.dl1_inv, v.x[l], ctl}, none, s)) !=
-            hipSuccess)
+        if ((e = launch_gspmv<T, M>(V::A(lv), OpVcSmooth<T, M>{v.t[l], v.b[l], V::dinv(lv), v.x[l], ctl}, none,
+                                    s)) != hipSuccess)
             return e;
     }
     return hipSuccess;
+}
+
+// x = M^-1 b for binary64 blocks, the V-cycle in binary64 or (vc32) in
+// binary32 between a rounding of b and a widening of its result
+template <int M>
+hipError_t precondition(const AmgDev &H, const double *b, double *x, char *ws, bool vc32, const Ctl *ctl,
+                        hipStream_t s)
+{
+    if (!vc32) {
+        VcBufs<double> v;
+        vc_layout<double>(H, M, ws, &v);
+        return vcycle<double, M>(H, b, x, v, ctl, s);
+    }
+    VcBufs<float> v;
+    vc_layout<float>(H, M, ws, &v);
+    const RedBufs<double> none{nullptr, nullptr, nullptr};
+    const int32_t n = H.lev[0].n;
+    hipError_t e;
+    if ((e = launch_stream<double, M>(n, OpTo32<M>{b, v.b[0], ctl}, none, s)) != hipSuccess)
+        return e;
+    if ((e = vcycle<float, M>(H, v.b[0], v.x[0], v, ctl, s)) != hipSuccess)
+        return e;
+    return launch_stream<double, M>(n, OpTo64<M>{v.x[0], x, ctl}, none, s);
 }
 
 #define AMG_TRY(expr)           \
@@ -390,11 +491,11 @@ struct AmgSteps {
     static hipError_t iterate(Ctx &c, int k)
     {
         for (int it = 0; it < k; ++it) {
-            AMG_TRY(vcycle<M>(*c.amg, c.p, c.ph, c.vcws, c.ctl, c.s));
+            AMG_TRY(precondition<M>(*c.amg, c.p, c.ph, c.vcws, c.vc32, c.ctl, c.s));
             AMG_TRY((launch_gspmv<double, M>(A(c), OpSpmv1<double, M>{c.ph, c.v, nullptr, c.ctl, c.kry64, c.ldp64},
                                               c.rb64, c.s)));
             AMG_TRY((launch_stream<double, M>(c.n, OpSForm<M>{c.r, c.v, c.sv, c.ctl, c.kry64, c.ldp64}, c.rb64, c.s)));
-            AMG_TRY(vcycle<M>(*c.amg, c.sv, c.sh, c.vcws, c.ctl, c.s));
+            AMG_TRY(precondition<M>(*c.amg, c.sv, c.sh, c.vcws, c.vc32, c.ctl, c.s));
             OpSpmv2P<M> om{};
             om.r = c.r;
             om.v = c.v;
@@ -460,7 +561,7 @@ struct VcLaunch {
     template <int M>
     hipError_t operator()() const
     {
-        return vcycle<M>(*H, b, x, ws, nullptr, s);
+        return precondition<M>(*H, b, x, ws, false, nullptr, s);
     }
 };
 
@@ -480,7 +581,10 @@ const AmgStepTable &amg_table(int m)
     return tables[m];
 }
 
-size_t amg_vcycle_bytes(const AmgDev &H, int32_t m) { return vc_layout(H, m, nullptr, nullptr); }
+size_t amg_vcycle_bytes(const AmgDev &H, int32_t m)
+{
+    return std::max(vc_layout<double>(H, m, nullptr, nullptr), vc_layout<float>(H, m, nullptr, nullptr));
+}
 
 } // namespace mrhs
 
@@ -569,10 +673,73 @@ void free_amg(mrhs_amg_s *H)
     delete H;
 }
 
+__global__ void k_round32(const double *__restrict__ src, float *__restrict__ dst, int64_t count)
+{
+    for (int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < count;
+         k += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        dst[k] = static_cast<float>(src[k]);
+}
+
+// binary32 rounding (nearest even) of count device values, padding included
+float *round32(mrhs_amg_s *H, const double *src, int64_t count, hipError_t *err)
+{
+    void *p = nullptr;
+    if (*err != hipSuccess)
+        return nullptr;
+    const size_t bytes = sizeof(float) * static_cast<size_t>(std::max<int64_t>(count, 1));
+    if ((*err = hipMalloc(&p, bytes)) != hipSuccess)
+        return nullptr;
+    H->allocs.push_back(p);
+    H->bytes += bytes;
+    if (count > 0) {
+        const int64_t blocks = std::min<int64_t>((count + 255) / 256, 65536);
+        hipLaunchKernelGGL(k_round32, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, nullptr, src,
+                           static_cast<float *>(p), count);
+        *err = hipGetLastError();
+    }
+    return static_cast<float *>(p);
+}
+
+CsrView<float> view32(mrhs_amg_s *H, const CsrView<double> &v, int64_t nnz, hipError_t *err)
+{
+    return {v.rp, v.ci, round32(H, v.va, nnz + static_cast<int64_t>(kPadElems), err), v.n, v.reach, v.split};
+}
+
 } // namespace
 
 const AmgDev *amg_dev_of(mrhs_amg H) { return &H->dev; }
 size_t amg_bytes_of(mrhs_amg H) { return H->bytes; }
+
+mrhs_status amg_make32(mrhs_amg H)
+{
+    if (H->dev.has32)
+        return MRHS_OK;
+    (void)hipSetDevice(H->device);
+    hipError_t e = hipSuccess;
+    AmgDev &D = H->dev;
+    const int L = D.nlev;
+    for (int l = 0; l < L && e == hipSuccess; ++l) {
+        AmgLevelDev &d = D.lev[l];
+        d.A32 = view32(H, d.A, d.nnz_a, &e);
+        d.dl1_inv32 = round32(H, d.dl1_inv, d.n, &e);
+        if (l + 1 < L) {
+            d.Ah32 = view32(H, d.Ah, d.nnz_a, &e);
+            d.P32 = view32(H, d.P, d.nnz_p, &e);
+            d.R32 = view32(H, d.R, d.nnz_p, &e);
+        }
+    }
+    const int64_t nc = D.lev[L - 1].n;
+    D.cinv32 = view32(H, D.cinv, nc * nc, &e);
+    if (e == hipSuccess)
+        e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(e == hipErrorOutOfMemory ? MRHS_ENOMEM : MRHS_EDEVICE, "binary32 hierarchy failed: %s",
+                         hipGetErrorString(e));
+    }
+    D.has32 = true;
+    return MRHS_OK;
+}
 
 } // namespace mrhs
 
@@ -825,7 +992,7 @@ MRHS_API mrhs_status block_bicgstab_amg(mrhs_amg H, const double *B, double *X, 
         return set_error(MRHS_EINVAL, "tol must be positive and finite");
     if (maxit < 1)
         return set_error(MRHS_EINVAL, "maxit must be at least 1");
-    if (flags & ~MRHS_X0_GIVEN)
+    if (flags & ~(MRHS_X0_GIVEN | MRHS_MIXED))
         return set_error(MRHS_EINVAL, "unknown flags 0x%x", flags);
     if (!B || !X)
         return set_error(MRHS_EINVAL, "B or X is NULL");
@@ -850,8 +1017,12 @@ MRHS_API mrhs_status block_bicgstab_amg(mrhs_amg H, const double *B, double *X, 
         own = true;
         ws_bytes = need;
     }
-    const mrhs_status st =
-        block_solve(A, B, X, SolveParams{m, tol, maxit, flags}, ws, ws_bytes, s, info, nullptr, &H->dev);
+    mrhs_status st = MRHS_OK;
+    if (flags & MRHS_MIXED)
+        st = amg_make32(H);
+    const uint32_t sflags = (flags & MRHS_X0_GIVEN) | ((flags & MRHS_MIXED) ? kAmgVc32 : 0u);
+    if (st == MRHS_OK)
+        st = block_solve(A, B, X, SolveParams{m, tol, maxit, sflags}, ws, ws_bytes, s, info, nullptr, &H->dev);
     if (own) {
         (void)hipStreamSynchronize(s);
         (void)hipFree(ws);

@@ -235,13 +235,21 @@ struct AmgLevelDev {
     int64_t nnz_a = 0, nnz_p = 0;
     CsrView<double> A{}, Ah{}, P{}, R{};
     double *dl1_inv = nullptr;
+    // binary32 roundings of the values (same indices), made on first use
+    CsrView<float> A32{}, Ah32{}, P32{}, R32{};
+    float *dl1_inv32 = nullptr;
 };
 
 struct AmgDev {
     int nlev = 0;
     AmgLevelDev lev[kAmgMaxLevels];
     CsrView<double> cinv{};  // dense inverse of the coarsest operator, as a full CRS matrix
+    CsrView<float> cinv32{};
+    bool has32 = false;
 };
+
+// internal solve flag: AMG V-cycle in binary32 (block_bicgstab_amg with MRHS_MIXED)
+constexpr uint32_t kAmgVc32 = 1u << 8;
 
 struct Ctx;
 struct AmgStepTable {
@@ -275,6 +283,7 @@ struct Ctx {
     const AmgDev *amg = nullptr;           // AMG-preconditioned iteration (else Jacobi)
     double *sv = nullptr, *ph = nullptr, *sh = nullptr;  // AMG: s, M^-1 p, M^-1 s
     char *vcws = nullptr;                  // AMG: V-cycle level buffers
+    bool vc32 = false;                     // AMG: V-cycle in binary32
 };
 
 struct StepTable {
@@ -360,9 +369,11 @@ size_t padded_block_bytes(int32_t n, int w);
 
 size_t solve_workspace_bytes(const mrhs_csr_s &A, int32_t m, uint32_t flags, const AmgDev *amg = nullptr);
 
-// The device view and device bytes of a hierarchy (amg.hip).
+// The device view and device bytes of a hierarchy (amg.hip); amg_make32
+// adds the binary32 roundings of its values once.
 const AmgDev *amg_dev_of(mrhs_amg H);
 size_t amg_bytes_of(mrhs_amg H);
+mrhs_status amg_make32(mrhs_amg H);
 // host_ctl and amg as for Engine
 mrhs_status block_solve(const mrhs_csr_s &A, const double *B, double *X, const SolveParams &p,
                         void *ws, size_t ws_bytes, hipStream_t s, mrhs_col_info *info, Ctl *host_ctl = nullptr,

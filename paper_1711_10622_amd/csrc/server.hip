@@ -194,8 +194,6 @@ MRHS_API mrhs_status solve_server_create(size_t hbm_budget_bytes, uint32_t flags
     *out = nullptr;
     if (flags & ~(MRHS_SERVER_MIXED | MRHS_SERVER_AMG))
         return set_error(MRHS_EINVAL, "unknown flags 0x%x", flags);
-    if ((flags & MRHS_SERVER_MIXED) && (flags & MRHS_SERVER_AMG))
-        return set_error(MRHS_EINVAL, "MRHS_SERVER_MIXED and MRHS_SERVER_AMG exclude each other");
     auto *s = new (std::nothrow) mrhs_server_s(hbm_budget_bytes);
     if (!s)
         return set_error(MRHS_ENOMEM, "host allocation failed");
@@ -213,12 +211,17 @@ MRHS_API mrhs_status solve_server_register(mrhs_server srv, mrhs_csr A, int32_t 
         return set_error(MRHS_EINVAL, "empty matrix");
     if (A->zero_diag)
         return set_error(MRHS_EINVAL, "the matrix has a zero diagonal entry");
-    const uint32_t eflags = (srv->flags & MRHS_SERVER_MIXED) ? MRHS_MIXED : 0u;
+    // binary32 in the engine: the inner Jacobi solves, or the V-cycle with AMG
+    const bool use_amg = (srv->flags & MRHS_SERVER_AMG) != 0;
+    const bool f32 = (srv->flags & MRHS_SERVER_MIXED) != 0;
+    const uint32_t eflags = f32 ? (use_amg ? kAmgVc32 : MRHS_MIXED) : 0u;
     mrhs_amg H = nullptr;
-    if (srv->flags & MRHS_SERVER_AMG) {
-        const mrhs_status a = amg_create(A, 0.0, 0, 0, &H);
+    if (use_amg) {
+        mrhs_status a = amg_create(A, 0.0, 0, 0, &H);
+        if (a == MRHS_OK && f32 && (a = amg_make32(H)) != MRHS_OK)
+            (void)amg_destroy(H);
         if (a != MRHS_OK)
-            return a;  // amg_create set the message
+            return a;  // amg_create / amg_make32 set the message
     }
     const AmgDev *amg = H ? amg_dev_of(H) : nullptr;
     const size_t resident = A->bytes + (H ? amg_bytes_of(H) : 0);

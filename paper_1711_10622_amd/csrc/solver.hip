@@ -406,6 +406,7 @@ Engine::Engine(const mrhs_csr_s &A, int m, uint32_t flags, void *ws, const doubl
             c_.ph = reinterpret_cast<double *>(base + L.ph64);
             c_.sh = reinterpret_cast<double *>(base + L.sh64);
             c_.vcws = base + L.vc;
+            c_.vc32 = (flags & kAmgVc32) != 0;
         }
     }
     chunk_ = env_int("MRHS_POLL_ITERS", 16, 1, 1024);

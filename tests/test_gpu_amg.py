@@ -161,12 +161,57 @@ def test_amg_argument_errors(env):
     v = ctypes.c_void_p
     assert lib.amg_vcycle(H.handle, v(B.data_ptr()), v(X.data_ptr()), 4, None, 0, None) == _lib.EINVAL
     assert lib.amg_vcycle(H.handle, v(B.data_ptr()), v(B.data_ptr()), 4, None, 0, None) == _lib.EINVAL
-    assert lib.block_bicgstab_amg(H.handle, v(B.data_ptr()), v(X.data_ptr()), 4, 1e-10, 10, _lib.MIXED, None, 0,
+    assert lib.block_bicgstab_amg(H.handle, v(B.data_ptr()), v(X.data_ptr()), 4, 1e-10, 10, 0x40, None, 0,
                                   None, None) == _lib.EINVAL
     assert lib.amg_level(H.handle, H.levels, None, None, None) == _lib.EINVAL
     assert lib.amg_create(M.handle, 1.5, 0, 0, ctypes.byref(ctypes.c_void_p())) == _lib.EINVAL
     # zero right-hand sides: x = 0, OK, no iterations
     Xz, infos, st = H.solve(B, tol=1e-10, maxit=10)
     assert st == 0 and all(i["iters"] == 0 for i in infos) and torch.count_nonzero(Xz) == 0
+    H.close()
+    M.close()
+
+
+@pytest.mark.parametrize("case,m", [(0, 4), (1, 3), (2, 8), (3, 8), (2, 16)])
+def test_amg_solve_vcycle32(env, case, m):
+    """The V-cycle in binary32 (MRHS_MIXED): the iteration, its products and
+    x stay binary64, so the solve still reaches 1e-10 (true residual); the
+    preconditioner differs from the binary64 one by rounding only, so the
+    iteration counts stay within max(2, 20 %) of the binary64 V-cycle's and
+    the solutions agree within the tolerance."""
+    torch, p = env
+    name, A, ns = list(small_cases())[case]
+    M = p.CsrMatrix.from_csr(A, nullspace_const=ns)
+    H = p.AmgHierarchy(M)
+    B = rng.rhs_block(A.n, m, 750 + m, mean_zero=ns)
+    X64, i64, s64 = H.solve(torch.from_numpy(B).cuda(), tol=1e-10, maxit=200)
+    X32, i32, s32 = H.solve(torch.from_numpy(B).cuda(), tol=1e-10, maxit=200, mixed=True)
+    assert s64 == 0 and s32 == 0, (i64, i32)
+    X64, X32 = X64.cpu().numpy(), X32.cpu().numpy()
+    assert np.all(true_relres(A, X32, B) <= 1e-10)
+    for a, b in zip(i32, i64):
+        assert abs(a["iters"] - b["iters"]) <= max(2, 0.2 * b["iters"]), (a, b)
+    d = np.linalg.norm(mean_free(X32) - mean_free(X64), axis=0) / np.linalg.norm(mean_free(X64), axis=0)
+    assert np.all(d <= 1e-6), d
+    # the binary32 roundings are made once and kept: a second call agrees bitwise
+    X32b, _, _ = H.solve(torch.from_numpy(B).cuda(), tol=1e-10, maxit=200, mixed=True)
+    assert np.array_equal(X32b.cpu().numpy(), X32)
+    H.close()
+    M.close()
+
+
+@pytest.mark.parametrize("wl,m", [("chan128", 16), ("cube192", 8)])
+def test_amg_solve_vcycle32_full_size(env, wl, m):
+    torch, p = env
+    w = configs.WORKLOADS[wl]
+    A = w.matrix()
+    B = w.rhs(A.n, m)
+    M = p.CsrMatrix.from_csr(A)
+    H = p.AmgHierarchy(M)
+    X, infos, st = H.solve(torch.from_numpy(B).cuda(), tol=1e-10, maxit=500, mixed=True)
+    X = X.cpu().numpy()
+    assert st == 0, infos
+    assert max(i["iters"] for i in infos) <= 100, infos
+    assert np.all(true_relres(A, X, B) <= 1e-10)
     H.close()
     M.close()

@@ -197,16 +197,18 @@ def test_budget_turns_no_starvation(mrhs, mats):
     srv.close()
 
 
-def test_amg_server(mrhs, mats):
+@pytest.mark.parametrize("vc32", [False, True])
+def test_amg_server(mrhs, mats, vc32):
     """MRHS_SERVER_AMG: every request is solved by AMG-preconditioned block
-    BiCGStab (a hierarchy per registered matrix); each result meets the
-    tolerance in few iterations, equals bitwise the same request served
-    alone, and agrees with block_bicgstab_amg on the matrix."""
+    BiCGStab (a hierarchy per registered matrix; with MRHS_SERVER_MIXED the
+    V-cycle in binary32); each result meets the tolerance in few iterations,
+    equals bitwise the same request served alone, and agrees with
+    block_bicgstab_amg on the matrix."""
     import torch
     As, Ms = mats
     A = As["chan"]
     R = rhs_for(A, 3, 4343)
-    srv = mrhs.SolveServer(4 * GiB, amg=True)
+    srv = mrhs.SolveServer(4 * GiB, amg=True, mixed=vc32)
     mid = srv.register(Ms["chan"])
     X_alone, inf_alone, st = srv.wait(srv.submit(mid, R, tol=1e-10))
     srv.close()
@@ -214,12 +216,12 @@ def test_amg_server(mrhs, mats):
     assert np.all(true_relres(A, X_alone, R) <= 1e-10)
     assert max(i["iters"] for i in inf_alone) <= 40, inf_alone
     H = mrhs.AmgHierarchy(Ms["chan"])
-    Xh, ih, sh = H.solve(torch.from_numpy(R).cuda(), tol=1e-10, maxit=20000)
+    Xh, ih, sh = H.solve(torch.from_numpy(R).cuda(), tol=1e-10, maxit=20000, mixed=vc32)
     H.close()
     assert sh == 0
     Xh = Xh.cpu().numpy()
     assert np.linalg.norm(X_alone - Xh) <= 1e-6 * np.linalg.norm(Xh)
-    srv = mrhs.SolveServer(4 * GiB, amg=True)
+    srv = mrhs.SolveServer(4 * GiB, amg=True, mixed=vc32)
     ids = {k: srv.register(M) for k, M in Ms.items()}
     r = np.random.default_rng(8)
     sent = []
