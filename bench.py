@@ -528,11 +528,12 @@ def gspmv_only(name):
     return 0
 
 
-def solve_only(name, mixed, steps, maxit=20000):
+def solve_only(name, mixed, steps, maxit=20000, reorder=False):
     """``steps`` block solves of one workload at its largest configured m
     (binary64, or mixed), after one untimed solve: for kernel traces and
     counter runs under rocprofv3.  A small ``maxit`` caps the iterations
-    (every column stays active, so every launch moves its full bytes)."""
+    (every column stays active, so every launch moves its full bytes);
+    ``reorder`` renumbers the matrix by reverse Cuthill-McKee."""
     import numpy as np
     import torch
     import paper_1711_10622_amd as mrhs
@@ -541,14 +542,14 @@ def solve_only(name, mixed, steps, maxit=20000):
     wl = configs.WORKLOADS[name]
     m = max(wl.ms)
     A = wl.matrix()
-    M = mrhs.CsrMatrix.from_csr(A)
+    M = mrhs.CsrMatrix.from_csr(A, reorder=reorder)
     B = torch.from_numpy(np.ascontiguousarray(wl.rhs(A.n, m))).cuda()
     X = torch.empty_like(B)
     ws = torch.empty(M.workspace_size(m, mixed), dtype=torch.uint8, device="cuda")
     ok = maxit >= 20000
     timed_solves(torch, M, B, X, ws, 1, mixed=mixed, maxit=maxit, expect_ok=ok)
     t, infos, _ = timed_solves(torch, M, B, X, ws, steps, mixed=mixed, maxit=maxit, expect_ok=ok)
-    log(f"solve {name} m={m} {'mixed' if mixed else 'fp64'}: {t * 1e3:.1f} ms per solve, "
+    log(f"solve {name}{' (RCM)' if reorder else ''} m={m} {'mixed' if mixed else 'fp64'}: {t * 1e3:.1f} ms per solve, "
         f"iterations max {max(i['iters'] for i in infos)}, outer max {max(i['outer'] for i in infos)}")
     M.close()
     return 0
@@ -793,6 +794,8 @@ def main():
                     help="run only --steps solves of WORKLOAD (after one warm-up), for kernel traces")
     ap.add_argument("--mixed", action="store_true", help="with --solve-only: mixed precision")
     ap.add_argument("--maxit", type=int, default=20000, help="with --solve-only: iteration cap")
+    ap.add_argument("--reorder", action="store_true",
+                    help="with --solve-only: renumber the matrix by reverse Cuthill-McKee")
     ap.add_argument("--gspmv-only", metavar="MATRIX",
                     help="run only five GSpMV launches per case on MATRIX (counter runs under rocprofv3)")
     ap.add_argument("--summarize", nargs=3, metavar=("OUTDIR", "WORKLOAD", "M"),
@@ -810,7 +813,7 @@ def main():
     if args.gspmv_only:
         return gspmv_only(args.gspmv_only)
     if args.solve_only:
-        return solve_only(args.solve_only, args.mixed, args.steps, args.maxit)
+        return solve_only(args.solve_only, args.mixed, args.steps, args.maxit, args.reorder)
 
     import numpy as np
     import torch

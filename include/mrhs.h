@@ -447,7 +447,7 @@ mrhs_status mrhs_stream_probe(int32_t kind, const void *src, void *dst, size_t b
  * {"<kernel>/<f64|f32>/m<M>/g<grid>": {"seen", "launches", "total_ms",
  * "min_ms", "max_ms"}, ...} into buf (cap bytes; the grid is followed by
  * "w" for products that staged their gathered rows in LDS windows, the plane
- * march of grid operators), where "seen" counts all
+ * march of grid operators that MRHS_MARCH=1 selects), where "seen" counts all
  * launches of the class and "launches" the timed ones; *len receives the
  * length needed (without the NUL).  EINVAL if the text did not fit (it is
  * truncated).  Not for use while other threads launch library kernels.

@@ -542,10 +542,54 @@ __device__ __forceinline__ void gspmv_tiles(const CsrView<T> &A, const Op &op,
             continue;
         const int32_t r0 = tile * S::TR;
         const int nr = min(S::TR, A.n - r0);
-        const Staged st = stage_csr<T, S::NZCAP>(A, r0, nr, s_rp, s_ci, s_va);
-        const int32_t z0 = st.z0;
-        const int lead = st.lead;
-        const bool staged = st.staged;
+        for (int k = tid; k <= nr; k += kBlock)
+            s_rp[k] = A.rp[r0 + k];
+        __syncthreads();
+        const int32_t z0 = s_rp[0];
+        const int cnt = s_rp[nr] - z0;
+        // 16-byte loads from the 4-aligned index zb <= z0 (the matrix arrays
+        // carry 4 elements of padding, so whole vectors stay in bounds); every
+        // thread issues all of its loads before writing any of them to LDS
+        const int32_t zb = z0 & ~3;
+        const int lead = z0 - zb;
+        const bool staged = cnt + lead <= S::NZCAP;
+        if (staged) {
+            using I4 = int __attribute__((ext_vector_type(4)));
+            constexpr int VV = 16 / static_cast<int>(sizeof(T));
+            using TV = T __attribute__((ext_vector_type(VV)));
+            constexpr int CI_PT = ((S::NZCAP + 4) / 4 + kBlock - 1) / kBlock;
+            constexpr int VA_PT = ((S::NZCAP + 4) / VV + kBlock - 1) / kBlock;
+            const int nci = (cnt + lead + 3) / 4;
+            const int nva = (cnt + lead + VV - 1) / VV;
+            const I4 *gci = reinterpret_cast<const I4 *>(A.ci + zb);
+            const TV *gva = reinterpret_cast<const TV *>(A.va + zb);
+            I4 bci[CI_PT];
+            TV bva[VA_PT];
+#pragma unroll
+            for (int u = 0; u < CI_PT; ++u) {
+                const int k = tid + u * kBlock;
+                if (k < nci)
+                    bci[u] = __builtin_nontemporal_load(gci + k);
+            }
+#pragma unroll
+            for (int u = 0; u < VA_PT; ++u) {
+                const int k = tid + u * kBlock;
+                if (k < nva)
+                    bva[u] = __builtin_nontemporal_load(gva + k);
+            }
+#pragma unroll
+            for (int u = 0; u < CI_PT; ++u) {
+                const int k = tid + u * kBlock;
+                if (k < nci)
+                    reinterpret_cast<I4 *>(s_ci)[k] = bci[u];
+            }
+#pragma unroll
+            for (int u = 0; u < VA_PT; ++u) {
+                const int k = tid + u * kBlock;
+                if (k < nva)
+                    reinterpret_cast<TV *>(s_va)[k] = bva[u];
+            }
+        }
         __syncthreads();
         const int32_t *lci = s_ci + lead;
         const T *lva = s_va + lead;
@@ -578,13 +622,6 @@ __device__ __forceinline__ void gspmv_tiles(const CsrView<T> &A, const Op &op,
         __syncthreads();
     }
 }
-
-// Ops that set kMarch = true take the plane march (gspmv_march) on grid
-// operators by default; the others only when MRHS_MARCH=2.
-template <class Op, class = void>
-struct march_ok : std::false_type {};
-template <class Op>
-struct march_ok<Op, std::void_t<decltype(Op::kMarch)>> : std::integral_constant<bool, Op::kMarch> {};
 
 // ---- plane march: gathered block rows staged in LDS -------------------------
 // For a grid operator in natural order (forward reach R = a whole number of

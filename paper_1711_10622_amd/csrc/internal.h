@@ -119,8 +119,9 @@ __global__ void __launch_bounds__(kBlock) k_gspmv_march(CsrView<T> A, Op op, Red
 // workgroups, discounted by the extra window each run loads first.
 int32_t march_runs(int32_t n, int32_t reach, int tile_rows, int grid);
 
-// MRHS_MARCH: 0 never march, 1 (default) march the ops that set kMarch,
-// 2 march every product (measurement).
+// MRHS_MARCH=1 runs every product over a grid operator as a plane march
+// (measured slower than the tiled products at every block width, so off by
+// default; kept to measure LDS staging of the gathered rows).
 int march_mode();
 
 template <typename T, int M, class Op>
@@ -166,7 +167,7 @@ inline hipError_t launch_gspmv(const CsrView<T> &A, const Op &op, const RedBufs<
             return hipGetLastError();
         }
     }
-    if (A.reach > 0 && A.reach % MarchShape<T, M>::TR == 0 && march_mode() >= (march_ok<Op>::value ? 1 : 2)) {
+    if (A.reach > 0 && A.reach % MarchShape<T, M>::TR == 0 && march_mode()) {
         const void *fm = reinterpret_cast<const void *>(&k_gspmv_march<T, M, Op>);
         const int grid = grid_for(fm, A.n, MarchShape<T, M>::TR);
         const int32_t runs = march_runs(A.n, A.reach, MarchShape<T, M>::TR, grid);

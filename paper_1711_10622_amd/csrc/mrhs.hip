@@ -82,7 +82,7 @@ int grid_for(const void *kernel, int64_t n, int tile_rows)
     return static_cast<int>(g);
 }
 
-int march_mode() { return env_int("MRHS_MARCH", 1, 0, 2); }
+int march_mode() { return env_int("MRHS_MARCH", 0, 0, 1); }
 
 int32_t march_runs(int32_t n, int32_t reach, int tile_rows, int grid)
 {

@@ -501,11 +501,6 @@ struct OpSpmv2 {
 #define MRHS_OMEGA_GATHERED 2
 #endif
     static constexpr int GATHERED = MRHS_OMEGA_GATHERED;  // r and v
-    // on grid operators the plane march stages s = r - alpha v once per row
-    // in LDS instead of gathering both r and v at every entry (12.6M-row
-    // channel, m = 16: binary64 2072 -> 1994 us; binary32 1059 -> 1069 us,
-    // so binary32 keeps the tiled product)
-    static constexpr bool kMarch = std::is_same<T, double>::value;
     const T *r;
     const T *v;
     const uint8_t *sgn;  // sign bits of the shadow residual, or null: generated
