@@ -261,6 +261,32 @@ def gspmv_sweep(torch, A, ms, dtypes, flush=False, reps=50):
     return out
 
 
+def gspmv_locality(torch, A, line=256):
+    """GSpMV on A with every column index moved into its row's own line of
+    ``line`` rows (same row lengths, values and bytes; every gather then hits
+    rows the tile just fetched): the time the product would take if staging
+    the gathered rows made every gather local."""
+    import numpy as np
+    from workloads.grids import CSRMatrix
+    rows = np.repeat(np.arange(A.n, dtype=np.int64), np.diff(A.row_ptr))
+    col = ((rows // line) * line + (A.col.astype(np.int64) % line)).astype(np.int32)
+    del rows
+    L = CSRMatrix(A.n, A.row_ptr, col, A.val, name=A.name + "_inline")
+    return gspmv_sweep(torch, L, [8, 16], ("f64", "f32"), reps=20)
+
+
+def gspmv_cube(torch):
+    """GSpMV on the relabelled cube channel as generated and renumbered by
+    reverse Cuthill-McKee (the permutation MRHS_CSR_REORDER applies)."""
+    import paper_1711_10622_amd as mrhs
+    from workloads import configs, grids
+    C = configs.MATRICES["cube192"]()
+    out = {"relabelled": gspmv_sweep(torch, C, [8, 16], ("f64", "f32"), reps=20)}
+    Cr = grids.permute_symmetric(C, mrhs.reorder_permutation(C))
+    out["rcm"] = gspmv_sweep(torch, Cr, [8, 16], ("f64", "f32"), reps=20)
+    return out
+
+
 def solve_pair(torch, name, m, steps, reorder=False, amg_per_iter=None):
     """binary64 and mixed block solves of one workload, its own matrix
     (renumbered by reverse Cuthill-McKee when ``reorder``), then the AMG legs."""
@@ -887,7 +913,9 @@ def main():
         extra["amg"] = amg_legs(torch, A, Bh, m, step_s)
         log(f"amg: {extra['amg']}")
         extra["gspmv_chan256"] = gspmv_sweep(torch, A, list(range(1, 17)), ("f64", "f32"), reps=20)
-        log("gspmv sweep done")
+        extra["gspmv_chan256_local_gathers"] = gspmv_locality(torch, A)
+        extra["gspmv_cube192"] = gspmv_cube(torch)
+        log("gspmv sweeps done")
         legs, A2, Bh2, Xs2 = chan128_legs(torch, 2)
         extra["chan128"] = legs
         log(f"chan128: {legs}")

@@ -1009,6 +1009,42 @@ struct ColLane {
     bool on;
 };
 
+// W = A Z for the K refinement columns whose inner solves ended in the same
+// round, their vectors column-major (one n-vector per column, so each column
+// keeps streaming only its own vectors): one product reads the matrix once
+// for all K columns (each column's row sums are those of its own product).
+template <int K>
+struct OpColsStore {
+    static constexpr const char *kName = "gcr_aw";
+    using S = Shape<double, K>;
+    static constexpr int NDOT = 0;
+    const double *z[K];
+    double *w[K];
+    struct Lane {
+        bool on;
+    };
+    __device__ Lane lane(int) const { return {true}; }
+    __device__ __forceinline__ void gather(const Lane &, int32_t c, int g, double *x) const
+    {
+#pragma unroll
+        for (int v = 0; v < S::VW; ++v) {
+            const int q = g * S::VW + v;
+            x[v] = q < K ? z[q][c] : 0.0;
+        }
+    }
+    __device__ __forceinline__ void row(const Lane &, int32_t i, int g, const double *sum,
+                                        Acc<double, S::VW, NDOT> &) const
+    {
+#pragma unroll
+        for (int v = 0; v < S::VW; ++v) {
+            const int q = g * S::VW + v;
+            if (q < K)
+                __builtin_nontemporal_store(sum[v], w[q] + i);
+        }
+    }
+    __device__ void finish(const double *) const {}
+};
+
 // beta_j = (w, w_j) / (w_j, w_j) over the column's stored directions (slot
 // kcol[c] is about to be replaced and is left out)
 struct OpColDots {

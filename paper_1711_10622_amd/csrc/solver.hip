@@ -193,6 +193,25 @@ __global__ void k_ctl_reset(Ctl *ctl, int32_t mode, double tol_in, int32_t max_o
             return e_;          \
     } while (0)
 
+// launches OpColsStore<K> for the K columns listed in cols
+struct ColsProduct {
+    CsrView<double> A;
+    Ctx &c;
+    int cols[kMaxM];
+    int k;
+    template <int K>
+    hipError_t operator()() const
+    {
+        OpColsStore<K> op{};
+        const size_t n = static_cast<size_t>(c.n);
+        for (int q = 0; q < K; ++q) {
+            op.z[q] = c.gcr.znew + static_cast<size_t>(cols[q]) * n;
+            op.w[q] = c.gcr.wnew + static_cast<size_t>(cols[q]) * n;
+        }
+        return launch_gspmv<double, K>(A, op, c.rb64, c.s);
+    }
+};
+
 template <int M>
 struct Steps {
     static hipError_t f64_start(Ctx &c, uint32_t cmask, bool x0)
@@ -256,12 +275,19 @@ struct Steps {
         MRHS_TRY((launch_stream<float, M>(c.n, OpGcrZ<M>{c.gcr.znew, c.y32, c.A->dinv, c.ctl, c.n}, c.rb32, c.s)));
         const CsrView<double> A = view<double>(*c.A, false);
         const size_t n = static_cast<size_t>(c.n);
+        {  // w = A z for every column of the round in one product
+            ColsProduct cp{A, c, {}, 0};
+            for (int col = 0; col < M; ++col)
+                if ((cmask >> col) & 1u)
+                    cp.cols[cp.k++] = col;
+            if (cp.k > 0)
+                MRHS_TRY(dispatch_m(cp.k, cp));
+        }
         for (int col = 0; col < M; ++col) {
             if (!((cmask >> col) & 1u))
                 continue;
             const size_t off = static_cast<size_t>(col) * n;
             double *z = c.gcr.znew + off, *w = c.gcr.wnew + off, *r = c.r64 + off;
-            MRHS_TRY((launch_gspmv<double, 1>(A, OpStore<double, 1>{z, w}, c.rb64, c.s)));
             OpColDots dots{};
             OpColOrth orth{};
             for (int j = 0; j < kGcrMax; ++j) {
