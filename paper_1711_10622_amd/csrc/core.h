@@ -641,7 +641,15 @@ __device__ __forceinline__ void gspmv_tiles(const CsrView<T> &A, const Op &op,
 // Schedule: group x = b % 8 owns the x-th eighth of the tile columns; its
 // workgroups take units u = (run, column) in turn, the columns of one run of
 // planes first, so the tiles beside a column are walked by the group's other
-// workgroups at about the same time.
+// workgroups at about the same time.  The window of plane z + 2 is fetched
+// into registers while plane z is computed.
+//
+// Measured on the 12.6M-row channel (binary64, m = 16) it is slower than
+// gspmv_tiles: the 64-row march tiles that keep three windows and four
+// workgroups per CU in LDS cost four times the tile-staging round trips of a
+// 256-row tile, more than the plane gathers it saves (the GSpMV with every
+// gather local takes 840 us against 1003 us, an upper bound on any staging).
+// It is selected only by MRHS_MARCH=1.
 #ifndef MRHS_MARCH_ROWS
 #define MRHS_MARCH_ROWS 64
 #endif
