@@ -614,7 +614,7 @@ OP_NAMES = {"OpXR": "xr_update", "OpSpmv2": "spmv_omega", "OpSpmv1": "spmv_sigma
             "OpCast": "cast32", "OpGcrZ": "gcr_z", "OpColDots": "gcr_dots", "OpColOrth": "gcr_orth",
             "OpColUpdate": "gcr_update", "OpFold": "fold", "OpSpmv2P": "amg_omega", "OpXRP": "amg_xr",
             "OpSForm": "amg_s", "OpVcRes": "vc_resid", "OpVcProl": "vc_prolong", "OpVcSmooth": "vc_smooth",
-            "OpVcStore": "vc_store"}
+            "OpVcStore": "vc_store", "OpColsStore": "gcr_aw", "OpTo32": "amg_to32", "OpTo64": "amg_to64"}
 
 
 def kernel_class(name):
