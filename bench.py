@@ -132,17 +132,22 @@ def dominant_kernel(trace, n, nnz):
 
 
 def timed_solves(torch, M, B, X, ws, steps, mixed=False, trace=False, tol=1e-10, maxit=20000,
-                 expect_ok=True):
+                 expect_ok=True, label=None):
+    """``steps`` block solves; each returns once its columns are decided (the
+    library reads their states back), so a ``label`` line after every solve
+    reports progress without adding a synchronization."""
     import paper_1711_10622_amd as mrhs
     infos = None
     torch.cuda.synchronize()
     if trace:
         mrhs.trace_enable(True, every=TRACE_EVERY)
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for k in range(steps):
         _, infos, st = M.solve(B, tol=tol, maxit=maxit, mixed=mixed, out=X, workspace=ws)
         if expect_ok and st != 0:
             raise RuntimeError(f"solve did not converge: {infos}")
+        if label:
+            log(f"{label} solve {k + 1}/{steps} done")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     tr = None
@@ -861,8 +866,8 @@ def main():
     log(f"workload {HEADLINE} n={A.n} nnz={A.nnz} m={m}")
 
     if args.warmup:
-        timed_solves(torch, M, B, X, ws, args.warmup)
-    step_s, infos, trace = timed_solves(torch, M, B, X, ws, args.steps, trace=True)
+        timed_solves(torch, M, B, X, ws, args.warmup, label="warm-up")
+    step_s, infos, trace = timed_solves(torch, M, B, X, ws, args.steps, trace=True, label="timed")
     dom = dominant_kernel(trace, A.n, A.nnz)
     iters = max(i["iters"] for i in infos)
     log(f"step {step_s * 1e3:.2f} ms, {iters} iterations, dominant {dom['kernel']} {dom['avg_us']:.1f} us")
