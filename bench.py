@@ -614,6 +614,26 @@ def per_iteration(torch, M, Bh, ms, reps=1):
     return out
 
 
+def small_iterations(torch):
+    """Time per binary64 block iteration (m = 16) on matrices small enough
+    that an iteration's three kernels are bound by their fixed costs (launch,
+    the grid reductions' last-workgroup tails) rather than by bytes: the
+    ceiling on what merging the iteration's kernels could save."""
+    import paper_1711_10622_amd as mrhs
+    from workloads import configs
+    out = {}
+    for name in ("dir16", "dir32", "dir64", "chan128"):
+        wl = configs.WORKLOADS[name]
+        A = wl.matrix()
+        M = mrhs.CsrMatrix.from_csr(A)
+        Bh = wl.rhs(A.n, 16)
+        r = per_iteration(torch, M, Bh, (16,))
+        out[name] = {"n": A.n, "ms_per_iter": r[16]["ms_per_iter"],
+                     "us_per_kernel": round(r[16]["ms_per_iter"] * 1e3 / 3, 1)}
+        M.close()
+    return out
+
+
 OP_NAMES = {"OpXR": "xr_update", "OpSpmv2": "spmv_omega", "OpSpmv1": "spmv_sigma", "OpResid": "resid",
             "OpScale": "scale", "OpRestart": "restart", "OpColSum": "colsum", "OpStore": "gspmv",
             "OpCast": "cast32", "OpGcrZ": "gcr_z", "OpColDots": "gcr_dots", "OpColOrth": "gcr_orth",
@@ -912,8 +932,10 @@ def main():
         del Xf, d, xf
         del ws, B, X
         torch.cuda.empty_cache()
-        extra["per_iter_fp64"] = per_iteration(torch, M, Bh, (1, 2, 4, 8, 16))
+        extra["per_iter_fp64"] = per_iteration(torch, M, Bh, (1, 2, 4, 7, 8, 15, 16))
         log(f"per iteration: {extra['per_iter_fp64']}")
+        extra["per_iter_small"] = small_iterations(torch)
+        log(f"per iteration, small matrices: {extra['per_iter_small']}")
         M.close()
         extra["amg"] = amg_legs(torch, A, Bh, m, step_s)
         log(f"amg: {extra['amg']}")
