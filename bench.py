@@ -768,15 +768,23 @@ def amg_legs(torch, A, Bh, m, t_jacobi, per_iter_ms=(1, 2, 4, 8, 16), steps=1, r
         Bm = torch.from_numpy(np.ascontiguousarray(Bh[:, :mm])).to("cuda")
         Xm = torch.empty_like(Bm)
         wsm = torch.empty(H.workspace_size(mm), dtype=torch.uint8, device="cuda")
+        # 4 and 12 iterations: the preconditioned residual is still far above
+        # rounding level there (about 17 iterations reach 1e-10), so no column
+        # stops early on a breakdown; the faster of two runs of each
         tt = {}
-        for k in (10, 20):
+        for k in (4, 12):
             H.solve(Bm, tol=1e-300, maxit=k, out=Xm, workspace=wsm)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            H.solve(Bm, tol=1e-300, maxit=k, out=Xm, workspace=wsm)
-            torch.cuda.synchronize()
-            tt[k] = time.perf_counter() - t0
-        per[mm] = {"ms_per_iter": round((tt[20] - tt[10]) / 10 * 1e3, 4)}
+            best = None
+            for _ in range(2):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, inf, _ = H.solve(Bm, tol=1e-300, maxit=k, out=Xm, workspace=wsm)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                best = dt if best is None else min(best, dt)
+            assert all(i["iters"] == k for i in inf), inf
+            tt[k] = best
+        per[mm] = {"ms_per_iter": round((tt[12] - tt[4]) / 8 * 1e3, 4)}
         del Bm, Xm, wsm
     if 1 in per:
         for mm, d in per.items():
