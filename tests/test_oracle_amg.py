@@ -183,3 +183,33 @@ def test_amg_bicgstab_against_lapack(case):
             ev = np.linalg.eigvalsh(D)
             kappa = ev[-1] / ev[0]
         assert np.linalg.norm(x - ref) <= kappa * 1e-11 * np.linalg.norm(ref) * 1.01
+
+
+def test_l1_jacobi_weights_closed_form():
+    """The l1-Jacobi weights of the unit 7-point Dirichlet stencil: a row's
+    absolute sum is 6 plus one per neighbour inside the box, so interior,
+    face, edge and corner rows weigh 1/12, 1/11, 1/10 and 1/9."""
+    N = 6
+    A = grids.dirichlet7(N)
+    H = amg.setup(A.n, A.row_ptr, A.col, A.val)
+    w = H.levels[0].dl1_inv
+    for z in range(N):
+        for y in range(N):
+            for x in range(N):
+                inside = sum(1 for c in (x, y, z) for d in (-1, 1) if 0 <= c + d < N)
+                assert w[(z * N + y) * N + x] == 1.0 / (6 + inside)
+
+
+def test_singular_coarsest_level_solves_mean_free():
+    """A channel operator (periodic x, z; Neumann walls) has the constants as
+    null space.  With one level the V-cycle applies (A + s 1 1^T)^-1, which on
+    a mean-free b returns the mean-free solution of A x = b exactly (to
+    rounding): 1^T A = 0 forces 1^T x = 0 and then A x = b."""
+    A = grids.channel7(6, 5, 4, beta=2.0)
+    H = amg.setup(A.n, A.row_ptr, A.col, A.val, nullspace_const=True, max_coarse=10**6)
+    assert len(H.levels) == 1 and H.shift > 0.0
+    b = rng.rhs_block(A.n, 3, 55, mean_zero=True)
+    x = amg.vcycle(H, b)
+    Ad = H.levels[0].A.to_dense()
+    assert np.abs(Ad @ x - b).max() <= 1e-11 * np.abs(b).max()
+    assert np.abs(x.mean(axis=0)).max() <= 1e-12 * np.abs(x).max()
