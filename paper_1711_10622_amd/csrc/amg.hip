@@ -25,6 +25,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <vector>
 
 #include "amg.h"
@@ -593,6 +594,7 @@ struct mrhs_amg_s {
     mrhs_csr A = nullptr;
     int device = 0;
     mrhs::AmgDev dev;
+    std::mutex mu32;  // serializes the one-time binary32 rounding (amg_make32)
     std::vector<std::vector<int8_t>> cf;  // C/F marks of every level but the coarsest
     std::vector<void *> allocs;
     size_t bytes = 0;
@@ -712,6 +714,7 @@ size_t amg_bytes_of(mrhs_amg H) { return H->bytes; }
 
 mrhs_status amg_make32(mrhs_amg H)
 {
+    std::lock_guard<std::mutex> lk(H->mu32);
     if (H->dev.has32)
         return MRHS_OK;
     (void)hipSetDevice(H->device);
