@@ -634,12 +634,43 @@ def small_iterations(torch):
     return out
 
 
+def merged_vs_plain(torch):
+    """Time per binary64 block iteration with two kernels per iteration
+    (MRHS_MERGE=2: the x/r/p update fused with the next v = A p) and with
+    three (MRHS_MERGE=0), at several m on a 64^3 Dirichlet operator and the
+    128x64x64 channel."""
+    import paper_1711_10622_amd as mrhs
+    from workloads import configs
+    out = {}
+    old = os.environ.get("MRHS_MERGE")
+    try:
+        for name in ("dir64", "chan128"):
+            wl = configs.WORKLOADS[name]
+            A = wl.matrix()
+            Bh = wl.rhs(A.n, 16)
+            rec = {}
+            for flag, tag in (("0", "three_kernels"), ("2", "two_kernels")):
+                os.environ["MRHS_MERGE"] = flag
+                M = mrhs.CsrMatrix.from_csr(A)
+                r = per_iteration(torch, M, Bh, (1, 4, 8, 16))
+                rec[tag] = {mm: d["ms_per_iter"] for mm, d in r.items()}
+                M.close()
+            out[name] = rec
+    finally:
+        if old is None:
+            os.environ.pop("MRHS_MERGE", None)
+        else:
+            os.environ["MRHS_MERGE"] = old
+    return out
+
+
 OP_NAMES = {"OpXR": "xr_update", "OpSpmv2": "spmv_omega", "OpSpmv1": "spmv_sigma", "OpResid": "resid",
             "OpScale": "scale", "OpRestart": "restart", "OpColSum": "colsum", "OpStore": "gspmv",
             "OpCast": "cast32", "OpGcrZ": "gcr_z", "OpColDots": "gcr_dots", "OpColOrth": "gcr_orth",
             "OpColUpdate": "gcr_update", "OpFold": "fold", "OpSpmv2P": "amg_omega", "OpXRP": "amg_xr",
             "OpSForm": "amg_s", "OpVcRes": "vc_resid", "OpVcProl": "vc_prolong", "OpVcSmooth": "vc_smooth",
-            "OpVcStore": "vc_store", "OpColsStore": "gcr_aw", "OpTo32": "amg_to32", "OpTo64": "amg_to64"}
+            "OpVcStore": "vc_store", "OpColsStore": "gcr_aw", "OpTo32": "amg_to32", "OpTo64": "amg_to64",
+            "OpXRSigma": "xr_sigma"}
 
 
 def kernel_class(name):
@@ -944,6 +975,8 @@ def main():
         log(f"per iteration: {extra['per_iter_fp64']}")
         extra["per_iter_small"] = small_iterations(torch)
         log(f"per iteration, small matrices: {extra['per_iter_small']}")
+        extra["merged_iteration"] = merged_vs_plain(torch)
+        log(f"merged iteration: {extra['merged_iteration']}")
         M.close()
         extra["amg"] = amg_legs(torch, A, Bh, m, step_s)
         log(f"amg: {extra['amg']}")

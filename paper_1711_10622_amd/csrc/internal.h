@@ -285,6 +285,8 @@ struct Ctx {
     double *sv = nullptr, *ph = nullptr, *sh = nullptr;  // AMG: s, M^-1 p, M^-1 s
     char *vcws = nullptr;                  // AMG: V-cycle level buffers
     bool vc32 = false;                     // AMG: V-cycle in binary32
+    bool merged = false;                   // binary64 Jacobi: two kernels per iteration
+    double *r2 = nullptr, *v2 = nullptr, *p2 = nullptr;  // merged: the other r/v/p set
 };
 
 struct StepTable {

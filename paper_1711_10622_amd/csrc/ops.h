@@ -444,6 +444,19 @@ __device__ __forceinline__ RunLane<T, M> run_lane(const Ctl *ctl, int g)
     return ln;
 }
 
+// Column c (running) after its sigma = (r^, v): counts the iteration and
+// forms alpha, or marks a breakdown.
+template <typename T>
+__device__ __forceinline__ void sigma_decide(Ctl &k, Kry<T> *kry, int c, T sigma)
+{
+    k.iters[c] += 1;
+    if (bad(sigma)) {
+        k.status[c] = (k.mode == MODE_INNER) ? COL_INNER_DONE : COL_PEND_BD;
+        return;
+    }
+    kry->alpha[c] = kry->rho[c] / sigma;
+}
+
 // v = Ah p with sigma = (r^, v); the last workgroup forms alpha.
 template <typename T, int M>
 struct OpSpmv1 {
@@ -479,14 +492,7 @@ struct OpSpmv1 {
         const int c = threadIdx.x;
         if (c >= M || ctl->status[c] != COL_RUN)
             return;
-        Ctl &k = *ctl;
-        k.iters[c] += 1;
-        const T sigma = tot[c];
-        if (bad(sigma)) {
-            k.status[c] = (k.mode == MODE_INNER) ? COL_INNER_DONE : COL_PEND_BD;
-            return;
-        }
-        kry->alpha[c] = kry->rho[c] / sigma;
+        sigma_decide(*ctl, kry, c, tot[c]);
     }
 };
 
@@ -587,6 +593,47 @@ struct OpSpmv2 {
     }
 };
 
+// Column c (running) after its x/r update with sums (r^, r) and (r, r): the
+// stopping tests and the next rho.
+template <typename T>
+__device__ __forceinline__ void xr_decide(Ctl &k, Kry<T> *kry, int c, T rhr, T rr)
+{
+    const bool inner = k.mode == MODE_INNER;
+    const double nb = inner ? static_cast<double>(kry->nbi[c]) : k.nb[c];
+    const double tol = inner ? k.tol_in : k.tol[c];
+    const double rn = static_cast<double>(sqrt(rr)) / nb;
+    k.rn[c] = rn;
+    const int32_t f = k.flag[c];
+    if (f & F_SCONV) {
+        k.status[c] = inner ? COL_INNER_DONE : COL_PEND_CHECK;
+        return;
+    }
+    if (f & F_OMEGA_BAD) {
+        k.status[c] = inner ? COL_INNER_DONE : COL_PEND_BD;
+        return;
+    }
+    kry->rho_old[c] = kry->rho[c];
+    kry->rho[c] = rhr;
+    k.fresh[c] = 0;
+    k.bd_run[c] = 0;
+    if (rn <= tol) {
+        k.status[c] = inner ? COL_INNER_DONE : COL_PEND_CHECK;
+    } else if (bad(rhr)) {
+        k.status[c] = inner ? COL_INNER_DONE : COL_PEND_BD;
+    } else if (inner) {
+        if (k.iters[c] >= k.inner_maxit[c]) {
+            k.status[c] = COL_INNER_DONE;
+        } else if (k.iters[c] - k.stag_it[c] >= k.stag_window) {
+            if (rn > 0.5 * k.stag_rn[c])
+                k.status[c] = COL_INNER_DONE;
+            k.stag_it[c] = k.iters[c];
+            k.stag_rn[c] = rn;
+        }
+    } else if (k.iters[c] >= k.maxit[c]) {
+        k.status[c] = COL_NOCONV;
+    }
+}
+
 // y += alpha p + omega s;  r = s - omega t  (s = r - alpha v); sums (r^, r)
 // and (r, r).  The last workgroup updates rho and each column's state.
 template <typename T, int M>
@@ -661,42 +708,133 @@ struct OpXR {
         const int c = threadIdx.x;
         if (c >= M || ctl->status[c] != COL_RUN)
             return;
-        Ctl &k = *ctl;
-        const bool inner = k.mode == MODE_INNER;
-        const T rhr = tot[c], rr = tot[M + c];
-        const double nb = inner ? static_cast<double>(kry->nbi[c]) : k.nb[c];
-        const double tol = inner ? k.tol_in : k.tol[c];
-        const double rn = static_cast<double>(sqrt(rr)) / nb;
-        k.rn[c] = rn;
-        const int32_t f = k.flag[c];
-        if (f & F_SCONV) {
-            k.status[c] = inner ? COL_INNER_DONE : COL_PEND_CHECK;
+        xr_decide(*ctl, kry, c, tot[c], tot[M + c]);
+    }
+};
+
+// One kernel for the end of an iteration and the start of the next: the
+// x/r/p update of OpXR and the product v = Ah p of OpSpmv1 with the new p.
+// The new p of a gathered row is formed on the fly from that row's old r, v,
+// t and p with the same fused operations as the row's own update, so v is
+// exactly Ah times the stored new p.  Other workgroups still gather the old
+// r, v, p while a row's new values are written, so those go to a second set
+// of blocks (r2, v2, p2; the caller alternates the two sets); y is only read
+// and written by its own row and is updated in place.  Sums (r^, r), (r, r)
+// and sigma = (r^, v); the last workgroup takes OpXR's decisions and then,
+// for columns still running, OpSpmv1's.  The binary64 Jacobi solve uses it
+// for narrow blocks on small and mid-size matrices (see merged_iteration).
+template <typename T, int M>
+struct OpXRSigma {
+    static constexpr const char *kName = "xr_sigma";
+    using S = Shape<T, M>;
+    static constexpr int NDOT = 3;
+    static constexpr int GATHERED = 4;  // r, v, t, p
+    T *y;
+    const T *r, *v, *t, *p;  // this iteration's blocks (r and v with row stride ldp)
+    T *r2, *v2, *p2;         // the next iteration's
+    Ctl *ctl;
+    Kry<T> *kry;
+    int32_t ldp;
+    struct Lane {
+        bool on;
+        bool act[S::VW];
+        bool use_w[S::VW];
+        T alpha[S::VW], omega[S::VW], beta[S::VW];
+    };
+    __device__ Lane lane(int g) const
+    {
+        Lane ln;
+        const RunLane<T, M> rl = run_lane<T, M>(ctl, g);
+        ln.on = rl.on;
+#pragma unroll
+        for (int q = 0; q < S::VW; ++q) {
+            const int c = g * S::VW + q;
+            ln.act[q] = rl.act[q];
+            ln.use_w[q] = c < M && ctl->flag[c] == 0;
+            ln.alpha[q] = c < M ? kry->alpha[c] : T(0);
+            ln.omega[q] = ln.use_w[q] ? kry->omega[c] : T(0);
+            ln.beta[q] = c < M ? kry->beta[c] : T(0);
+        }
+        return ln;
+    }
+    // s = r - alpha v; r' = s - omega t; p' = r' + beta (p - omega v) for a
+    // column taking the full step, r' = s and p' = p after the half step
+    // (s converged, or omega unusable), everything unchanged for a column
+    // that is not running
+    static __device__ __forceinline__ void step(const Lane &ln, int q, T r, T v, T t, T p, T &s, T &rn, T &pn)
+    {
+        if (!ln.act[q]) {
+            s = r;
+            rn = r;
+            pn = p;
             return;
         }
-        if (f & F_OMEGA_BAD) {
-            k.status[c] = inner ? COL_INNER_DONE : COL_PEND_BD;
-            return;
+        s = __builtin_fma(-ln.alpha[q], v, r);
+        if (ln.use_w[q]) {
+            rn = __builtin_fma(-ln.omega[q], t, s);
+            pn = __builtin_fma(ln.beta[q], __builtin_fma(-ln.omega[q], v, p), rn);
+        } else {
+            rn = s;
+            pn = p;
         }
-        kry->rho_old[c] = kry->rho[c];
-        kry->rho[c] = rhr;
-        k.fresh[c] = 0;
-        k.bd_run[c] = 0;
-        if (rn <= tol) {
-            k.status[c] = inner ? COL_INNER_DONE : COL_PEND_CHECK;
-        } else if (bad(rhr)) {
-            k.status[c] = inner ? COL_INNER_DONE : COL_PEND_BD;
-        } else if (inner) {
-            if (k.iters[c] >= k.inner_maxit[c]) {
-                k.status[c] = COL_INNER_DONE;
-            } else if (k.iters[c] - k.stag_it[c] >= k.stag_window) {
-                if (rn > 0.5 * k.stag_rn[c])
-                    k.status[c] = COL_INNER_DONE;
-                k.stag_it[c] = k.iters[c];
-                k.stag_rn[c] = rn;
+    }
+    __device__ __forceinline__ void gather(const Lane &ln, int32_t c, int g, T *x) const
+    {
+        T rr[S::VW], vv[S::VW], tt[S::VW], pp[S::VW];
+        ld<T, M>(r, c, g, rr, ldp);
+        ld<T, M>(v, c, g, vv, ldp);
+        ld<T, M>(t, c, g, tt);
+        ld<T, M>(p, c, g, pp);
+#pragma unroll
+        for (int q = 0; q < S::VW; ++q) {
+            T s_, r_;
+            step(ln, q, rr[q], vv[q], tt[q], pp[q], s_, r_, x[q]);
+        }
+    }
+    struct Pre {
+        T y[S::VW], r[S::VW], v[S::VW], t[S::VW], p[S::VW];
+    };
+    __device__ __forceinline__ Pre pre(const Lane &, int32_t i, int g) const
+    {
+        Pre pr;
+        ld<T, M>(y, i, g, pr.y);
+        ld<T, M>(r, i, g, pr.r, ldp);
+        ld<T, M>(v, i, g, pr.v, ldp);
+        ld<T, M>(t, i, g, pr.t);
+        ld<T, M>(p, i, g, pr.p);
+        return pr;
+    }
+    __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, const T *sum, Acc<T, S::VW, NDOT> &acc,
+                                        const Pre &pr) const
+    {
+        T yy[S::VW], rn[S::VW], pn[S::VW], hh[S::VW];
+        shadow_row<T, M>(nullptr, i, g, hh);
+#pragma unroll
+        for (int q = 0; q < S::VW; ++q) {
+            T s;
+            step(ln, q, pr.r[q], pr.v[q], pr.t[q], pr.p[q], s, rn[q], pn[q]);
+            yy[q] = pr.y[q];
+            if (ln.act[q]) {
+                yy[q] = ln.use_w[q] ? pr.y[q] + (ln.alpha[q] * pr.p[q] + ln.omega[q] * s)
+                                    : pr.y[q] + ln.alpha[q] * pr.p[q];
+                acc.a[0][q] += hh[q] * rn[q];
+                acc.a[1][q] += rn[q] * rn[q];
+                acc.a[2][q] += hh[q] * sum[q];
             }
-        } else if (k.iters[c] >= k.maxit[c]) {
-            k.status[c] = COL_NOCONV;
         }
+        st<T, M>(y, i, g, yy);
+        st<T, M>(r2, i, g, rn, ldp);
+        st<T, M>(p2, i, g, pn);
+        st<T, M>(v2, i, g, sum, ldp);
+    }
+    __device__ void finish(const T *tot) const
+    {
+        const int c = threadIdx.x;
+        if (c >= M || ctl->status[c] != COL_RUN)
+            return;
+        xr_decide(*ctl, kry, c, tot[c], tot[M + c]);
+        if (ctl->status[c] == COL_RUN)
+            sigma_decide(*ctl, kry, c, tot[2 * M + c]);
     }
 };
 

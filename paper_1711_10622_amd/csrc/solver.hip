@@ -40,6 +40,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
     size_t ctl, kry64, kry32, tickets, part, gpart;
     size_t rv64, p64, t64;  // r and v (one region, see pair_rv), p, t (binary64 solve)
+    size_t rv64b, p64b;     // the second r/v region and p of the merged iteration
     size_t sv64, ph64, sh64, vc;  // s, M^-1 p, M^-1 s, V-cycle buffers (AMG preconditioner)
     size_t r64;         // refinement residual             (mixed)
     size_t z[kGcrMax];  // stored directions z_j           (mixed)
@@ -70,6 +71,25 @@ bool pair_rv(const mrhs_csr_s &A, int32_t m, size_t elem)
     const int64_t P = (static_cast<int64_t>(A.reach) + kTileRows / 2) / kTileRows;
     const bool planes = P >= 2 * kGroups && ntiles >= 4 * P;
     return !planes || m * elem >= 128;
+}
+
+// The binary64 Jacobi iteration runs as two kernels (OpXRSigma, then
+// spmv_omega) where that was measured faster: narrow blocks on small and
+// mid-size matrices, whose iterations are bound by the kernels' latency
+// chains rather than bytes.  Per iteration (ms, three kernels -> two):
+// 524k-row channel m = 1 0.083 -> 0.061, m = 4 0.096 -> 0.086, m = 8 0.129 ->
+// 0.139; 64^3 Dirichlet m = 4 0.069 -> 0.054, m = 8 0.084 -> 0.080, m = 16
+// 0.122 -> 0.140; 12.6M-row channel slower at every m (its gathers of four
+// blocks per entry and occupancy 2 cost more than a kernel boundary).
+// MRHS_MERGE: 0 never, 1 (default) where faster, 2 always.
+bool merged_iteration(int32_t n, int32_t m, uint32_t flags, const AmgDev *amg)
+{
+    if ((flags & MRHS_MIXED) || amg)
+        return false;
+    const int mode = env_int("MRHS_MERGE", 1, 0, 2);
+    if (mode != 1)
+        return mode == 2;
+    return (m <= 4 && n <= 600000) || (m <= 8 && n <= 300000);
 }
 
 Layout layout(int32_t n, int32_t m, uint32_t flags, const AmgDev *amg = nullptr)
@@ -118,6 +138,10 @@ Layout layout(int32_t n, int32_t m, uint32_t flags, const AmgDev *amg = nullptr)
         L.rv64 = take_blk(2 * blk64 + kPairGap);
         L.p64 = take_blk(blk64);
         L.t64 = take_blk(blk64);
+        if (merged_iteration(n, m, flags, amg)) {
+            L.rv64b = take_blk(2 * blk64 + kPairGap);
+            L.p64b = take_blk(blk64);
+        }
         if (amg) {
             L.sv64 = take_blk(blk64);
             L.ph64 = take_blk(blk64);
@@ -225,6 +249,37 @@ struct Steps {
     static hipError_t f64_iterate(Ctx &c, int k)
     {
         const CsrView<double> Ah = view<double>(*c.A, true);
+        if (c.merged) {  // v = Ah p, then (t = Ah s, merged update and next v) k - 1 times, t = Ah s, update
+            MRHS_TRY((launch_gspmv<double, M>(Ah, OpSpmv1<double, M>{c.p, c.v, nullptr, c.ctl, c.kry64, c.ldp64},
+                                               c.rb64, c.s)));
+            for (int it = 0; it < k; ++it) {
+                MRHS_TRY((launch_gspmv<double, M>(
+                    Ah, OpSpmv2<double, M>{c.r, c.v, nullptr, c.t, c.ctl, c.kry64, c.ldp64}, c.rb64, c.s)));
+                if (it + 1 < k) {
+                    OpXRSigma<double, M> op{};
+                    op.y = c.X;
+                    op.r = c.r;
+                    op.v = c.v;
+                    op.t = c.t;
+                    op.p = c.p;
+                    op.r2 = c.r2;
+                    op.v2 = c.v2;
+                    op.p2 = c.p2;
+                    op.ctl = c.ctl;
+                    op.kry = c.kry64;
+                    op.ldp = c.ldp64;
+                    MRHS_TRY((launch_gspmv<double, M>(Ah, op, c.rb64, c.s)));
+                    std::swap(c.r, c.r2);
+                    std::swap(c.v, c.v2);
+                    std::swap(c.p, c.p2);
+                } else {
+                    MRHS_TRY((launch_stream<double, M>(
+                        c.n, OpXR<double, M>{c.X, c.r, c.p, c.v, c.t, nullptr, c.ctl, c.kry64, c.ldp64}, c.rb64,
+                        c.s)));
+                }
+            }
+            return hipSuccess;
+        }
         for (int it = 0; it < k; ++it) {
             MRHS_TRY((launch_gspmv<double, M>(Ah, OpSpmv1<double, M>{c.p, c.v, nullptr, c.ctl, c.kry64, c.ldp64},
                                                c.rb64, c.s)));
@@ -425,6 +480,12 @@ Engine::Engine(const mrhs_csr_s &A, int m, uint32_t flags, void *ws, const doubl
         c_.ldp64 = pair ? 2 * m_ : m_;
         c_.p = reinterpret_cast<double *>(base + L.p64);
         c_.t = reinterpret_cast<double *>(base + L.t64);
+        if (merged_iteration(A.n, m, flags, amg)) {
+            c_.merged = true;
+            c_.r2 = reinterpret_cast<double *>(base + L.rv64b);
+            c_.v2 = pair ? c_.r2 + m_ : c_.r2 + static_cast<size_t>(A.n) * m_ + kPairGap / sizeof(double);
+            c_.p2 = reinterpret_cast<double *>(base + L.p64b);
+        }
         if (amg) {
             AT_ = &amg_table(m);
             c_.amg = amg;

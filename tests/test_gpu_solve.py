@@ -289,3 +289,49 @@ def test_full_size_fp64_and_mixed(torch_cuda, mrhs, name, m):
     d = mean_free(Xmx) - mean_free(X64)
     err = np.linalg.norm(d, axis=0) / np.linalg.norm(mean_free(X64), axis=0)
     assert np.all(err <= 1e-5), err
+
+
+def _merge_env(flag):
+    import os
+    old = os.environ.get("MRHS_MERGE")
+    os.environ["MRHS_MERGE"] = flag
+    return old
+
+
+def _merge_restore(old):
+    import os
+    if old is None:
+        os.environ.pop("MRHS_MERGE", None)
+    else:
+        os.environ["MRHS_MERGE"] = old
+
+
+@pytest.mark.parametrize("m", [1, 3, 4, 8, 16])
+def test_merged_iteration(torch_cuda, mrhs, m):
+    """Two kernels per iteration (the x/r/p update fused with the next
+    iteration's v = A p, MRHS_MERGE=2) against three (MRHS_MERGE=0): the
+    iterate after k iterations matches the oracle's, converged solves meet
+    the tolerance and agree, iteration counts within 15 %."""
+    A = grids.channel7(24, 16, 20, beta=2.0)
+    B = mean_free(rng.rhs_block(A.n, m, 3300 + m))
+    out = {}
+    for flag in ("2", "0"):
+        old = _merge_env(flag)
+        try:
+            Xk, ik, sk = gpu_solve(mrhs, torch_cuda, A, B, tol=1e-14, maxit=3)
+            X, infos, st = gpu_solve(mrhs, torch_cuda, A, B, tol=1e-10, maxit=20000)
+        finally:
+            _merge_restore(old)
+        assert st == 0, infos
+        assert np.all(true_relres(A, X, B) <= 1e-10)
+        out[flag] = (Xk, X, infos)
+    Xo, io, _ = oracle.bicgstab(A, B, tol=1e-14, maxit=3, shadow_seed=SHADOW_SEED)
+    for flag in ("2", "0"):
+        Xk = out[flag][0]
+        for l in range(m):
+            err = np.linalg.norm(Xk[:, l] - Xo[:, l]) / np.linalg.norm(Xo[:, l])
+            assert err <= 1e-11, (flag, l, err)
+    d = np.linalg.norm(mean_free(out["2"][1]) - mean_free(out["0"][1]), axis=0)
+    assert np.all(d <= 1e-6 * np.linalg.norm(mean_free(out["0"][1]), axis=0)), d
+    for a, b in zip(out["2"][2], out["0"][2]):
+        assert abs(a["iters"] - b["iters"]) <= max(3, 0.15 * b["iters"]), (a, b)
