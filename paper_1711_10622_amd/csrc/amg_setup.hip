@@ -4,8 +4,11 @@
 // the hierarchy is a deterministic function of the matrix.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <numeric>
+#include <thread>
 #include <utility>
+#include <vector>
 
 #include "amg.h"
 
@@ -15,58 +18,135 @@ namespace mrhs {
 namespace amg {
 namespace {
 
+// Rows are independent in every per-row step below, so they run on host
+// threads over contiguous row ranges, each range's rows appended in order to
+// its own buffers and the buffers joined in range order: the result is the
+// sequential one, bit for bit.
+// (MRHS_AMG_THREADS fixes the count, for testing the split on small matrices)
+int host_threads(int64_t rows)
+{
+    if (const char *e = std::getenv("MRHS_AMG_THREADS"))
+        return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(std::atoi(e), std::max<int64_t>(rows, 1))));
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int64_t by_size = rows / 32768 + 1;
+    return static_cast<int>(std::min<int64_t>({static_cast<int64_t>(hw), 16, by_size}));
+}
+
+// fn(lo, hi, t) for T contiguous ranges of [0, n)
+template <class F>
+void parallel_ranges(int32_t n, int T, F &&fn)
+{
+    if (T <= 1) {
+        fn(0, n, 0);
+        return;
+    }
+    std::vector<std::thread> th;
+    th.reserve(static_cast<size_t>(T));
+    for (int t = 0; t < T; ++t) {
+        const int32_t lo = static_cast<int32_t>(static_cast<int64_t>(n) * t / T);
+        const int32_t hi = static_cast<int32_t>(static_cast<int64_t>(n) * (t + 1) / T);
+        th.emplace_back([&fn, lo, hi, t] { fn(lo, hi, t); });
+    }
+    for (auto &x : th)
+        x.join();
+}
+
+// A CRS matrix of nr rows built by row(i, ci, va, scratch), which appends
+// row i's entries; MakeScratch() gives each thread its own scratch;
+// reserve(lo, hi) estimates the entries of rows lo..hi-1.
+template <class MakeScratch, class Row, class Reserve>
+HostCsr build_rows(int32_t nr, int32_t nc, MakeScratch make_scratch, Row row, Reserve reserve)
+{
+    const int T = host_threads(nr);
+    std::vector<std::vector<int32_t>> cis(T), lens(T);
+    std::vector<std::vector<double>> vas(T);
+    parallel_ranges(nr, T, [&](int32_t lo, int32_t hi, int t) {
+        auto scratch = make_scratch();
+        std::vector<int32_t> &ci = cis[t], &len = lens[t];
+        std::vector<double> &va = vas[t];
+        len.reserve(static_cast<size_t>(hi - lo));
+        const size_t est = reserve(lo, hi);
+        ci.reserve(est);
+        va.reserve(est);
+        for (int32_t i = lo; i < hi; ++i) {
+            const size_t before = ci.size();
+            row(i, ci, va, scratch);
+            len.push_back(static_cast<int32_t>(ci.size() - before));
+        }
+    });
+    HostCsr C;
+    C.nr = nr;
+    C.nc = nc;
+    C.rp.assign(static_cast<size_t>(nr) + 1, 0);
+    size_t total = 0;
+    for (int t = 0; t < T; ++t)
+        total += cis[t].size();
+    C.ci.reserve(total);
+    C.va.reserve(total);
+    int32_t i = 0;
+    for (int t = 0; t < T; ++t) {
+        for (int32_t l : lens[t]) {
+            C.rp[i + 1] = C.rp[i] + l;
+            ++i;
+        }
+        C.ci.insert(C.ci.end(), cis[t].begin(), cis[t].end());
+        C.va.insert(C.va.end(), vas[t].begin(), vas[t].end());
+        std::vector<int32_t>().swap(cis[t]);
+        std::vector<double>().swap(vas[t]);
+    }
+    return C;
+}
+
+struct NoScratch {};
+
 // Rows sorted by column, repeated columns summed in storage order.
 HostCsr canonical(int32_t n, const int32_t *rp, const int32_t *ci, const double *va)
 {
-    HostCsr A;
-    A.nr = A.nc = n;
-    A.rp.assign(static_cast<size_t>(n) + 1, 0);
-    A.ci.reserve(static_cast<size_t>(rp[n]));
-    A.va.reserve(static_cast<size_t>(rp[n]));
-    std::vector<std::pair<int32_t, int32_t>> row;  // (column, storage index)
-    for (int32_t i = 0; i < n; ++i) {
-        row.clear();
-        for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
-            row.emplace_back(ci[k], k);
-        std::sort(row.begin(), row.end());
-        for (size_t q = 0; q < row.size(); ++q) {
-            if (q > 0 && row[q].first == row[q - 1].first) {
-                A.va.back() = A.va.back() + va[row[q].second];
-            } else {
-                A.ci.push_back(row[q].first);
-                A.va.push_back(va[row[q].second]);
-            }
-        }
-        A.rp[i + 1] = static_cast<int32_t>(A.ci.size());
-    }
-    return A;
+    using Row = std::vector<std::pair<int32_t, int32_t>>;  // (column, storage index)
+    return build_rows(n, n, [] { return Row(); },
+                      [&](int32_t i, std::vector<int32_t> &oci, std::vector<double> &ova, Row &row) {
+                          row.clear();
+                          for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
+                              row.emplace_back(ci[k], k);
+                          std::sort(row.begin(), row.end());
+                          for (size_t q = 0; q < row.size(); ++q) {
+                              if (q > 0 && row[q].first == row[q - 1].first) {
+                                  ova.back() = ova.back() + va[row[q].second];
+                              } else {
+                                  oci.push_back(row[q].first);
+                                  ova.push_back(va[row[q].second]);
+                              }
+                          }
+                      },
+                      [&](int32_t lo, int32_t hi) { return static_cast<size_t>(rp[hi] - rp[lo]); });
 }
 
 // Strong connections of every row, as a CRS pattern (columns increasing).
 void strength(const HostCsr &A, double theta, std::vector<int32_t> &srp, std::vector<int32_t> &sci)
 {
-    srp.assign(static_cast<size_t>(A.nr) + 1, 0);
-    sci.clear();
-    for (int32_t i = 0; i < A.nr; ++i) {
-        double mx = 0.0;
-        bool have = false;
-        for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
-            if (A.ci[k] == i)
-                continue;
-            const double v = -A.va[k];
-            if (!have || v > mx) {
-                mx = v;
-                have = true;
-            }
-        }
-        if (have && mx > 0.0) {
-            const double thr = theta * mx;
-            for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
-                if (A.ci[k] != i && -A.va[k] >= thr)
-                    sci.push_back(A.ci[k]);
-        }
-        srp[i + 1] = static_cast<int32_t>(sci.size());
-    }
+    HostCsr S = build_rows(A.nr, A.nc, [] { return NoScratch{}; },
+                           [&](int32_t i, std::vector<int32_t> &oci, std::vector<double> &, NoScratch &) {
+                               double mx = 0.0;
+                               bool have = false;
+                               for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+                                   if (A.ci[k] == i)
+                                       continue;
+                                   const double v = -A.va[k];
+                                   if (!have || v > mx) {
+                                       mx = v;
+                                       have = true;
+                                   }
+                               }
+                               if (have && mx > 0.0) {
+                                   const double thr = theta * mx;
+                                   for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
+                                       if (A.ci[k] != i && -A.va[k] >= thr)
+                                           oci.push_back(A.ci[k]);
+                               }
+                           },
+                           [&](int32_t lo, int32_t hi) { return static_cast<size_t>(A.rp[hi] - A.rp[lo]); });
+    srp.swap(S.rp);
+    sci.swap(S.ci);
 }
 
 // Max-heap over rows keyed by (measure, -row) with positions, so a row's
@@ -218,50 +298,45 @@ HostCsr interpolation(const HostCsr &A, const std::vector<int32_t> &srp, const s
     for (int32_t i = 0; i < n; ++i)
         if (cf[i])
             cidx[i] = nc++;
-    HostCsr P;
-    P.nr = n;
-    P.nc = nc;
-    P.rp.assign(static_cast<size_t>(n) + 1, 0);
-    std::vector<int32_t> mark(n, -1);  // mark[j] == i: j is a strong C neighbour of i
-    for (int32_t i = 0; i < n; ++i) {
-        if (cf[i]) {
-            P.ci.push_back(cidx[i]);
-            P.va.push_back(1.0);
-            P.rp[i + 1] = static_cast<int32_t>(P.ci.size());
-            continue;
-        }
-        bool any = false;
-        for (int32_t k = srp[i]; k < srp[i + 1]; ++k)
-            if (cf[sci[k]]) {
-                mark[sci[k]] = i;
-                any = true;
-            }
-        double diag = 0.0, neg_n = 0.0, pos_n = 0.0, neg_p = 0.0;
-        for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
-            const int32_t j = A.ci[k];
-            const double a = A.va[k];
-            if (j == i) {
-                diag += a;
-            } else if (a < 0.0) {
-                neg_n += a;
-                if (mark[j] == i)
-                    neg_p += a;
-            } else if (a > 0.0) {
-                pos_n += a;
-            }
-        }
-        if (any && neg_p != 0.0) {
-            const double alpha = neg_n / neg_p;
-            const double d = diag + pos_n;
-            for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
-                if (mark[A.ci[k]] == i) {
-                    P.ci.push_back(cidx[A.ci[k]]);
-                    P.va.push_back(-(alpha * A.va[k]) / d);
-                }
-        }
-        P.rp[i + 1] = static_cast<int32_t>(P.ci.size());
-    }
-    return P;
+    // mark[j] == i: j is a strong C neighbour of i
+    return build_rows(n, nc, [n] { return std::vector<int32_t>(n, -1); },
+                      [&](int32_t i, std::vector<int32_t> &oci, std::vector<double> &ova, std::vector<int32_t> &mark) {
+                          if (cf[i]) {
+                              oci.push_back(cidx[i]);
+                              ova.push_back(1.0);
+                              return;
+                          }
+                          bool any = false;
+                          for (int32_t k = srp[i]; k < srp[i + 1]; ++k)
+                              if (cf[sci[k]]) {
+                                  mark[sci[k]] = i;
+                                  any = true;
+                              }
+                          double diag = 0.0, neg_n = 0.0, pos_n = 0.0, neg_p = 0.0;
+                          for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+                              const int32_t j = A.ci[k];
+                              const double a = A.va[k];
+                              if (j == i) {
+                                  diag += a;
+                              } else if (a < 0.0) {
+                                  neg_n += a;
+                                  if (mark[j] == i)
+                                      neg_p += a;
+                              } else if (a > 0.0) {
+                                  pos_n += a;
+                              }
+                          }
+                          if (any && neg_p != 0.0) {
+                              const double alpha = neg_n / neg_p;
+                              const double d = diag + pos_n;
+                              for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
+                                  if (mark[A.ci[k]] == i) {
+                                      oci.push_back(cidx[A.ci[k]]);
+                                      ova.push_back(-(alpha * A.va[k]) / d);
+                                  }
+                          }
+                      },
+                      [&](int32_t lo, int32_t hi) { return static_cast<size_t>(srp[hi] - srp[lo] + (hi - lo)); });
 }
 
 HostCsr transpose(const HostCsr &P)
@@ -286,51 +361,103 @@ HostCsr transpose(const HostCsr &P)
 }
 
 // L R: row i sums, over L's row i in storage order, each entry times R's
-// row in storage order; result columns increasing.
+// row in storage order; result columns increasing.  A row's distinct columns
+// are collected in a short list searched linearly (rows of these operators
+// have tens of entries, and the list stays in cache where column-indexed
+// arrays of the full width would not); a row with more than kShort distinct
+// columns moves to the full-width arrays.  Either way each column's terms
+// are added in the order they are generated.
+struct MulScratch {
+    std::vector<double> acc;
+    std::vector<int32_t> seen, cols;
+    std::vector<std::pair<int32_t, double>> small;
+};
+
 HostCsr multiply(const HostCsr &L, const HostCsr &Rm)
 {
-    HostCsr C;
-    C.nr = L.nr;
-    C.nc = Rm.nc;
-    C.rp.assign(static_cast<size_t>(L.nr) + 1, 0);
-    std::vector<double> acc(Rm.nc, 0.0);
-    std::vector<int32_t> seen(Rm.nc, -1), cols;
-    for (int32_t i = 0; i < L.nr; ++i) {
-        cols.clear();
-        for (int32_t k = L.rp[i]; k < L.rp[i + 1]; ++k) {
-            const double a = L.va[k];
-            const int32_t l = L.ci[k];
-            for (int32_t q = Rm.rp[l]; q < Rm.rp[l + 1]; ++q) {
-                const int32_t j = Rm.ci[q];
-                const double t = a * Rm.va[q];
-                if (seen[j] != i) {
-                    seen[j] = i;
-                    acc[j] = t;
-                    cols.push_back(j);
-                } else {
-                    acc[j] = acc[j] + t;
+    constexpr size_t kShort = 64;
+    const int32_t nc = Rm.nc;
+    return build_rows(
+        L.nr, nc, [] { return MulScratch{}; },
+        [&](int32_t i, std::vector<int32_t> &oci, std::vector<double> &ova, MulScratch &w) {
+            w.small.clear();
+            bool wide = false;
+            w.cols.clear();
+            for (int32_t k = L.rp[i]; k < L.rp[i + 1]; ++k) {
+                const double a = L.va[k];
+                const int32_t l = L.ci[k];
+                for (int32_t q = Rm.rp[l]; q < Rm.rp[l + 1]; ++q) {
+                    const int32_t j = Rm.ci[q];
+                    const double t = a * Rm.va[q];
+                    if (!wide) {
+                        size_t e = 0;
+                        while (e < w.small.size() && w.small[e].first != j)
+                            ++e;
+                        if (e < w.small.size()) {
+                            w.small[e].second = w.small[e].second + t;
+                            continue;
+                        }
+                        if (w.small.size() < kShort) {
+                            w.small.emplace_back(j, t);
+                            continue;
+                        }
+                        // too many columns: continue in the full-width arrays
+                        if (w.acc.empty()) {
+                            w.acc.assign(nc, 0.0);
+                            w.seen.assign(nc, -1);
+                        }
+                        for (const auto &e2 : w.small) {
+                            w.seen[e2.first] = i;
+                            w.acc[e2.first] = e2.second;
+                            w.cols.push_back(e2.first);
+                        }
+                        wide = true;
+                    }
+                    if (w.seen[j] != i) {
+                        w.seen[j] = i;
+                        w.acc[j] = t;
+                        w.cols.push_back(j);
+                    } else {
+                        w.acc[j] = w.acc[j] + t;
+                    }
                 }
             }
-        }
-        std::sort(cols.begin(), cols.end());
-        for (int32_t j : cols) {
-            C.ci.push_back(j);
-            C.va.push_back(acc[j]);
-        }
-        C.rp[i + 1] = static_cast<int32_t>(C.ci.size());
-    }
-    return C;
+            if (!wide) {
+                std::sort(w.small.begin(), w.small.end(),
+                          [](const std::pair<int32_t, double> &x, const std::pair<int32_t, double> &y) {
+                              return x.first < y.first;
+                          });
+                for (const auto &e : w.small) {
+                    oci.push_back(e.first);
+                    ova.push_back(e.second);
+                }
+                return;
+            }
+            std::sort(w.cols.begin(), w.cols.end());
+            for (int32_t j : w.cols) {
+                oci.push_back(j);
+                ova.push_back(w.acc[j]);
+            }
+        },
+        [&](int32_t lo, int32_t hi) {
+            // about the row count times L's mean row length times Rm's
+            const double ln = static_cast<double>(L.rp[hi] - L.rp[lo]);
+            const double rn = Rm.nr ? static_cast<double>(Rm.rp[Rm.nr]) / Rm.nr : 0.0;
+            return static_cast<size_t>(ln * std::min(rn, 4.0));
+        });
 }
 
 std::vector<double> l1_inverse(const HostCsr &A)
 {
     std::vector<double> out(A.nr);
-    for (int32_t i = 0; i < A.nr; ++i) {
-        double s = 0.0;
-        for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
-            s += std::fabs(A.va[k]);
-        out[i] = s > 0.0 ? 1.0 / s : 0.0;
-    }
+    parallel_ranges(A.nr, host_threads(A.nr), [&](int32_t lo, int32_t hi, int) {
+        for (int32_t i = lo; i < hi; ++i) {
+            double s = 0.0;
+            for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
+                s += std::fabs(A.va[k]);
+            out[i] = s > 0.0 ? 1.0 / s : 0.0;
+        }
+    });
     return out;
 }
 

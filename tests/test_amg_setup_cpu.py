@@ -25,7 +25,7 @@ def driver(tmp_path_factory):
     if cxx is None:
         pytest.skip("g++ not available")
     exe = str(tmp_path_factory.mktemp("amg") / "amg_setup_driver")
-    cmd = [cxx, "-std=c++17", "-O2", "-ffp-contract=off", "-Wno-unknown-pragmas", f"-I{CSRC}",
+    cmd = [cxx, "-std=c++17", "-O2", "-pthread", "-ffp-contract=off", "-Wno-unknown-pragmas", f"-I{CSRC}",
            "-x", "c++", os.path.join(CSRC, "amg_setup.hip"), "-x", "none",
            os.path.join(ROOT, "tests", "amg_setup_driver.cpp"), "-o", exe]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -33,7 +33,7 @@ def driver(tmp_path_factory):
     return exe
 
 
-def run_driver(exe, tmp, A, ns):
+def run_driver(exe, tmp, A, ns, threads=None):
     fin, fout = os.path.join(tmp, "in.bin"), os.path.join(tmp, "out.bin")
     with open(fin, "wb") as f:
         np.array([A.n], np.int32).tofile(f)
@@ -42,7 +42,10 @@ def run_driver(exe, tmp, A, ns):
         np.asarray(A.row_ptr, np.int32).tofile(f)
         np.asarray(A.col, np.int32).tofile(f)
         np.asarray(A.val, np.float64).tofile(f)
-    r = subprocess.run([exe, fin, fout], capture_output=True, text=True)
+    env = dict(os.environ)
+    if threads is not None:
+        env["MRHS_AMG_THREADS"] = str(threads)
+    r = subprocess.run([exe, fin, fout], capture_output=True, text=True, env=env)
     assert r.returncode == 0, r.stderr
     buf = open(fout, "rb").read()
     pos = 0
@@ -92,10 +95,13 @@ def cases():
     yield "dir9_dups", grids.CSRMatrix(D.n, rp, col2[o2].astype(np.int32), val2[o2]), False
 
 
+@pytest.mark.parametrize("threads", [None, 3])
 @pytest.mark.parametrize("case", list(range(5)))
-def test_library_hierarchy_equals_oracle(driver, tmp_path, case):
+def test_library_hierarchy_equals_oracle(driver, tmp_path, case, threads):
+    """Also with every per-row step split over 3 host threads (uneven row
+    ranges): the joined result must be the sequential one, bit for bit."""
     name, A, ns = list(cases())[case]
-    levels, cinv = run_driver(driver, str(tmp_path), A, ns)
+    levels, cinv = run_driver(driver, str(tmp_path), A, ns, threads)
     H = amg.setup(A.n, A.row_ptr, A.col, A.val, nullspace_const=ns)
     assert len(levels) == len(H.levels), name
     for l, (got, ref) in enumerate(zip(levels, H.levels)):
