@@ -149,3 +149,26 @@ def test_server_with_renumbered_matrix(env, cube, mixed):
         assert np.all(true_relres(A, X, B) <= 1e-10)
     srv.close()
     M.close()
+
+
+def test_degenerate_matrices(env):
+    """Renumbering an empty matrix, a single row and a diagonal matrix (every
+    row its own component): creation, products and solves behave as without
+    renumbering."""
+    torch, p = env
+    from workloads.grids import CSRMatrix
+    E = CSRMatrix(0, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    Me = p.CsrMatrix.from_csr(E, reorder=True)
+    Me.close()
+    for n in (1, 37):
+        D = CSRMatrix(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32),
+                      np.linspace(1.0, 2.0, n))
+        assert np.array_equal(np.sort(p.reorder_permutation(D)), np.arange(n))
+        B = rng.rhs_block(n, 3, 88)
+        M = p.CsrMatrix.from_csr(D, reorder=True)
+        Y = p.gspmv(M, cuda(torch, B)).cpu().numpy()
+        assert np.array_equal(Y, D.val[:, None] * B)
+        X, infos, st = M.solve(cuda(torch, B), tol=1e-12, maxit=10)
+        assert st == 0, infos
+        assert np.allclose(X.cpu().numpy(), B / D.val[:, None], rtol=1e-12, atol=0)
+        M.close()
