@@ -280,6 +280,20 @@ def gspmv_locality(torch, A, line=256):
     return gspmv_sweep(torch, L, [8, 16], ("f64", "f32"), reps=20)
 
 
+def gspmv_march(torch, A):
+    """GSpMV on A as a plane march (MRHS_MARCH=1: the gathered rows of three
+    planes kept in LDS windows), beside the tiled product of the main sweep."""
+    old = os.environ.get("MRHS_MARCH")
+    os.environ["MRHS_MARCH"] = "1"
+    try:
+        return gspmv_sweep(torch, A, [1, 8, 16], ("f64", "f32"), reps=20)
+    finally:
+        if old is None:
+            os.environ.pop("MRHS_MARCH", None)
+        else:
+            os.environ["MRHS_MARCH"] = old
+
+
 def gspmv_cube(torch):
     """GSpMV on the relabelled cube channel as generated and renumbered by
     reverse Cuthill-McKee (the permutation MRHS_CSR_REORDER applies)."""
@@ -982,6 +996,7 @@ def main():
         log(f"amg: {extra['amg']}")
         extra["gspmv_chan256"] = gspmv_sweep(torch, A, list(range(1, 17)), ("f64", "f32"), reps=20)
         extra["gspmv_chan256_local_gathers"] = gspmv_locality(torch, A)
+        extra["gspmv_chan256_plane_march"] = gspmv_march(torch, A)
         extra["gspmv_cube192"] = gspmv_cube(torch)
         log("gspmv sweeps done")
         legs, A2, Bh2, Xs2 = chan128_legs(torch, 2)
