@@ -225,34 +225,13 @@ struct VecU {
 // elements apart (ld = M, or 2M for a half of an interleaved pair of blocks).
 // The last lane of a row whose width VW does not divide reads its TAIL
 // elements one by one (the rest of v is zero), so no access leaves the row.
-// VW elements at p with one nontemporal vector load.
-template <typename T, int VW>
-__device__ __forceinline__ void load_nt(const T *p, T *v)
-{
-    if constexpr (VW == 1) {
-        v[0] = __builtin_nontemporal_load(p);
-    } else {
-        typedef T vt __attribute__((ext_vector_type(VW)));
-        const vt t = __builtin_nontemporal_load(reinterpret_cast<const vt *>(p));
-#pragma unroll
-        for (int q = 0; q < VW; ++q)
-            v[q] = t[q];
-    }
-}
-
-// NT: a streaming (nontemporal) load, for rows that no other lane of the
-// pass reads again; gathered rows and a row's own entries that neighbouring
-// rows gather use the default, cached load.
-template <typename T, int M, bool NT = false>
+template <typename T, int M>
 __device__ __forceinline__ void ld(const T *base, int32_t row, int g, T *v, int32_t ld = M)
 {
     using S = Shape<T, M>;
     const T *p = base + static_cast<size_t>(row) * ld + g * S::VW;
     if constexpr (S::TAIL == S::VW) {
-        if constexpr (NT)
-            load_nt<T, S::VW>(p, v);
-        else
-            Vec<T, S::VW>::load(p, v);
+        Vec<T, S::VW>::load(p, v);
     } else if (g == S::G - 1) {
 #pragma unroll
         for (int q = 0; q < S::VW; ++q)

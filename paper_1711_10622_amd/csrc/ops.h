@@ -276,6 +276,7 @@ struct OpResid {
     __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, const double *sum,
                                         Acc<double, S::VW, NDOT> &acc, const Pre &pr) const
     {
+        const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         const double *b = pr.b;
         double r[S::VW];
         const bool restart = kind == RES_SETUP || kind == RES_CHECK;
@@ -310,7 +311,6 @@ struct OpResid {
         } else {
             // only the columns this kind owns are written
             const size_t orow = static_cast<size_t>(i) * (rld ? rld : M) + g * S::VW;
-            const size_t o = static_cast<size_t>(i) * M + g * S::VW;
 #pragma unroll
             for (int v = 0; v < S::VW; ++v) {
                 if (!ln.act[v])
@@ -478,6 +478,7 @@ struct OpSpmv1 {
     __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, const T *sum,
                                         Acc<T, S::VW, NDOT> &acc) const
     {
+        const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         T h[S::VW];
         shadow_row<T, M>(sgn, i, g, h);
         st<T, M>(v, i, g, sum, ldp);
@@ -673,15 +674,13 @@ struct OpXR {
     }
     __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, Acc<T, S::VW, NDOT> &acc) const
     {
+        const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         T yy[S::VW], rr[S::VW], pp[S::VW], vv[S::VW], tt[S::VW];
-        // every element is read once per pass: streaming loads (on the
-        // 12.6M-row channel, binary64: m = 16 2114 -> 2060 us, m = 8 1053 ->
-        // 995 us per launch)
-        ld<T, M, true>(y, i, g, yy);
-        ld<T, M, true>(r, i, g, rr, ldp);
-        ld<T, M, true>(p, i, g, pp);
-        ld<T, M, true>(v, i, g, vv, ldp);
-        ld<T, M, true>(t, i, g, tt);
+        ld<T, M>(y, i, g, yy);
+        ld<T, M>(r, i, g, rr, ldp);
+        ld<T, M>(p, i, g, pp);
+        ld<T, M>(v, i, g, vv, ldp);
+        ld<T, M>(t, i, g, tt);
         T hh[S::VW];
         shadow_row<T, M>(sgn, i, g, hh);
 #pragma unroll
@@ -868,6 +867,7 @@ struct OpRestart {
     }
     __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, Acc<T, S::VW, NDOT> &) const
     {
+        const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         T a[S::VW], b[S::VW], pp[S::VW];
         ld<T, M>(rt, i, g, a);
         ld<T, M>(r, i, g, b, ldp);
@@ -927,6 +927,7 @@ struct OpScale {
     }
     __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, Acc<double, S::VW, NDOT> &) const
     {
+        const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         double a[S::VW];
         ld<double, M>(x, i, g, a);
         const double di = (kind == SC_IN) ? diag[i] : (kind == SC_OUT ? dinv[i] : 1.0);
@@ -1027,6 +1028,7 @@ struct OpCast {
     }
     __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, Acc<float, S::VW, NDOT> &acc) const
     {
+        const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         float a[S::VW], z[S::VW], pp[S::VW];
         ld<float, M>(r, i, g, a, ldp);
         ld<float, M>(y, i, g, z);
