@@ -63,11 +63,14 @@ def log(msg):
     print(f"# {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_bytes(name, n, nnz, m, S):
+def kernel_bytes(name, n, nnz, m, S, mat=None):
     """Algorithmic HBM bytes of one launch of a library kernel with all m
     columns active: each block (n x m, S bytes/element) read or written once,
-    the matrix (int32 row offsets and columns, S-byte values) read once."""
-    mat = 4 * (n + 1) + (4 + S) * nnz
+    the matrix read once: ``mat`` bytes (csr_stream_bytes: row offsets plus
+    2-byte codes in the dictionary form), by default the plain arrays (int32
+    row offsets and columns, S-byte values)."""
+    if mat is None:
+        mat = 4 * (n + 1) + (4 + S) * nnz
     blk = S * m * n
     # the binary64 shadow residual is generated in the kernels; binary32
     # inner solves read its sign bits, one byte per lane of a row
@@ -84,8 +87,47 @@ def kernel_bytes(name, n, nnz, m, S):
     return table.get(name)
 
 
+_MAT_CACHE = {}
+
+
+def matrix_stream_bytes(A, S, scaled):
+    """Bytes a product streams from A's arrays, by the rule csr_create uses
+    for the dictionary form (at most 32 distinct column offsets; at most 2048
+    distinct values in the value array: A or A D^-1, binary64 or its binary32
+    rounding), for offline summaries; runs on a device use
+    CsrMatrix.stream_bytes."""
+    import numpy as np
+    key = (id(A), S, bool(scaled))
+    if key not in _MAT_CACHE or _MAT_CACHE[key][0] is not A:
+        plain = 4 * (A.n + 1) + (4 + S) * A.nnz
+        rows = np.repeat(np.arange(A.n, dtype=np.int64), np.diff(A.row_ptr))
+        off = A.col.astype(np.int64) - rows
+        ok = np.unique(off).size <= 32
+        if ok:
+            v = A.val
+            if scaled:
+                d = np.zeros(A.n)
+                np.add.at(d, rows[off == 0], A.val[off == 0])
+                dc = d[A.col]
+                v = np.where(dc != 0.0, A.val / np.where(dc != 0.0, dc, 1.0), 0.0)
+            if S == 4:
+                v = v.astype(np.float32)
+            ok = np.unique(v.view(np.uint64 if S == 8 else np.uint32)).size <= 2048
+        # (the entry keeps A alive, so its id is not reused while cached)
+        _MAT_CACHE[key] = (A, 4 * (A.n + 1) + 2 * A.nnz if ok else plain)
+    return _MAT_CACHE[key][1]
+
+
 def next_pow2(x):
     return 1 if x <= 1 else 2 * next_pow2((x + 1) // 2)
+
+
+def summary_mat(A, name, S):
+    """Matrix bytes of a product kernel in an offline summary (gspmv reads A,
+    the solvers' products A D^-1)."""
+    if name not in ("gspmv", "spmv_sigma", "spmv_omega"):
+        return None
+    return matrix_stream_bytes(A, S, scaled=name != "gspmv")
 
 
 def kernel_sources_digest():
@@ -116,7 +158,9 @@ def stored_traffic(kernel):
     return None
 
 
-def dominant_kernel(trace, n, nnz):
+def dominant_kernel(trace, n, nnz, mats=None):
+    """The kernel class with the largest estimated total time; ``mats``:
+    matrix bytes per product by element size (the solvers' scaled matrix)."""
     best = None
     for key, st in trace.items():
         name, dt, mtag, _ = key.split("/")
@@ -125,7 +169,7 @@ def dominant_kernel(trace, n, nnz):
             best = (key, st, name, 8 if dt == "f64" else 4, int(mtag[1:]), share)
     key, st, name, S, m, _ = best
     avg_ms = st["total_ms"] / st["launches"]
-    byt = kernel_bytes(name, n, nnz, m, S)
+    byt = kernel_bytes(name, n, nnz, m, S, (mats or {}).get(S))
     achieved = byt / (avg_ms * 1e-3) / 1e9 if byt else None
     return {"kernel": key, "class": "/".join(key.split("/")[:3]), "launches": st["seen"], "timed": st["launches"],
             "avg_us": avg_ms * 1e3, "bytes_per_launch": byt, "achieved": achieved}
@@ -255,7 +299,7 @@ def gspmv_sweep(torch, A, ms, dtypes, flush=False, reps=50):
             for tag, between in runs.items():
                 us = event_times_us(torch, lambda: M.gspmv(X, out=Y), reps, 5, between)
                 med = float(np.median(us))
-                byt = est.traffic_compulsory(A.n, A.nnz, m, V=S, S=S)
+                byt = M.stream_bytes(dt) + 2 * S * m * A.n
                 gbs = byt / (med * 1e-6) / 1e9
                 rec[tag] = {"us_median": round(med, 2), "us_p10": round(float(np.percentile(us, 10)), 2),
                             "us_p90": round(float(np.percentile(us, 90)), 2), "GBps": round(gbs, 1),
@@ -716,7 +760,8 @@ def summarize_profiles(out, workload, m):
         for r in st:
             cls = kernel_class(r["Name"])
             parts = cls.split("/")
-            byt = kernel_bytes(parts[0], A.n, A.nnz, int(parts[2][1:]), 8 if parts[1] == "f64" else 4) \
+            byt = kernel_bytes(parts[0], A.n, A.nnz, int(parts[2][1:]), 8 if parts[1] == "f64" else 4,
+                               summary_mat(A, parts[0], 8 if parts[1] == "f64" else 4)) \
                 if len(parts) == 3 else None
             avg = float(r["AverageNs"]) / 1e3
             lines.append(f"| {cls} | {r['Calls']} | {avg:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
@@ -746,7 +791,8 @@ def summarize_profiles(out, workload, m):
             w = sum(d["WRITE_SIZE"]) / len(d["WRITE_SIZE"])
             hbm = (f * cal["FETCH_SIZE"] + w * cal["WRITE_SIZE"]) * 1024
             name, dt, mt = cls.split("/")
-            byt = kernel_bytes(name, A.n, A.nnz, int(mt[1:]), 8 if dt == "f64" else 4)
+            S = 8 if dt == "f64" else 4
+            byt = kernel_bytes(name, A.n, A.nnz, int(mt[1:]), S, summary_mat(A, name, S))
             ratio = f"{hbm / byt:.3f}" if byt else ""
             lines.append(f"| {cls} | {len(d['FETCH_SIZE'])} | {f:.0f} | {w:.0f} | {hbm / 1e6:.1f} | "
                          f"{byt / 1e6 if byt else '':{'.1f' if byt else ''}} | {ratio} |")
@@ -941,7 +987,9 @@ def main():
     if args.warmup:
         timed_solves(torch, M, B, X, ws, args.warmup, label="warm-up")
     step_s, infos, trace = timed_solves(torch, M, B, X, ws, args.steps, trace=True, label="timed")
-    dom = dominant_kernel(trace, A.n, A.nnz)
+    mats = {8: M.stream_bytes("f64", True), 4: M.stream_bytes("f32", True)}
+    log(f"matrix bytes per product: binary64 {mats[8]}, binary32 {mats[4]}")
+    dom = dominant_kernel(trace, A.n, A.nnz, mats)
     iters = max(i["iters"] for i in infos)
     log(f"step {step_s * 1e3:.2f} ms, {iters} iterations, dominant {dom['kernel']} {dom['avg_us']:.1f} us")
     extra = {"iters": [i["iters"] for i in infos], "max_relres": max(i["relres"] for i in infos),

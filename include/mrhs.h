@@ -111,6 +111,16 @@ const char *mrhs_version(void);
  * decreasing row_ptr, row_ptr[n] != nnz, a column outside [0, n), or a
  * non-finite value.  A zero diagonal is accepted here and rejected by the
  * solvers.
+ *
+ * Dictionary form: when the solvers' matrix has at most 32 distinct column
+ * offsets col - row (a structured grid's stencil) the handle also stores, for
+ * each value array with at most 2048 distinct values, one 16-bit code per
+ * entry (offset index and value index) and the two tables; the tiled products
+ * then stream 2 bytes per entry instead of 4 + 8 (binary64) or 4 + 4
+ * (binary32) and sum exactly the same values in the same order.  Building it
+ * reads the derived arrays back and takes one pass over the entries per
+ * array; the environment variable MRHS_CSR_DICT=0 turns it off.  See
+ * csr_stream_bytes.
  */
 mrhs_status csr_create(int32_t n, int64_t nnz, const int32_t *row_ptr,
                        const int32_t *col_idx, const double *val,
@@ -134,6 +144,17 @@ mrhs_status csr_destroy(mrhs_csr A);
 
 /* Size of the matrix and the device bytes the handle holds. */
 mrhs_status csr_info(mrhs_csr A, int32_t *n, int64_t *nnz, size_t *device_bytes);
+
+/*
+ * Bytes one tiled product streams from the matrix arrays (Section 2.3: the
+ * matrix part of the GSpMV memory traffic): the row offsets plus, per entry,
+ * a 2-byte code in the dictionary form or a 4-byte column index and a value
+ * otherwise.  dtype MRHS_F64 or MRHS_F32; scaled != 0 for the solvers'
+ * column-scaled matrix A D^-1, 0 for A.  gspmv of a handle made with
+ * MRHS_CSR_REORDER reads the caller's arrays in plain form.  EINVAL: NULL
+ * handle or output, unknown dtype.
+ */
+mrhs_status csr_stream_bytes(mrhs_csr A, int32_t dtype, int32_t scaled, int64_t *bytes);
 
 /*
  * Y = A X (Section 2.3, Figure 1) for device blocks X, Y of m binary64

@@ -26,7 +26,8 @@ NOALLOC_SCRATCH_BYTES = 64 << 20  # MRHS_NOALLOC_SCRATCH_BYTES
 
 # every symbol include/mrhs.h declares
 EXPORTS = (
-    "mrhs_last_error", "mrhs_version", "csr_create", "csr_destroy", "csr_info", "csr_reorder_permutation",
+    "mrhs_last_error", "mrhs_version", "csr_create", "csr_destroy", "csr_info", "csr_stream_bytes",
+    "csr_reorder_permutation",
     "gspmv", "gspmv_ex",
     "block_bicgstab", "block_bicgstab_ex", "block_bicgstab_workspace_size", "block_bicgstab_noalloc",
     "solve_server_create", "solve_server_register", "solve_server_submit", "solve_server_poll",
@@ -78,6 +79,7 @@ def _declare(lib):
         "csr_create": [i32, i64, vp, vp, vp, u32, c.POINTER(vp)],
         "csr_destroy": [vp],
         "csr_info": [vp, c.POINTER(i32), c.POINTER(i64), c.POINTER(sz)],
+        "csr_stream_bytes": [vp, i32, i32, c.POINTER(i64)],
         "csr_reorder_permutation": [i32, vp, vp, vp],
         "gspmv": [vp, vp, vp, i32],
         "gspmv_ex": [vp, i32, vp, vp, i32, vp],

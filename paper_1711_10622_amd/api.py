@@ -76,6 +76,14 @@ class CsrMatrix:
         _lib.check(self._lib.csr_info(self._h, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(b)))
         return int(b.value)
 
+    def stream_bytes(self, dtype="f64", scaled=False) -> int:
+        """Bytes one product streams from the matrix arrays (row offsets plus
+        2 bytes per entry in the dictionary form, else index and value)."""
+        b = ctypes.c_int64()
+        dt = _lib.F64 if dtype == "f64" else _lib.F32
+        _lib.check(self._lib.csr_stream_bytes(self._h, dt, 1 if scaled else 0, ctypes.byref(b)))
+        return int(b.value)
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             self._lib.csr_destroy(self._h)

@@ -356,6 +356,15 @@ __device__ __forceinline__ int32_t plane_chunks(int32_t P, int32_t reach, int32_
 }
 
 // ---- matrix view ----------------------------------------------------------------
+// Dictionary form of a matrix whose entries take few distinct column offsets
+// (col - row) and few distinct values, as the finite-difference operators of
+// a structured grid do: entry j is one 16-bit code, its column
+// row + otab[code & omask] and its value vtab[code >> ob], both exact, so a
+// product sums the same values in the same order as from the plain arrays
+// and reads 2 bytes per entry instead of 4 + sizeof(T).
+constexpr int kDictOffs = 32;    // at most this many distinct offsets
+constexpr int kDictVals = 2048;  // and this many distinct values per array
+
 template <typename T>
 struct CsrView {
     const int32_t *__restrict__ rp;
@@ -364,6 +373,12 @@ struct CsrView {
     int32_t n;
     int32_t reach;  // median over rows of the largest forward column offset
     int32_t split;  // nonzero: long rows, one wave per row (gspmv_rows_split)
+    // dictionary form (gspmv_tiles only; null code: the plain arrays)
+    const uint16_t *__restrict__ code = nullptr;  // [nnz + 8]
+    const int32_t *__restrict__ otab = nullptr;   // [noffs]
+    const T *__restrict__ vtab = nullptr;         // [nvals]
+    int32_t noffs = 0, nvals = 0;
+    int32_t ob = 0;  // bits of the offset index in a code
 };
 
 // One row of the product: sum over the row's entries in storage order of
@@ -386,6 +401,38 @@ __device__ __forceinline__ void row_product(PI cis, PV vas, int j0, int j1, int 
             const int jj = ok[k] ? j + k : j1 - 1;
             c[k] = cis[jj];
             a[k] = vas[jj];
+        }
+#pragma unroll
+        for (int k = 0; k < NB; ++k)
+            op.gather(ln, c[k], g, x[k]);
+#pragma unroll
+        for (int k = 0; k < NB; ++k)
+#pragma unroll
+            for (int v = 0; v < VW; ++v)
+                if (ok[k])
+                    sum[v] += a[k] * x[k][v];
+    }
+}
+
+// row_product over the dictionary form: entry j's column is
+// row + otab[code & omask], its value vtab[code >> ob] (tables in LDS).
+template <typename T, int VW, class Op, typename PC>
+__device__ __forceinline__ void row_product_dict(PC codes, const int32_t *otab, const T *vtab, int ob,
+                                                 uint32_t omask, int32_t row, int j0, int j1, int g, const Op &op,
+                                                 const typename Op::Lane &ln, T *sum)
+{
+    constexpr int NB = MRHS_GATHER_BATCH;
+    for (int j = j0; j < j1; j += NB) {
+        int32_t c[NB];
+        T a[NB], x[NB][VW];
+        bool ok[NB];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            ok[k] = j + k < j1;
+            const int jj = ok[k] ? j + k : j1 - 1;
+            const uint32_t cd = codes[jj];
+            c[k] = row + otab[cd & omask];
+            a[k] = vtab[cd >> ob];
         }
 #pragma unroll
         for (int k = 0; k < NB; ++k)
@@ -519,14 +566,129 @@ __device__ __forceinline__ Staged stage_csr(const CsrView<T> &A, int32_t r0, int
 // coalesced streaming loads (one pass over HBM, no reuse in cache needed), then
 // every lane walks its rows out of LDS and gathers block rows of X through the
 // cache hierarchy.  A tile whose nonzeros exceed S::NZCAP reads them directly.
+// LDS of a tile: the plain form's indices and values, or the dictionary
+// form's codes and tables, in one buffer.
+template <typename T, int M>
+struct TileLds {
+    using S = Shape<T, M>;
+    static constexpr int CI_BYTES = (S::NZCAP + 4) * 4;
+    static constexpr int PLAIN = CI_BYTES + (S::NZCAP + 4) * static_cast<int>(sizeof(T));
+    static constexpr int CODE_BYTES = ((S::NZCAP + 8) * 2 + 15) / 16 * 16;
+    static constexpr int VTAB_AT = CODE_BYTES + kDictOffs * 4;
+    static constexpr int DICT = VTAB_AT + kDictVals * static_cast<int>(sizeof(T));
+    static constexpr int BYTES = PLAIN > DICT ? PLAIN : DICT;
+};
+
+// gspmv_tiles over the dictionary form: the tables are loaded into LDS
+// once, then every tile stages its codes (16-byte loads of 8 codes from the
+// 8-aligned index zb <= z0; the code array carries 8 codes of padding).
+template <typename T, int M, class Op>
+__device__ __forceinline__ void gspmv_tiles_dict(const CsrView<T> &A, const Op &op,
+                                                 Acc<T, Shape<T, M>::VW, Op::NDOT> &acc, int32_t *s_rp,
+                                                 unsigned char *s_buf)
+{
+    using S = Shape<T, M>;
+    using LD = TileLds<T, M>;
+    using I4 = int __attribute__((ext_vector_type(4)));
+    uint16_t *s_code = reinterpret_cast<uint16_t *>(s_buf);
+    int32_t *s_otab = reinterpret_cast<int32_t *>(s_buf + LD::CODE_BYTES);
+    T *s_vtab = reinterpret_cast<T *>(s_buf + LD::VTAB_AT);
+    const int tid = threadIdx.x;
+    const int g = S::lane_of(tid);
+    const int rl = S::row_of(tid);
+    const typename Op::Lane ln = op.lane(g < S::G ? g : 0);
+    const bool lane_on = S::used(tid) && g < S::G && ln.on;
+    for (int k = tid; k < A.noffs; k += kBlock)
+        s_otab[k] = A.otab[k];
+    for (int k = tid; k < A.nvals; k += kBlock)
+        s_vtab[k] = A.vtab[k];
+    // (visible after the first tile's barrier)
+    const int ob = A.ob;
+    const uint32_t omask = (1u << ob) - 1u;
+    const int32_t ntiles = static_cast<int32_t>((static_cast<int64_t>(A.n) + S::TR - 1) / S::TR);
+    const int32_t P = plane_tiles(A.reach, S::TR, ntiles);
+    constexpr int32_t kBlockBytes = (gathered_blocks<Op>::value + 1) * S::TR * M * static_cast<int32_t>(sizeof(T));
+    const TileRange tr = tile_range(ntiles, P, plane_chunks(P, A.reach, S::TR, kBlockBytes));
+    constexpr int CO_PT = ((S::NZCAP + 8) / 8 + kBlock - 1) / kBlock;
+    for (int32_t step = tr.first; step < tr.end; step += tr.stride) {
+        const int32_t tile = tr.tile(step);
+        if (tile >= ntiles)
+            continue;
+        const int32_t r0 = tile * S::TR;
+        const int nr = min(S::TR, A.n - r0);
+        for (int k = tid; k <= nr; k += kBlock)
+            s_rp[k] = A.rp[r0 + k];
+        __syncthreads();
+        const int32_t z0 = s_rp[0];
+        const int cnt = s_rp[nr] - z0;
+        const int32_t zb = z0 & ~7;
+        const int lead = z0 - zb;
+        const bool staged = cnt + lead <= S::NZCAP;
+        if (staged) {
+            const int nco = (cnt + lead + 7) / 8;
+            const I4 *gco = reinterpret_cast<const I4 *>(A.code + zb);
+            I4 bco[CO_PT];
+#pragma unroll
+            for (int u = 0; u < CO_PT; ++u) {
+                const int k = tid + u * kBlock;
+                if (k < nco)
+                    bco[u] = __builtin_nontemporal_load(gco + k);
+            }
+#pragma unroll
+            for (int u = 0; u < CO_PT; ++u) {
+                const int k = tid + u * kBlock;
+                if (k < nco)
+                    reinterpret_cast<I4 *>(s_code)[k] = bco[u];
+            }
+        }
+        __syncthreads();
+        const uint16_t *lco = s_code + lead;
+#pragma unroll 1
+        for (int p = 0; p < S::PASSES; ++p) {
+            const int row_l = p * S::RPP + rl;
+            if (lane_on && row_l < nr) {
+                const int32_t row = r0 + row_l;
+                const int j0 = s_rp[row_l] - z0;
+                const int j1 = s_rp[row_l + 1] - z0;
+                T sum[S::VW];
+#pragma unroll
+                for (int v = 0; v < S::VW; ++v)
+                    sum[v] = T(0);
+                if constexpr (has_pre<Op>::value) {
+                    const typename Op::Pre pr = op.pre(ln, row, g);
+                    if (staged)
+                        row_product_dict<T, S::VW>(lco, s_otab, s_vtab, ob, omask, row, j0, j1, g, op, ln, sum);
+                    else
+                        row_product_dict<T, S::VW>(A.code + z0, s_otab, s_vtab, ob, omask, row, j0, j1, g, op, ln,
+                                                   sum);
+                    op.row(ln, row, g, sum, acc, pr);
+                } else {
+                    if (staged)
+                        row_product_dict<T, S::VW>(lco, s_otab, s_vtab, ob, omask, row, j0, j1, g, op, ln, sum);
+                    else
+                        row_product_dict<T, S::VW>(A.code + z0, s_otab, s_vtab, ob, omask, row, j0, j1, g, op, ln,
+                                                   sum);
+                    op.row(ln, row, g, sum, acc);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 template <typename T, int M, class Op>
 __device__ __forceinline__ void gspmv_tiles(const CsrView<T> &A, const Op &op,
                                             Acc<T, Shape<T, M>::VW, Op::NDOT> &acc)
 {
     using S = Shape<T, M>;
     __shared__ int32_t s_rp[S::TR + 1];
-    __shared__ __align__(16) int32_t s_ci[S::NZCAP + 4];
-    __shared__ __align__(16) T s_va[S::NZCAP + 4];
+    __shared__ __align__(16) unsigned char s_buf[TileLds<T, M>::BYTES];
+    if (A.code) {
+        gspmv_tiles_dict<T, M>(A, op, acc, s_rp, s_buf);
+        return;
+    }
+    int32_t *s_ci = reinterpret_cast<int32_t *>(s_buf);
+    T *s_va = reinterpret_cast<T *>(s_buf + TileLds<T, M>::CI_BYTES);
     const int tid = threadIdx.x;
     const int g = S::lane_of(tid);
     const int rl = S::row_of(tid);

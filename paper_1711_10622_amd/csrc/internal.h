@@ -34,6 +34,15 @@ struct mrhs_csr_s {
     double *uval = nullptr;
     float *uval32 = nullptr;
     int32_t ureach = 0;
+    // dictionary form of the solver arrays (CsrView): offset table, and per
+    // value array (val, valh, val32, valh32) codes and value table; a null
+    // code means that array has too many distinct values (or the matrix too
+    // many distinct offsets) and products read the plain arrays
+    int32_t *otab = nullptr;
+    int32_t noffs = 0, ob = 0;
+    uint16_t *code[4] = {nullptr, nullptr, nullptr, nullptr};
+    void *vtab[4] = {nullptr, nullptr, nullptr, nullptr};
+    int32_t nvals[4] = {0, 0, 0, 0};
 };
 
 namespace mrhs {
@@ -58,16 +67,33 @@ int max_grid();  // upper bound of grid_for over all kernels (for buffer sizing)
 template <typename T>
 inline CsrView<T> view(const mrhs_csr_s &A, bool scaled);
 
+// The view of value array k (0 val, 1 valh, 2 val32, 3 valh32), in its
+// dictionary form when it has one.
+template <typename T>
+inline CsrView<T> view_of(const mrhs_csr_s &A, const T *va, int k)
+{
+    CsrView<T> v{A.rp, A.ci, va, A.n, A.reach, 0};
+    if (A.code[k]) {
+        v.code = A.code[k];
+        v.otab = A.otab;
+        v.vtab = static_cast<const T *>(A.vtab[k]);
+        v.noffs = A.noffs;
+        v.nvals = A.nvals[k];
+        v.ob = A.ob;
+    }
+    return v;
+}
+
 template <>
 inline CsrView<double> view<double>(const mrhs_csr_s &A, bool scaled)
 {
-    return {A.rp, A.ci, scaled ? A.valh : A.val, A.n, A.reach, 0};
+    return scaled ? view_of<double>(A, A.valh, 1) : view_of<double>(A, A.val, 0);
 }
 
 template <>
 inline CsrView<float> view<float>(const mrhs_csr_s &A, bool scaled)
 {
-    return {A.rp, A.ci, scaled ? A.valh32 : A.val32, A.n, A.reach, 0};
+    return scaled ? view_of<float>(A, A.valh32, 3) : view_of<float>(A, A.val32, 2);
 }
 
 // The matrix in the caller's numbering (gspmv): the handle's own arrays, or

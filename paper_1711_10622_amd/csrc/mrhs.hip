@@ -5,6 +5,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -236,12 +237,15 @@ void free_csr(mrhs_csr_s *A)
     if (!A)
         return;
     void *ptrs[] = {A->rp,   A->ci,   A->val, A->valh, A->val32, A->valh32, A->diag,
-                    A->dinv, A->perm, A->urp, A->uci, A->uval, A->uval32};
+                    A->dinv, A->perm, A->urp, A->uci, A->uval, A->uval32, A->otab,
+                    A->code[0], A->code[1], A->code[2], A->code[3],
+                    A->vtab[0], A->vtab[1], A->vtab[2], A->vtab[3]};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
     delete A;
 }
+
 
 template <typename T>
 mrhs_status dev_alloc(T **p, size_t count, size_t &total)
@@ -257,6 +261,203 @@ mrhs_status dev_alloc(T **p, size_t count, size_t &total)
 }
 
 constexpr size_t kPad = 4;  // elements of padding after the nnz entries
+
+// ---- dictionary form (CsrView::code) ----------------------------------------
+// Distinct keys in order of first appearance, at most `limit`; open
+// addressing over a power-of-two table.
+template <typename K>
+struct KeySet {
+    std::vector<K> keys;
+    std::vector<int32_t> slot;  // index into keys + 1, 0 empty
+    uint64_t mask = 0;
+    explicit KeySet(int limit)
+    {
+        size_t cap = 16;
+        while (cap < 4 * static_cast<size_t>(limit))
+            cap *= 2;
+        slot.assign(cap, 0);
+        mask = cap - 1;
+    }
+    static uint64_t hash(K k)
+    {
+        uint64_t z = static_cast<uint64_t>(k) * 0x9E3779B97F4A7C15ull;
+        return z ^ (z >> 29);
+    }
+    // index of k, inserting it; -1 when that would exceed limit
+    int32_t add(K k, int limit)
+    {
+        for (uint64_t h = hash(k) & mask;; h = (h + 1) & mask) {
+            const int32_t e = slot[h];
+            if (!e) {
+                if (static_cast<int>(keys.size()) >= limit)
+                    return -1;
+                keys.push_back(k);
+                slot[h] = static_cast<int32_t>(keys.size());
+                return slot[h] - 1;
+            }
+            if (keys[e - 1] == k)
+                return e - 1;
+        }
+    }
+    int32_t find(K k) const
+    {
+        for (uint64_t h = hash(k) & mask;; h = (h + 1) & mask) {
+            const int32_t e = slot[h];
+            if (!e || keys[e - 1] == k)
+                return e - 1;
+        }
+    }
+};
+
+int dict_threads()
+{
+    const unsigned hw = std::thread::hardware_concurrency();
+    return std::max(1, std::min(16, static_cast<int>(hw ? hw : 1)));
+}
+
+// Runs fn(lo, hi, t) over T contiguous row ranges of [0, n) in threads.
+template <class F>
+void row_ranges(int32_t n, int T, F &&fn)
+{
+    std::vector<std::thread> th;
+    for (int t = 0; t < T; ++t) {
+        const int32_t lo = static_cast<int32_t>(static_cast<int64_t>(n) * t / T);
+        const int32_t hi = static_cast<int32_t>(static_cast<int64_t>(n) * (t + 1) / T);
+        th.emplace_back([&fn, lo, hi, t] { fn(lo, hi, t); });
+    }
+    for (auto &x : th)
+        x.join();
+}
+
+// Distinct keys of key(j) over the entries of rows [0, n), in order of first
+// appearance in row order, at most limit (false when there are more).
+template <typename K, class KeyOf>
+bool distinct_keys(int32_t n, const int32_t *rp, int limit, KeyOf key, KeySet<K> &out)
+{
+    const int T = dict_threads();
+    std::vector<KeySet<K>> local(T, KeySet<K>(limit));
+    std::vector<char> over(T, 0);
+    row_ranges(n, T, [&](int32_t lo, int32_t hi, int t) {
+        for (int32_t i = lo; i < hi && !over[t]; ++i)
+            for (int32_t j = rp[i]; j < rp[i + 1]; ++j)
+                if (local[t].add(key(i, j), limit) < 0) {
+                    over[t] = 1;
+                    break;
+                }
+    });
+    for (int t = 0; t < T; ++t) {
+        if (over[t])
+            return false;
+        for (K k : local[t].keys)
+            if (out.add(k, limit) < 0)
+                return false;
+    }
+    return true;
+}
+
+template <typename V>
+struct BitsOf;
+template <>
+struct BitsOf<double> {
+    using U = uint64_t;
+};
+template <>
+struct BitsOf<float> {
+    using U = uint32_t;
+};
+
+// Codes and value table of one value array (host values hv) given the
+// offset set; false (nothing allocated) when it has too many distinct values.
+template <typename V>
+mrhs_status dict_array(mrhs_csr_s *A, const int32_t *rp, const int32_t *ci, const V *hv,
+                       const KeySet<int64_t> &offs, int k, size_t &total)
+{
+    using U = typename BitsOf<V>::U;
+    const int32_t n = A->n;
+    const int64_t nnz = A->nnz;
+    const int limit = std::min(kDictVals, 1 << (16 - A->ob));
+    KeySet<U> vals(limit);
+    auto bits = [&](int32_t, int32_t j) {
+        U u;
+        std::memcpy(&u, &hv[j], sizeof(U));
+        return u;
+    };
+    if (!distinct_keys<U>(n, rp, limit, bits, vals))
+        return MRHS_OK;
+    std::vector<uint16_t> code(static_cast<size_t>(nnz) + 8, 0);
+    row_ranges(n, dict_threads(), [&](int32_t lo, int32_t hi, int) {
+        for (int32_t i = lo; i < hi; ++i)
+            for (int32_t j = rp[i]; j < rp[i + 1]; ++j) {
+                const int32_t o = offs.find(static_cast<int64_t>(ci[j]) - i);
+                const int32_t v = vals.find(bits(i, j));
+                code[j] = static_cast<uint16_t>((v << A->ob) | o);
+            }
+    });
+    std::vector<V> tab(vals.keys.size());
+    std::memcpy(tab.data(), vals.keys.data(), sizeof(V) * tab.size());
+    uint16_t *dcode = nullptr;
+    V *dtab = nullptr;
+    mrhs_status st;
+    if ((st = dev_alloc(&dcode, code.size(), total)))
+        return st;
+    if ((st = dev_alloc(&dtab, tab.size(), total))) {
+        (void)hipFree(dcode);
+        return st;
+    }
+    A->code[k] = dcode;
+    A->vtab[k] = dtab;
+    A->nvals[k] = static_cast<int32_t>(tab.size());
+    hipError_t e;
+    if ((e = hipMemcpy(dcode, code.data(), sizeof(uint16_t) * code.size(), hipMemcpyHostToDevice)) ||
+        (e = hipMemcpy(dtab, tab.data(), sizeof(V) * tab.size(), hipMemcpyHostToDevice)))
+        return set_error(MRHS_EDEVICE, "dictionary upload failed: %s", hipGetErrorString(e));
+    return MRHS_OK;
+}
+
+// Builds the dictionary form of the solver arrays when the matrix has at
+// most kDictOffs distinct column offsets (rp, ci: the solver's numbering,
+// sval: its binary64 values on the host; the derived arrays are read back
+// from the device, so the tables hold exactly the values the products use).
+// MRHS_CSR_DICT=0 turns it off.
+mrhs_status build_dict(mrhs_csr_s *A, const int32_t *rp, const int32_t *ci, const double *sval, size_t &total)
+{
+    if (!env_int("MRHS_CSR_DICT", 1, 0, 1) || A->nnz == 0)
+        return MRHS_OK;
+    KeySet<int64_t> offs(kDictOffs);
+    auto off = [&](int32_t i, int32_t j) { return static_cast<int64_t>(ci[j]) - i; };
+    if (!distinct_keys<int64_t>(A->n, rp, kDictOffs, off, offs))
+        return MRHS_OK;
+    A->noffs = static_cast<int32_t>(offs.keys.size());
+    A->ob = 0;
+    while ((1 << A->ob) < A->noffs)
+        ++A->ob;
+    std::vector<int32_t> otab(offs.keys.begin(), offs.keys.end());
+    mrhs_status st;
+    if ((st = dev_alloc(&A->otab, otab.size(), total)))
+        return st;
+    hipError_t e;
+    if ((e = hipMemcpy(A->otab, otab.data(), sizeof(int32_t) * otab.size(), hipMemcpyHostToDevice)))
+        return set_error(MRHS_EDEVICE, "dictionary upload failed: %s", hipGetErrorString(e));
+    const size_t nnz = static_cast<size_t>(A->nnz);
+    if ((st = dict_array<double>(A, rp, ci, sval, offs, 0, total)))
+        return st;
+    {
+        std::vector<double> h(nnz);
+        if ((e = hipMemcpy(h.data(), A->valh, sizeof(double) * nnz, hipMemcpyDeviceToHost)))
+            return set_error(MRHS_EDEVICE, "read-back failed: %s", hipGetErrorString(e));
+        if ((st = dict_array<double>(A, rp, ci, h.data(), offs, 1, total)))
+            return st;
+    }
+    std::vector<float> h(nnz);
+    const float *src[2] = {A->val32, A->valh32};
+    for (int k = 0; k < 2; ++k) {
+        if ((e = hipMemcpy(h.data(), src[k], sizeof(float) * nnz, hipMemcpyDeviceToHost)))
+            return set_error(MRHS_EDEVICE, "read-back failed: %s", hipGetErrorString(e));
+        if ((st = dict_array<float>(A, rp, ci, h.data(), offs, 2 + k, total)))
+            return st;
+    }
+    return MRHS_OK;
+}
 
 bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
@@ -466,6 +667,11 @@ MRHS_API mrhs_status csr_create(int32_t n, int64_t nnz, const int32_t *row_ptr, 
         free_csr(A);
         return set_error(MRHS_EDEVICE, "derive kernels failed: %s", hipGetErrorString(e));
     }
+    if ((st = build_dict(A, row_ptr, col_idx, sval, total))) {
+        free_csr(A);
+        return st;
+    }
+    A->bytes = total;
     *out = A;
     return MRHS_OK;
 }
@@ -491,6 +697,19 @@ MRHS_API mrhs_status csr_info(mrhs_csr A, int32_t *n, int64_t *nnz, size_t *devi
         *nnz = A->nnz;
     if (device_bytes)
         *device_bytes = A->bytes;
+    return MRHS_OK;
+}
+
+MRHS_API mrhs_status csr_stream_bytes(mrhs_csr A, int32_t dtype, int32_t scaled, int64_t *bytes)
+{
+    clear_error();
+    if (!A || !bytes)
+        return set_error(MRHS_EINVAL, "NULL argument");
+    if (dtype != MRHS_F64 && dtype != MRHS_F32)
+        return set_error(MRHS_EINVAL, "unknown dtype %d", dtype);
+    const int k = (dtype == MRHS_F64 ? 0 : 2) + (scaled ? 1 : 0);
+    const int64_t per = A->code[k] ? 2 : 4 + (dtype == MRHS_F64 ? 8 : 4);
+    *bytes = 4 * (static_cast<int64_t>(A->n) + 1) + per * A->nnz;
     return MRHS_OK;
 }
 

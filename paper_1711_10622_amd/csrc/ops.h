@@ -478,7 +478,6 @@ struct OpSpmv1 {
     __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, const T *sum,
                                         Acc<T, S::VW, NDOT> &acc) const
     {
-        const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         T h[S::VW];
         shadow_row<T, M>(sgn, i, g, h);
         st<T, M>(v, i, g, sum, ldp);
@@ -674,7 +673,6 @@ struct OpXR {
     }
     __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, Acc<T, S::VW, NDOT> &acc) const
     {
-        const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         T yy[S::VW], rr[S::VW], pp[S::VW], vv[S::VW], tt[S::VW];
         ld<T, M>(y, i, g, yy);
         ld<T, M>(r, i, g, rr, ldp);
@@ -867,7 +865,6 @@ struct OpRestart {
     }
     __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, Acc<T, S::VW, NDOT> &) const
     {
-        const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         T a[S::VW], b[S::VW], pp[S::VW];
         ld<T, M>(rt, i, g, a);
         ld<T, M>(r, i, g, b, ldp);
@@ -927,7 +924,6 @@ struct OpScale {
     }
     __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, Acc<double, S::VW, NDOT> &) const
     {
-        const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         double a[S::VW];
         ld<double, M>(x, i, g, a);
         const double di = (kind == SC_IN) ? diag[i] : (kind == SC_OUT ? dinv[i] : 1.0);
@@ -1028,7 +1024,6 @@ struct OpCast {
     }
     __device__ __forceinline__ void row(const Lane &ln, int32_t i, int g, Acc<float, S::VW, NDOT> &acc) const
     {
-        const size_t o = static_cast<size_t>(i) * M + g * S::VW;
         float a[S::VW], z[S::VW], pp[S::VW];
         ld<float, M>(r, i, g, a, ldp);
         ld<float, M>(y, i, g, z);

@@ -66,6 +66,8 @@ def test_invalid_arguments_without_device():
     assert lib.block_bicgstab(None, None, None, 4, 1e-10, 10) == _lib.EINVAL
     b = ctypes.c_size_t()
     assert lib.block_bicgstab_workspace_size(None, 4, 0, ctypes.byref(b)) == _lib.EINVAL
+    sb = ctypes.c_int64()
+    assert lib.csr_stream_bytes(None, _lib.F64, 0, ctypes.byref(sb)) == _lib.EINVAL
     assert lib.mrhs_trace_enable(-1) == _lib.EINVAL
     assert lib.mrhs_trace_enable(0) == _lib.OK
     h = ctypes.c_void_p()

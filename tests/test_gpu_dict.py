@@ -1,0 +1,158 @@
+"""GPU parity of the dictionary form of a matrix (csr_create).
+
+A matrix with at most 32 distinct column offsets stores, per value array with
+at most 2048 distinct values, one 16-bit code per entry and two tables; the
+tiled products read those instead of the index and value arrays.  They sum the
+same values in the same order, so every product and solve must equal, bit for
+bit, the same call on a handle made with MRHS_CSR_DICT=0 (plain arrays), which
+the other GPU tests hold to the oracle.  Covered: stencil matrices (dictionary
+in every array), a banded matrix whose tiles exceed the staged capacity (codes
+read from HBM), both sides of the 2048-value limit, too many values and too
+many offsets (plain form), products at every block width in both precisions,
+binary64 (plain and merged iterations) and mixed solves.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import bench
+import oracle
+from helpers import abs_bound
+from workloads import grids, rng
+from workloads.grids import CSRMatrix
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1711_10622_amd as p
+    p.load(build_if_missing=False)
+    return torch, p
+
+
+def make(p, A, dict_on):
+    old = os.environ.get("MRHS_CSR_DICT")
+    os.environ["MRHS_CSR_DICT"] = "1" if dict_on else "0"
+    try:
+        return p.CsrMatrix.from_csr(A)
+    finally:
+        if old is None:
+            del os.environ["MRHS_CSR_DICT"]
+        else:
+            os.environ["MRHS_CSR_DICT"] = old
+
+
+def from_diagonals(n, offsets, values_of):
+    """Banded matrix: row i holds (i, i + o) for every offset o inside [0, n),
+    in ascending column order, with value values_of(i, o)."""
+    rp = [0]
+    ci, va = [], []
+    for i in range(n):
+        for o in sorted(offsets):
+            if 0 <= i + o < n:
+                ci.append(i + o)
+                va.append(values_of(i, o))
+        rp.append(len(ci))
+    return CSRMatrix(n, np.array(rp, np.int32), np.array(ci, np.int32), np.array(va, np.float64))
+
+
+def tridiag_k(n, k):
+    """Tridiagonal, diagonal 4 + (i mod k) 2^-10, off-diagonals -1: k + 1
+    distinct values (exact in binary32 too)."""
+    return from_diagonals(n, (-1, 0, 1), lambda i, o: 4.0 + (i % k) * 2.0 ** -10 if o == 0 else -1.0)
+
+
+def cases():
+    return {
+        "dir16": (grids.dirichlet7(16), True),
+        "chan32x24x16": (grids.channel7(32, 24, 16, beta=2.0), True),
+        # 25 entries per row: 256-row tiles exceed the staged 2048 entries
+        "band25": (from_diagonals(3000, range(-12, 13), lambda i, o: 40.0 if o == 0 else -1.0 - 0.5 * (o % 2)), True),
+        "values2048": (tridiag_k(3000, 2047), True),
+        "values2049": (tridiag_k(3000, 2048), False),
+        "perturbed": (None, False),
+        "relabelled": (grids.permute_symmetric(grids.dirichlet7(12), rng.permutation(12 ** 3, 5)), False),
+    }
+
+
+def matrix(name):
+    A, dict_expected = cases()[name]
+    if name == "perturbed":
+        B = grids.dirichlet7(12)
+        g = np.random.default_rng(3)
+        A = CSRMatrix(B.n, B.row_ptr, B.col, B.val * (1.0 + 1e-3 * g.random(B.val.size)))
+    return A, dict_expected
+
+
+def cuda(torch, X):
+    return torch.from_numpy(np.ascontiguousarray(X)).cuda()
+
+
+@pytest.mark.parametrize("name", list(cases()))
+def test_stream_bytes_reports_the_form(env, name):
+    _, p = env
+    A, dict_expected = matrix(name)
+    Md, M0 = make(p, A, True), make(p, A, False)
+    plain = {"f64": 4 * (A.n + 1) + 12 * A.col.size, "f32": 4 * (A.n + 1) + 8 * A.col.size}
+    for dt in ("f64", "f32"):
+        for scaled in (False, True):
+            assert M0.stream_bytes(dt, scaled) == plain[dt]
+            want = 4 * (A.n + 1) + 2 * A.col.size if dict_expected else plain[dt]
+            assert Md.stream_bytes(dt, scaled) == want, (dt, scaled)
+            # the offline rule the benchmark summaries use agrees
+            assert bench.matrix_stream_bytes(A, 8 if dt == "f64" else 4, scaled) == want, (dt, scaled)
+    if dict_expected:
+        assert Md.device_bytes() > M0.device_bytes()
+    Md.close()
+    M0.close()
+
+
+@pytest.mark.parametrize("name", list(cases()))
+def test_gspmv_bitwise_plain(env, name):
+    torch, p = env
+    A, _ = matrix(name)
+    Md, M0 = make(p, A, True), make(p, A, False)
+    for m in range(1, 17):
+        X = rng.rhs_block(A.n, m, 100 + m)
+        Yd = p.gspmv(Md, cuda(torch, X)).cpu().numpy()
+        Y0 = p.gspmv(M0, cuda(torch, X)).cpu().numpy()
+        assert np.array_equal(Yd, Y0), m
+        X32 = X.astype(np.float32)
+        Yd = p.gspmv(Md, cuda(torch, X32)).cpu().numpy()
+        Y0 = p.gspmv(M0, cuda(torch, X32)).cpu().numpy()
+        assert np.array_equal(Yd, Y0), ("f32", m)
+    X = rng.rhs_block(A.n, 5, 7)
+    Y = p.gspmv(Md, cuda(torch, X)).cpu().numpy()
+    assert np.all(np.abs(Y - oracle.gspmv(A, X)) <= 1e-13 * abs_bound(A, X))
+    Md.close()
+    M0.close()
+
+
+@pytest.mark.parametrize("name,m,mixed,maxit,tol", [
+    ("dir16", 4, False, 25, 1e-14),      # merged two-kernel iteration, not converged
+    ("dir16", 8, False, 2000, 1e-10),
+    ("chan32x24x16", 3, False, 4000, 1e-10),
+    ("chan32x24x16", 16, False, 4000, 1e-10),
+    ("chan32x24x16", 8, True, 4000, 1e-10),
+    ("band25", 7, False, 2000, 1e-10),
+    ("values2048", 4, True, 2000, 1e-10),
+])
+def test_solve_bitwise_plain(env, name, m, mixed, maxit, tol):
+    torch, p = env
+    A, _ = matrix(name)
+    B = rng.rhs_block(A.n, m, 200 + m, mean_zero=bool(getattr(A, "nullspace_const", False)))
+    out = []
+    for dict_on in (True, False):
+        M = make(p, A, dict_on)
+        X, infos, st = M.solve(cuda(torch, B), tol=tol, maxit=maxit, mixed=mixed)
+        out.append((X.cpu().numpy(), [(i["iters"], i["relres"]) for i in infos], st))
+        M.close()
+    assert out[0][2] == out[1][2]
+    assert out[0][1] == out[1][1]
+    assert np.array_equal(out[0][0], out[1][0])
+    if maxit > 100:
+        assert out[0][2] == 0
