@@ -246,7 +246,6 @@ void free_csr(mrhs_csr_s *A)
     delete A;
 }
 
-
 template <typename T>
 mrhs_status dev_alloc(T **p, size_t count, size_t &total)
 {
@@ -278,10 +277,16 @@ struct KeySet {
         slot.assign(cap, 0);
         mask = cap - 1;
     }
+    // MurmurHash3's 64-bit finalizer: every key bit reaches the low bits the
+    // table uses (values such as 4 + k 2^-10 have zero low mantissa bits)
     static uint64_t hash(K k)
     {
-        uint64_t z = static_cast<uint64_t>(k) * 0x9E3779B97F4A7C15ull;
-        return z ^ (z >> 29);
+        uint64_t z = static_cast<uint64_t>(k);
+        z ^= z >> 33;
+        z *= 0xff51afd7ed558ccdull;
+        z ^= z >> 33;
+        z *= 0xc4ceb9fe1a85ec53ull;
+        return z ^ (z >> 33);
     }
     // index of k, inserting it; -1 when that would exceed limit
     int32_t add(K k, int limit)
