@@ -92,9 +92,10 @@ _MAT_CACHE = {}
 
 def matrix_stream_bytes(A, S, scaled):
     """Bytes a product streams from A's arrays, by the rule csr_create uses
-    for the dictionary form (at most 32 distinct column offsets; at most 2048
-    distinct values in the value array: A or A D^-1, binary64 or its binary32
-    rounding), for offline summaries; runs on a device use
+    for the dictionary form (at most 2048 distinct values in the value array:
+    A or A D^-1, binary64 or its binary32 rounding; 2-byte codes with at most
+    32 distinct column offsets, else 4-byte codes when n fits 32 minus the
+    value index's bits), for offline summaries; runs on a device use
     CsrMatrix.stream_bytes."""
     import numpy as np
     key = (id(A), S, bool(scaled))
@@ -102,19 +103,22 @@ def matrix_stream_bytes(A, S, scaled):
         plain = 4 * (A.n + 1) + (4 + S) * A.nnz
         rows = np.repeat(np.arange(A.n, dtype=np.int64), np.diff(A.row_ptr))
         off = A.col.astype(np.int64) - rows
-        ok = np.unique(off).size <= 32
-        if ok:
-            v = A.val
-            if scaled:
-                d = np.zeros(A.n)
-                np.add.at(d, rows[off == 0], A.val[off == 0])
-                dc = d[A.col]
-                v = np.where(dc != 0.0, A.val / np.where(dc != 0.0, dc, 1.0), 0.0)
-            if S == 4:
-                v = v.astype(np.float32)
-            ok = np.unique(v.view(np.uint64 if S == 8 else np.uint32)).size <= 2048
+        by_offset = np.unique(off).size <= 32
+        v = A.val
+        if scaled:
+            d = np.zeros(A.n)
+            np.add.at(d, rows[off == 0], A.val[off == 0])
+            dc = d[A.col]
+            v = np.where(dc != 0.0, A.val / np.where(dc != 0.0, dc, 1.0), 0.0)
+        if S == 4:
+            v = v.astype(np.float32)
+        nv = np.unique(v.view(np.uint64 if S == 8 else np.uint32)).size
+        per = 4 + S
+        if nv <= 2048:
+            vb = max(1, int(np.ceil(np.log2(nv))) if nv > 1 else 1)
+            per = 2 if by_offset else 4 if A.n <= 2 ** (32 - vb) else per
         # (the entry keeps A alive, so its id is not reused while cached)
-        _MAT_CACHE[key] = (A, 4 * (A.n + 1) + 2 * A.nnz if ok else plain)
+        _MAT_CACHE[key] = (A, 4 * (A.n + 1) + per * A.nnz)
     return _MAT_CACHE[key][1]
 
 

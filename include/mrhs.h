@@ -112,11 +112,13 @@ const char *mrhs_version(void);
  * non-finite value.  A zero diagonal is accepted here and rejected by the
  * solvers.
  *
- * Dictionary form: when the solvers' matrix has at most 32 distinct column
- * offsets col - row (a structured grid's stencil) the handle also stores, for
- * each value array with at most 2048 distinct values, one 16-bit code per
- * entry (offset index and value index) and the two tables; the tiled products
- * then stream 2 bytes per entry instead of 4 + 8 (binary64) or 4 + 4
+ * Dictionary form: for each value array with at most 2048 distinct values
+ * the handle also stores one code per entry and the value table: a 16-bit
+ * code (offset index and value index, with the offset table) when the
+ * solvers' matrix has at most 32 distinct column offsets col - row (a
+ * structured grid's stencil), else a 32-bit code (column and value index)
+ * when the columns fit beside the value index.  The tiled products then
+ * stream 2 or 4 bytes per entry instead of 4 + 8 (binary64) or 4 + 4
  * (binary32) and sum exactly the same values in the same order.  Building it
  * reads the derived arrays back and takes one pass over the entries per
  * array; the environment variable MRHS_CSR_DICT=0 turns it off.  See
@@ -148,8 +150,8 @@ mrhs_status csr_info(mrhs_csr A, int32_t *n, int64_t *nnz, size_t *device_bytes)
 /*
  * Bytes one tiled product streams from the matrix arrays (Section 2.3: the
  * matrix part of the GSpMV memory traffic): the row offsets plus, per entry,
- * a 2-byte code in the dictionary form or a 4-byte column index and a value
- * otherwise.  dtype MRHS_F64 or MRHS_F32; scaled != 0 for the solvers'
+ * a 2- or 4-byte code in the dictionary form or a 4-byte column index and a
+ * value otherwise.  dtype MRHS_F64 or MRHS_F32; scaled != 0 for the solvers'
  * column-scaled matrix A D^-1, 0 for A.  gspmv of a handle made with
  * MRHS_CSR_REORDER reads the caller's arrays in plain form.  EINVAL: NULL
  * handle or output, unknown dtype.

@@ -361,7 +361,10 @@ __device__ __forceinline__ int32_t plane_chunks(int32_t P, int32_t reach, int32_
 // a structured grid do: entry j is one 16-bit code, its column
 // row + otab[code & omask] and its value vtab[code >> ob], both exact, so a
 // product sums the same values in the same order as from the plain arrays
-// and reads 2 bytes per entry instead of 4 + sizeof(T).
+// and reads 2 bytes per entry instead of 4 + sizeof(T).  A matrix with more
+// distinct offsets but few distinct values (a grid operator with its rows
+// renumbered) gets 32-bit codes instead: column code & cmask, value
+// vtab[code >> cb] (4 bytes per entry).
 constexpr int kDictOffs = 32;    // at most this many distinct offsets
 constexpr int kDictVals = 2048;  // and this many distinct values per array
 
@@ -373,12 +376,14 @@ struct CsrView {
     int32_t n;
     int32_t reach;  // median over rows of the largest forward column offset
     int32_t split;  // nonzero: long rows, one wave per row (gspmv_rows_split)
-    // dictionary form (gspmv_tiles only; null code: the plain arrays)
-    const uint16_t *__restrict__ code = nullptr;  // [nnz + 8]
-    const int32_t *__restrict__ otab = nullptr;   // [noffs]
-    const T *__restrict__ vtab = nullptr;         // [nvals]
+    // dictionary form (gspmv_tiles only; null code and ccode: the plain arrays)
+    const uint16_t *__restrict__ code = nullptr;   // [nnz + 8]
+    const int32_t *__restrict__ otab = nullptr;    // [noffs]
+    const uint32_t *__restrict__ ccode = nullptr;  // [nnz + 4] column codes
+    const T *__restrict__ vtab = nullptr;          // [nvals]
     int32_t noffs = 0, nvals = 0;
     int32_t ob = 0;  // bits of the offset index in a code
+    int32_t cb = 0;  // bits of the column in a column code
 };
 
 // One row of the product: sum over the row's entries in storage order of
@@ -401,6 +406,37 @@ __device__ __forceinline__ void row_product(PI cis, PV vas, int j0, int j1, int 
             const int jj = ok[k] ? j + k : j1 - 1;
             c[k] = cis[jj];
             a[k] = vas[jj];
+        }
+#pragma unroll
+        for (int k = 0; k < NB; ++k)
+            op.gather(ln, c[k], g, x[k]);
+#pragma unroll
+        for (int k = 0; k < NB; ++k)
+#pragma unroll
+            for (int v = 0; v < VW; ++v)
+                if (ok[k])
+                    sum[v] += a[k] * x[k][v];
+    }
+}
+
+// row_product over column codes: entry j's column is code & cmask, its value
+// vtab[code >> cb] (table in LDS).
+template <typename T, int VW, class Op, typename PC>
+__device__ __forceinline__ void row_product_cc(PC codes, const T *vtab, int cb, uint32_t cmask, int j0, int j1,
+                                               int g, const Op &op, const typename Op::Lane &ln, T *sum)
+{
+    constexpr int NB = MRHS_GATHER_BATCH;
+    for (int j = j0; j < j1; j += NB) {
+        int32_t c[NB];
+        T a[NB], x[NB][VW];
+        bool ok[NB];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            ok[k] = j + k < j1;
+            const int jj = ok[k] ? j + k : j1 - 1;
+            const uint32_t cd = codes[jj];
+            c[k] = static_cast<int32_t>(cd & cmask);
+            a[k] = vtab[cd >> cb];
         }
 #pragma unroll
         for (int k = 0; k < NB; ++k)
@@ -572,7 +608,9 @@ template <typename T, int M>
 struct TileLds {
     using S = Shape<T, M>;
     static constexpr int CI_BYTES = (S::NZCAP + 4) * 4;
-    static constexpr int PLAIN = CI_BYTES + (S::NZCAP + 4) * static_cast<int>(sizeof(T));
+    // values, or the value table of column codes
+    static constexpr int VA_ELEMS = S::NZCAP + 4 > kDictVals ? S::NZCAP + 4 : kDictVals;
+    static constexpr int PLAIN = CI_BYTES + VA_ELEMS * static_cast<int>(sizeof(T));
     static constexpr int CODE_BYTES = ((S::NZCAP + 8) * 2 + 15) / 16 * 16;
     static constexpr int VTAB_AT = CODE_BYTES + kDictOffs * 4;
     static constexpr int DICT = VTAB_AT + kDictVals * static_cast<int>(sizeof(T));
@@ -676,6 +714,98 @@ __device__ __forceinline__ void gspmv_tiles_dict(const CsrView<T> &A, const Op &
     }
 }
 
+// gspmv_tiles over column codes: the value table is loaded into LDS once,
+// then every tile stages its 4-byte codes as the plain form stages its
+// column indices (the code array carries 4 codes of padding).
+template <typename T, int M, class Op>
+__device__ __forceinline__ void gspmv_tiles_cc(const CsrView<T> &A, const Op &op,
+                                               Acc<T, Shape<T, M>::VW, Op::NDOT> &acc, int32_t *s_rp,
+                                               unsigned char *s_buf)
+{
+    using S = Shape<T, M>;
+    using LD = TileLds<T, M>;
+    using I4 = int __attribute__((ext_vector_type(4)));
+    uint32_t *s_cc = reinterpret_cast<uint32_t *>(s_buf);
+    T *s_vtab = reinterpret_cast<T *>(s_buf + LD::CI_BYTES);
+    const int tid = threadIdx.x;
+    const int g = S::lane_of(tid);
+    const int rl = S::row_of(tid);
+    const typename Op::Lane ln = op.lane(g < S::G ? g : 0);
+    const bool lane_on = S::used(tid) && g < S::G && ln.on;
+    for (int k = tid; k < A.nvals; k += kBlock)
+        s_vtab[k] = A.vtab[k];
+    // (visible after the first tile's barrier)
+    const int cb = A.cb;
+    const uint32_t cmask = cb >= 32 ? 0xffffffffu : (1u << cb) - 1u;
+    const int32_t ntiles = static_cast<int32_t>((static_cast<int64_t>(A.n) + S::TR - 1) / S::TR);
+    const int32_t P = plane_tiles(A.reach, S::TR, ntiles);
+    constexpr int32_t kBlockBytes = (gathered_blocks<Op>::value + 1) * S::TR * M * static_cast<int32_t>(sizeof(T));
+    const TileRange tr = tile_range(ntiles, P, plane_chunks(P, A.reach, S::TR, kBlockBytes));
+    constexpr int CC_PT = ((S::NZCAP + 4) / 4 + kBlock - 1) / kBlock;
+    for (int32_t step = tr.first; step < tr.end; step += tr.stride) {
+        const int32_t tile = tr.tile(step);
+        if (tile >= ntiles)
+            continue;
+        const int32_t r0 = tile * S::TR;
+        const int nr = min(S::TR, A.n - r0);
+        for (int k = tid; k <= nr; k += kBlock)
+            s_rp[k] = A.rp[r0 + k];
+        __syncthreads();
+        const int32_t z0 = s_rp[0];
+        const int cnt = s_rp[nr] - z0;
+        const int32_t zb = z0 & ~3;
+        const int lead = z0 - zb;
+        const bool staged = cnt + lead <= S::NZCAP;
+        if (staged) {
+            const int ncc = (cnt + lead + 3) / 4;
+            const I4 *gcc = reinterpret_cast<const I4 *>(A.ccode + zb);
+            I4 bcc[CC_PT];
+#pragma unroll
+            for (int u = 0; u < CC_PT; ++u) {
+                const int k = tid + u * kBlock;
+                if (k < ncc)
+                    bcc[u] = __builtin_nontemporal_load(gcc + k);
+            }
+#pragma unroll
+            for (int u = 0; u < CC_PT; ++u) {
+                const int k = tid + u * kBlock;
+                if (k < ncc)
+                    reinterpret_cast<I4 *>(s_cc)[k] = bcc[u];
+            }
+        }
+        __syncthreads();
+        const uint32_t *lcc = s_cc + lead;
+#pragma unroll 1
+        for (int p = 0; p < S::PASSES; ++p) {
+            const int row_l = p * S::RPP + rl;
+            if (lane_on && row_l < nr) {
+                const int32_t row = r0 + row_l;
+                const int j0 = s_rp[row_l] - z0;
+                const int j1 = s_rp[row_l + 1] - z0;
+                T sum[S::VW];
+#pragma unroll
+                for (int v = 0; v < S::VW; ++v)
+                    sum[v] = T(0);
+                if constexpr (has_pre<Op>::value) {
+                    const typename Op::Pre pr = op.pre(ln, row, g);
+                    if (staged)
+                        row_product_cc<T, S::VW>(lcc, s_vtab, cb, cmask, j0, j1, g, op, ln, sum);
+                    else
+                        row_product_cc<T, S::VW>(A.ccode + z0, s_vtab, cb, cmask, j0, j1, g, op, ln, sum);
+                    op.row(ln, row, g, sum, acc, pr);
+                } else {
+                    if (staged)
+                        row_product_cc<T, S::VW>(lcc, s_vtab, cb, cmask, j0, j1, g, op, ln, sum);
+                    else
+                        row_product_cc<T, S::VW>(A.ccode + z0, s_vtab, cb, cmask, j0, j1, g, op, ln, sum);
+                    op.row(ln, row, g, sum, acc);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 template <typename T, int M, class Op>
 __device__ __forceinline__ void gspmv_tiles(const CsrView<T> &A, const Op &op,
                                             Acc<T, Shape<T, M>::VW, Op::NDOT> &acc)
@@ -685,6 +815,10 @@ __device__ __forceinline__ void gspmv_tiles(const CsrView<T> &A, const Op &op,
     __shared__ __align__(16) unsigned char s_buf[TileLds<T, M>::BYTES];
     if (A.code) {
         gspmv_tiles_dict<T, M>(A, op, acc, s_rp, s_buf);
+        return;
+    }
+    if (A.ccode) {
+        gspmv_tiles_cc<T, M>(A, op, acc, s_rp, s_buf);
         return;
     }
     int32_t *s_ci = reinterpret_cast<int32_t *>(s_buf);

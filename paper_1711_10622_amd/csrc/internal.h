@@ -34,13 +34,16 @@ struct mrhs_csr_s {
     double *uval = nullptr;
     float *uval32 = nullptr;
     int32_t ureach = 0;
-    // dictionary form of the solver arrays (CsrView): offset table, and per
-    // value array (val, valh, val32, valh32) codes and value table; a null
-    // code means that array has too many distinct values (or the matrix too
-    // many distinct offsets) and products read the plain arrays
+    // dictionary form of the solver arrays (CsrView): per value array (val,
+    // valh, val32, valh32) either 16-bit codes over the offset table (at most
+    // kDictOffs distinct offsets) or 32-bit codes holding the column (more
+    // offsets), with the array's value table; neither (too many distinct
+    // values) means products read the plain arrays
     int32_t *otab = nullptr;
     int32_t noffs = 0, ob = 0;
     uint16_t *code[4] = {nullptr, nullptr, nullptr, nullptr};
+    uint32_t *ccode[4] = {nullptr, nullptr, nullptr, nullptr};
+    int32_t cbits[4] = {0, 0, 0, 0};
     void *vtab[4] = {nullptr, nullptr, nullptr, nullptr};
     int32_t nvals[4] = {0, 0, 0, 0};
 };
@@ -80,6 +83,11 @@ inline CsrView<T> view_of(const mrhs_csr_s &A, const T *va, int k)
         v.noffs = A.noffs;
         v.nvals = A.nvals[k];
         v.ob = A.ob;
+    } else if (A.ccode[k]) {
+        v.ccode = A.ccode[k];
+        v.vtab = static_cast<const T *>(A.vtab[k]);
+        v.nvals = A.nvals[k];
+        v.cb = A.cbits[k];
     }
     return v;
 }

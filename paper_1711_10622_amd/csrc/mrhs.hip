@@ -239,6 +239,7 @@ void free_csr(mrhs_csr_s *A)
     void *ptrs[] = {A->rp,   A->ci,   A->val, A->valh, A->val32, A->valh32, A->diag,
                     A->dinv, A->perm, A->urp, A->uci, A->uval, A->uval32, A->otab,
                     A->code[0], A->code[1], A->code[2], A->code[3],
+                    A->ccode[0], A->ccode[1], A->ccode[2], A->ccode[3],
                     A->vtab[0], A->vtab[1], A->vtab[2], A->vtab[3]};
     for (void *p : ptrs)
         if (p)
@@ -371,16 +372,18 @@ struct BitsOf<float> {
     using U = uint32_t;
 };
 
-// Codes and value table of one value array (host values hv) given the
-// offset set; false (nothing allocated) when it has too many distinct values.
+// Codes and value table of one value array (host values hv): 16-bit codes
+// over the offset set offs, or (offs null) 32-bit column codes; false
+// (nothing allocated) when it has too many distinct values or, for column
+// codes, the columns do not fit beside the value index.
 template <typename V>
 mrhs_status dict_array(mrhs_csr_s *A, const int32_t *rp, const int32_t *ci, const V *hv,
-                       const KeySet<int64_t> &offs, int k, size_t &total)
+                       const KeySet<int64_t> *offs, int k, size_t &total)
 {
     using U = typename BitsOf<V>::U;
     const int32_t n = A->n;
     const int64_t nnz = A->nnz;
-    const int limit = std::min(kDictVals, 1 << (16 - A->ob));
+    const int limit = offs ? std::min(kDictVals, 1 << (16 - A->ob)) : kDictVals;
     KeySet<U> vals(limit);
     auto bits = [&](int32_t, int32_t j) {
         U u;
@@ -389,68 +392,88 @@ mrhs_status dict_array(mrhs_csr_s *A, const int32_t *rp, const int32_t *ci, cons
     };
     if (!distinct_keys<U>(n, rp, limit, bits, vals))
         return MRHS_OK;
-    std::vector<uint16_t> code(static_cast<size_t>(nnz) + 8, 0);
+    int cb = 0;
+    if (!offs) {
+        int vb = 1;  // at least one bit, so the column field is at most 31 bits
+        while ((1 << vb) < static_cast<int>(vals.keys.size()))
+            ++vb;
+        cb = 32 - vb;
+        if (static_cast<int64_t>(n) > (static_cast<int64_t>(1) << cb))
+            return MRHS_OK;
+    }
+    const size_t ncode = static_cast<size_t>(nnz) + (offs ? 8 : kPad);
+    std::vector<uint16_t> code(offs ? ncode : 0, 0);
+    std::vector<uint32_t> ccode(offs ? 0 : ncode, 0);
     row_ranges(n, dict_threads(), [&](int32_t lo, int32_t hi, int) {
         for (int32_t i = lo; i < hi; ++i)
             for (int32_t j = rp[i]; j < rp[i + 1]; ++j) {
-                const int32_t o = offs.find(static_cast<int64_t>(ci[j]) - i);
-                const int32_t v = vals.find(bits(i, j));
-                code[j] = static_cast<uint16_t>((v << A->ob) | o);
+                const uint32_t v = static_cast<uint32_t>(vals.find(bits(i, j)));
+                if (offs)
+                    code[j] = static_cast<uint16_t>((v << A->ob) | offs->find(static_cast<int64_t>(ci[j]) - i));
+                else
+                    ccode[j] = (v << cb) | static_cast<uint32_t>(ci[j]);
             }
     });
     std::vector<V> tab(vals.keys.size());
     std::memcpy(tab.data(), vals.keys.data(), sizeof(V) * tab.size());
-    uint16_t *dcode = nullptr;
     V *dtab = nullptr;
     mrhs_status st;
-    if ((st = dev_alloc(&dcode, code.size(), total)))
+    if ((st = dev_alloc(&dtab, tab.size(), total)))
         return st;
-    if ((st = dev_alloc(&dtab, tab.size(), total))) {
-        (void)hipFree(dcode);
-        return st;
-    }
-    A->code[k] = dcode;
     A->vtab[k] = dtab;
     A->nvals[k] = static_cast<int32_t>(tab.size());
-    hipError_t e;
-    if ((e = hipMemcpy(dcode, code.data(), sizeof(uint16_t) * code.size(), hipMemcpyHostToDevice)) ||
-        (e = hipMemcpy(dtab, tab.data(), sizeof(V) * tab.size(), hipMemcpyHostToDevice)))
+    hipError_t e = hipMemcpy(dtab, tab.data(), sizeof(V) * tab.size(), hipMemcpyHostToDevice);
+    if (offs) {
+        if ((st = dev_alloc(&A->code[k], ncode, total)))
+            return st;
+        if (e == hipSuccess)
+            e = hipMemcpy(A->code[k], code.data(), sizeof(uint16_t) * ncode, hipMemcpyHostToDevice);
+    } else {
+        if ((st = dev_alloc(&A->ccode[k], ncode, total)))
+            return st;
+        A->cbits[k] = cb;
+        if (e == hipSuccess)
+            e = hipMemcpy(A->ccode[k], ccode.data(), sizeof(uint32_t) * ncode, hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess)
         return set_error(MRHS_EDEVICE, "dictionary upload failed: %s", hipGetErrorString(e));
     return MRHS_OK;
 }
 
-// Builds the dictionary form of the solver arrays when the matrix has at
-// most kDictOffs distinct column offsets (rp, ci: the solver's numbering,
-// sval: its binary64 values on the host; the derived arrays are read back
-// from the device, so the tables hold exactly the values the products use).
-// MRHS_CSR_DICT=0 turns it off.
+// Builds the dictionary form of the solver arrays (rp, ci: the solver's
+// numbering, sval: its binary64 values on the host; the derived arrays are
+// read back from the device, so the tables hold exactly the values the
+// products use): 16-bit codes when the matrix has at most kDictOffs distinct
+// column offsets, else 32-bit column codes.  MRHS_CSR_DICT=0 turns it off.
 mrhs_status build_dict(mrhs_csr_s *A, const int32_t *rp, const int32_t *ci, const double *sval, size_t &total)
 {
     if (!env_int("MRHS_CSR_DICT", 1, 0, 1) || A->nnz == 0)
         return MRHS_OK;
     KeySet<int64_t> offs(kDictOffs);
     auto off = [&](int32_t i, int32_t j) { return static_cast<int64_t>(ci[j]) - i; };
-    if (!distinct_keys<int64_t>(A->n, rp, kDictOffs, off, offs))
-        return MRHS_OK;
-    A->noffs = static_cast<int32_t>(offs.keys.size());
-    A->ob = 0;
-    while ((1 << A->ob) < A->noffs)
-        ++A->ob;
-    std::vector<int32_t> otab(offs.keys.begin(), offs.keys.end());
+    const bool by_offset = distinct_keys<int64_t>(A->n, rp, kDictOffs, off, offs);
     mrhs_status st;
-    if ((st = dev_alloc(&A->otab, otab.size(), total)))
-        return st;
     hipError_t e;
-    if ((e = hipMemcpy(A->otab, otab.data(), sizeof(int32_t) * otab.size(), hipMemcpyHostToDevice)))
-        return set_error(MRHS_EDEVICE, "dictionary upload failed: %s", hipGetErrorString(e));
+    if (by_offset) {
+        A->noffs = static_cast<int32_t>(offs.keys.size());
+        A->ob = 0;
+        while ((1 << A->ob) < A->noffs)
+            ++A->ob;
+        std::vector<int32_t> otab(offs.keys.begin(), offs.keys.end());
+        if ((st = dev_alloc(&A->otab, otab.size(), total)))
+            return st;
+        if ((e = hipMemcpy(A->otab, otab.data(), sizeof(int32_t) * otab.size(), hipMemcpyHostToDevice)))
+            return set_error(MRHS_EDEVICE, "dictionary upload failed: %s", hipGetErrorString(e));
+    }
+    const KeySet<int64_t> *po = by_offset ? &offs : nullptr;
     const size_t nnz = static_cast<size_t>(A->nnz);
-    if ((st = dict_array<double>(A, rp, ci, sval, offs, 0, total)))
+    if ((st = dict_array<double>(A, rp, ci, sval, po, 0, total)))
         return st;
     {
         std::vector<double> h(nnz);
         if ((e = hipMemcpy(h.data(), A->valh, sizeof(double) * nnz, hipMemcpyDeviceToHost)))
             return set_error(MRHS_EDEVICE, "read-back failed: %s", hipGetErrorString(e));
-        if ((st = dict_array<double>(A, rp, ci, h.data(), offs, 1, total)))
+        if ((st = dict_array<double>(A, rp, ci, h.data(), po, 1, total)))
             return st;
     }
     std::vector<float> h(nnz);
@@ -458,7 +481,7 @@ mrhs_status build_dict(mrhs_csr_s *A, const int32_t *rp, const int32_t *ci, cons
     for (int k = 0; k < 2; ++k) {
         if ((e = hipMemcpy(h.data(), src[k], sizeof(float) * nnz, hipMemcpyDeviceToHost)))
             return set_error(MRHS_EDEVICE, "read-back failed: %s", hipGetErrorString(e));
-        if ((st = dict_array<float>(A, rp, ci, h.data(), offs, 2 + k, total)))
+        if ((st = dict_array<float>(A, rp, ci, h.data(), po, 2 + k, total)))
             return st;
     }
     return MRHS_OK;
@@ -713,7 +736,7 @@ MRHS_API mrhs_status csr_stream_bytes(mrhs_csr A, int32_t dtype, int32_t scaled,
     if (dtype != MRHS_F64 && dtype != MRHS_F32)
         return set_error(MRHS_EINVAL, "unknown dtype %d", dtype);
     const int k = (dtype == MRHS_F64 ? 0 : 2) + (scaled ? 1 : 0);
-    const int64_t per = A->code[k] ? 2 : 4 + (dtype == MRHS_F64 ? 8 : 4);
+    const int64_t per = A->code[k] ? 2 : A->ccode[k] ? 4 : 4 + (dtype == MRHS_F64 ? 8 : 4);
     *bytes = 4 * (static_cast<int64_t>(A->n) + 1) + per * A->nnz;
     return MRHS_OK;
 }

@@ -1,15 +1,17 @@
 """GPU parity of the dictionary form of a matrix (csr_create).
 
-A matrix with at most 32 distinct column offsets stores, per value array with
-at most 2048 distinct values, one 16-bit code per entry and two tables; the
-tiled products read those instead of the index and value arrays.  They sum the
-same values in the same order, so every product and solve must equal, bit for
-bit, the same call on a handle made with MRHS_CSR_DICT=0 (plain arrays), which
-the other GPU tests hold to the oracle.  Covered: stencil matrices (dictionary
-in every array), a banded matrix whose tiles exceed the staged capacity (codes
-read from HBM), both sides of the 2048-value limit, too many values and too
-many offsets (plain form), products at every block width in both precisions,
-binary64 (plain and merged iterations) and mixed solves.
+Per value array with at most 2048 distinct values the handle stores one code
+per entry and the value table: 16-bit codes over an offset table when the
+matrix has at most 32 distinct column offsets, else 32-bit codes holding the
+column.  The tiled products read those instead of the index and value arrays
+and sum the same values in the same order, so every product and solve must
+equal, bit for bit, the same call on a handle made with MRHS_CSR_DICT=0 (plain
+arrays), which the other GPU tests hold to the oracle.  Covered: stencil
+matrices (16-bit codes), the same relabelled (32-bit codes), banded matrices
+whose tiles exceed the staged capacity (codes read from HBM) in both code
+forms, both sides of the 2048-value limit, too many values (plain form),
+products at every block width in both precisions, binary64 (plain and merged
+iterations) and mixed solves.
 """
 import os
 
@@ -66,26 +68,44 @@ def tridiag_k(n, k):
     return from_diagonals(n, (-1, 0, 1), lambda i, o: 4.0 + (i % k) * 2.0 ** -10 if o == 0 else -1.0)
 
 
+def band25():
+    # 25 entries per row: 256-row tiles exceed the staged 2048 entries
+    return from_diagonals(3000, range(-12, 13), lambda i, o: 40.0 if o == 0 else -1.0 - 0.5 * (o % 2))
+
+
+def perturbed():
+    B = grids.dirichlet7(12)
+    g = np.random.default_rng(3)
+    return CSRMatrix(B.n, B.row_ptr, B.col, B.val * (1.0 + 1e-3 * g.random(B.val.size)))
+
+
+def relabel(A, seed):
+    return grids.permute_symmetric(A, rng.permutation(A.n, seed))
+
+
+# name -> (matrix builder, bytes per entry the products stream: 2 and 4 are
+# the two code forms, 0 the plain arrays)
+CASES = {
+    "dir16": (lambda: grids.dirichlet7(16), 2),
+    "chan32x24x16": (lambda: grids.channel7(32, 24, 16, beta=2.0), 2),
+    "band25": (band25, 2),
+    "values2048": (lambda: tridiag_k(3000, 2047), 2),
+    "values2049": (lambda: tridiag_k(3000, 2048), 0),
+    "perturbed": (perturbed, 0),
+    "relabelled": (lambda: relabel(grids.dirichlet7(12), 5), 4),
+    "band25_relabelled": (lambda: relabel(band25(), 6), 4),
+    "values2048_relabelled": (lambda: relabel(tridiag_k(3000, 2047), 7), 4),
+    "perturbed_relabelled": (lambda: relabel(perturbed(), 8), 0),
+}
+
+
 def cases():
-    return {
-        "dir16": (grids.dirichlet7(16), True),
-        "chan32x24x16": (grids.channel7(32, 24, 16, beta=2.0), True),
-        # 25 entries per row: 256-row tiles exceed the staged 2048 entries
-        "band25": (from_diagonals(3000, range(-12, 13), lambda i, o: 40.0 if o == 0 else -1.0 - 0.5 * (o % 2)), True),
-        "values2048": (tridiag_k(3000, 2047), True),
-        "values2049": (tridiag_k(3000, 2048), False),
-        "perturbed": (None, False),
-        "relabelled": (grids.permute_symmetric(grids.dirichlet7(12), rng.permutation(12 ** 3, 5)), False),
-    }
+    return CASES
 
 
 def matrix(name):
-    A, dict_expected = cases()[name]
-    if name == "perturbed":
-        B = grids.dirichlet7(12)
-        g = np.random.default_rng(3)
-        A = CSRMatrix(B.n, B.row_ptr, B.col, B.val * (1.0 + 1e-3 * g.random(B.val.size)))
-    return A, dict_expected
+    build, per = CASES[name]
+    return build(), per
 
 
 def cuda(torch, X):
@@ -95,17 +115,17 @@ def cuda(torch, X):
 @pytest.mark.parametrize("name", list(cases()))
 def test_stream_bytes_reports_the_form(env, name):
     _, p = env
-    A, dict_expected = matrix(name)
+    A, per = matrix(name)
     Md, M0 = make(p, A, True), make(p, A, False)
     plain = {"f64": 4 * (A.n + 1) + 12 * A.col.size, "f32": 4 * (A.n + 1) + 8 * A.col.size}
     for dt in ("f64", "f32"):
         for scaled in (False, True):
             assert M0.stream_bytes(dt, scaled) == plain[dt]
-            want = 4 * (A.n + 1) + 2 * A.col.size if dict_expected else plain[dt]
+            want = 4 * (A.n + 1) + per * A.col.size if per else plain[dt]
             assert Md.stream_bytes(dt, scaled) == want, (dt, scaled)
             # the offline rule the benchmark summaries use agrees
             assert bench.matrix_stream_bytes(A, 8 if dt == "f64" else 4, scaled) == want, (dt, scaled)
-    if dict_expected:
+    if per:
         assert Md.device_bytes() > M0.device_bytes()
     Md.close()
     M0.close()
@@ -140,6 +160,9 @@ def test_gspmv_bitwise_plain(env, name):
     ("chan32x24x16", 8, True, 4000, 1e-10),
     ("band25", 7, False, 2000, 1e-10),
     ("values2048", 4, True, 2000, 1e-10),
+    ("relabelled", 8, False, 2000, 1e-10),
+    ("relabelled", 8, True, 2000, 1e-10),
+    ("band25_relabelled", 4, False, 2000, 1e-10),
 ])
 def test_solve_bitwise_plain(env, name, m, mixed, maxit, tol):
     torch, p = env
