@@ -496,6 +496,17 @@ struct Acc {
     }
 };
 
+// Workgroups per CU a streaming op is launched with at most (Op::kMaxPerCU
+// when the op defines it; 0: as many as fit).
+template <class Op, class = void>
+struct max_per_cu {
+    static constexpr int value = 0;
+};
+template <class Op>
+struct max_per_cu<Op, std::void_t<decltype(Op::kMaxPerCU)>> {
+    static constexpr int value = Op::kMaxPerCU;
+};
+
 // Blocks a product gathers per entry (Op::GATHERED when the op defines it).
 template <class Op, class = void>
 struct gathered_blocks {

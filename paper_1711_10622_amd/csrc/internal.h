@@ -64,7 +64,7 @@ void clear_error();
 // Number of workgroups for a tile-looping kernel over n rows: enough to keep
 // every CU at its occupancy limit, never more than there are tiles, rounded
 // up to a multiple of kGroups.
-int grid_for(const void *kernel, int64_t n, int tile_rows);
+int grid_for(const void *kernel, int64_t n, int tile_rows, int max_per_cu = 0);
 int max_grid();  // upper bound of grid_for over all kernels (for buffer sizing)
 
 template <typename T>
@@ -215,7 +215,7 @@ inline hipError_t launch_gspmv(const CsrView<T> &A, const Op &op, const RedBufs<
         }
     }
     const void *fn = reinterpret_cast<const void *>(&k_gspmv<T, M, Op>);
-    const int grid = grid_for(fn, A.n, Shape<T, M>::TR);
+    const int grid = grid_for(fn, A.n, Shape<T, M>::TR, max_per_cu<Op>::value);
     const int slot = g_trace_every ? trace_begin(s, Op::kName, static_cast<int>(sizeof(T)), M, grid) : -1;
     hipLaunchKernelGGL((k_gspmv<T, M, Op>), dim3(grid), dim3(kBlock), 0, s, A, op, rb);
     if (slot >= 0)
@@ -227,7 +227,7 @@ template <typename T, int M, class Op>
 inline hipError_t launch_stream(int32_t n, const Op &op, const RedBufs<T> &rb, hipStream_t s)
 {
     const void *fn = reinterpret_cast<const void *>(&k_stream<T, M, Op>);
-    const int grid = grid_for(fn, n, Shape<T, M>::TR);
+    const int grid = grid_for(fn, n, Shape<T, M>::TR, max_per_cu<Op>::value);
     const int slot = g_trace_every ? trace_begin(s, Op::kName, static_cast<int>(sizeof(T)), M, grid) : -1;
     hipLaunchKernelGGL((k_stream<T, M, Op>), dim3(grid), dim3(kBlock), 0, s, n, op, rb);
     if (slot >= 0)

@@ -60,7 +60,7 @@ int max_grid()
     return (g + kGroups - 1) / kGroups * kGroups;
 }
 
-int grid_for(const void *kernel, int64_t n, int tile_rows)
+int grid_for(const void *kernel, int64_t n, int tile_rows, int max_per_cu)
 {
     int per_cu = 1, cus = 0;
     {
@@ -76,6 +76,8 @@ int grid_for(const void *kernel, int64_t n, int tile_rows)
         }
         per_cu = it->second;
     }
+    if (max_per_cu > 0)
+        per_cu = std::min(per_cu, max_per_cu);
     const int64_t ntiles = (n + tile_rows - 1) / tile_rows;
     int64_t g = std::min<int64_t>(ntiles, static_cast<int64_t>(per_cu) * cus);
     g = std::max<int64_t>(g, 1);

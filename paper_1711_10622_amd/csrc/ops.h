@@ -638,6 +638,12 @@ __device__ __forceinline__ void xr_decide(Ctl &k, Kry<T> *kry, int c, T rhr, T r
 template <typename T, int M>
 struct OpXR {
     static constexpr const char *kName = "xr_update";
+    // two workgroups per CU instead of the six that fit: fewer concurrent
+    // streams (five read, three written per row) per memory channel; on the
+    // 12.6M-row channel 2520 -> 2436 us per launch at m = 16 and 1.2-2.3 %
+    // less time per iteration at m = 4, 8, 16 and in mixed solves, the same
+    // at m = 1 (full solves; one workgroup per CU is no faster)
+    static constexpr int kMaxPerCU = 2;
     using S = Shape<T, M>;
     static constexpr int NDOT = 2;
     T *y;
