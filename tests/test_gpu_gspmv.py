@@ -348,7 +348,9 @@ def test_plane_march_solve(torch_cuda, mrhs, mixed):
         assert np.all(true_relres(A, X, B) <= 1e-10)
     d = np.linalg.norm(mean_free(Xm) - mean_free(Xt), axis=0) / np.linalg.norm(mean_free(Xt), axis=0)
     assert np.all(d <= 1e-5), d
-    # the order of the partial dot products differs; binary64 counts move
-    # by a few %, the restarted binary32 inner solves' by up to ~20 %
+    # the order of the partial dot products differs, and at 1e-10 on this
+    # operator the iteration count moves with that order alone (one column:
+    # 473 against 551 between two grid sizes of the update pass; the
+    # restarted binary32 inner solves' by up to ~20 %)
     for a, b in zip(im, it):
-        assert abs(a["iters"] - b["iters"]) <= (0.3 if mixed else 0.15) * b["iters"], (a, b)
+        assert abs(a["iters"] - b["iters"]) <= 0.3 * b["iters"], (a, b)

@@ -239,8 +239,9 @@ def test_channel_full_m16(torch_cuda, mrhs, mixed):
         if not mixed:
             # at 1e-10 on this operator the count moves with summation order
             # alone: 456-512 iterations for one column under three dot-product
-            # orders in binary64 on the CPU, so two orders may differ by ~12%
-            assert abs(infos[l]["iters"] - io[l]["iters"]) <= 0.15 * io[l]["iters"]
+            # orders in binary64 on the CPU, 473-551 for one column under two
+            # workgroup counts on the GPU
+            assert abs(infos[l]["iters"] - io[l]["iters"]) <= 0.3 * io[l]["iters"]
 
 
 @pytest.fixture(scope="module")
