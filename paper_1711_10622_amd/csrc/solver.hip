@@ -62,15 +62,16 @@ constexpr size_t kPairGap = 8192;
 // row by row (v = r + m, row stride 2m) when the matrix has no regular plane
 // structure (its gathers visit rows in no particular order, and one line then
 // serves both rows of an entry: relabelled cube, m = 8, spmv_omega 601 -> 357
-// us binary64 and 553 -> 301 us binary32) or when each half is a whole
-// 128-byte line; else as two plain blocks (half-line rows made the channel's
-// binary32 passes 4 % slower).
-bool pair_rv(const mrhs_csr_s &A, int32_t m, size_t elem)
+// us binary64 and 553 -> 301 us binary32); else as two plain blocks
+// (interleaved, half-line rows made the channel's binary32 passes 4 % slower,
+// and whole-line rows its binary64 m = 16 solve 1.2 % slower: spmv_sigma
+// 1040 -> 1012 us, spmv_omega 1799 -> 1780 us as plain blocks).
+bool pair_rv(const mrhs_csr_s &A)
 {
     const int64_t ntiles = (static_cast<int64_t>(A.n) + kTileRows - 1) / kTileRows;
     const int64_t P = (static_cast<int64_t>(A.reach) + kTileRows / 2) / kTileRows;
     const bool planes = P >= 2 * kGroups && ntiles >= 4 * P;
-    return !planes || m * elem >= 128;
+    return !planes;
 }
 
 // The binary64 Jacobi iteration runs as two kernels (OpXRSigma, then
@@ -465,7 +466,7 @@ Engine::Engine(const mrhs_csr_s &A, int m, uint32_t flags, void *ws, const doubl
         c_.gcr.wnew = reinterpret_cast<double *>(base + L.wnew);
         c_.gcr.xacc = reinterpret_cast<double *>(base + L.xacc);
         c_.gcr.ndirs = ndirs_;
-        const bool pair = pair_rv(A, m, sizeof(float));
+        const bool pair = pair_rv(A);
         c_.r32 = reinterpret_cast<float *>(base + L.rv32);
         c_.v32 = pair ? c_.r32 + m_ : c_.r32 + static_cast<size_t>(A.n) * m_ + kPairGap / sizeof(float);
         c_.ldp32 = pair ? 2 * m_ : m_;
@@ -474,7 +475,7 @@ Engine::Engine(const mrhs_csr_s &A, int m, uint32_t flags, void *ws, const doubl
             *v32[i] = reinterpret_cast<float *>(base + L.v32[i]);
         c_.sgn32 = reinterpret_cast<uint8_t *>(base + L.sgn32);
     } else {
-        const bool pair = pair_rv(A, m, sizeof(double));
+        const bool pair = pair_rv(A);
         c_.r = reinterpret_cast<double *>(base + L.rv64);
         c_.v = pair ? c_.r + m_ : c_.r + static_cast<size_t>(A.n) * m_ + kPairGap / sizeof(double);
         c_.ldp64 = pair ? 2 * m_ : m_;
