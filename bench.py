@@ -283,11 +283,22 @@ def projection_step(torch, ms=(1, 16), tau=0.05, reps=20):
     return out
 
 
-def gspmv_sweep(torch, A, ms, dtypes, flush=False, reps=50):
+def gspmv_sweep(torch, A, ms, dtypes, flush=False, reps=50, plain=False):
+    """GSpMV times over block widths ``ms``; ``plain``: the handle is made
+    with MRHS_CSR_DICT=0, so the products read the index and value arrays."""
     import numpy as np
     import paper_1711_10622_amd as mrhs
-    from paper_1711_10622_amd import estimates as est
-    M = mrhs.CsrMatrix.from_csr(A)
+    old = os.environ.get("MRHS_CSR_DICT")
+    if plain:
+        os.environ["MRHS_CSR_DICT"] = "0"
+    try:
+        M = mrhs.CsrMatrix.from_csr(A)
+    finally:
+        if plain:
+            if old is None:
+                del os.environ["MRHS_CSR_DICT"]
+            else:
+                os.environ["MRHS_CSR_DICT"] = old
     out = {}
     scratch = torch.empty(1 << 30, dtype=torch.uint8, device="cuda") if flush else None
     for dt in dtypes:
@@ -1052,6 +1063,7 @@ def main():
         extra["amg"] = amg_legs(torch, A, Bh, m, step_s)
         log(f"amg: {extra['amg']}")
         extra["gspmv_chan256"] = gspmv_sweep(torch, A, list(range(1, 17)), ("f64", "f32"), reps=20)
+        extra["gspmv_chan256_plain_arrays"] = gspmv_sweep(torch, A, [1, 8, 16], ("f64", "f32"), reps=20, plain=True)
         extra["gspmv_chan256_local_gathers"] = gspmv_locality(torch, A)
         extra["gspmv_chan256_plane_march"] = gspmv_march(torch, A)
         extra["gspmv_cube192"] = gspmv_cube(torch)
