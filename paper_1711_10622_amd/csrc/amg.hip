@@ -29,6 +29,7 @@
 #include <vector>
 
 #include "amg.h"
+#include "dict.h"
 #include "internal.h"
 
 #define MRHS_API extern "C" __attribute__((visibility("default")))
@@ -666,6 +667,38 @@ CsrView<double> upload_csr(mrhs_amg_s *H, const amg::HostCsr &C, const std::vect
     return v;
 }
 
+// The dictionary form (16-bit or column codes, value table) of a level
+// operator's binary64 view v with values vals, when it has one; otab: the
+// level's offset table on the device (16-bit codes).  The binary32 views
+// made later read the plain arrays.
+void attach_dict(mrhs_amg_s *H, const amg::HostCsr &C, const std::vector<double> &vals, const dict::Offsets &offs,
+                 const int32_t *otab, CsrView<double> &v, hipError_t *err)
+{
+    if (*err != hipSuccess)
+        return;
+    const dict::Codes<double> c = dict::codes<double>(C.nr, C.nnz(), C.rp.data(), C.ci.data(), vals.data(), offs);
+    if (!c.ok)
+        return;
+    const double *tab = upload(H, c.tab.data(), c.tab.size(), 0, err);
+    if (offs.ok) {
+        const uint16_t *code = upload(H, c.code.data(), c.code.size(), 0, err);
+        if (*err != hipSuccess)
+            return;
+        v.code = code;
+        v.otab = otab;
+        v.noffs = static_cast<int32_t>(offs.set.keys.size());
+        v.ob = offs.ob;
+    } else {
+        const uint32_t *ccode = upload(H, c.ccode.data(), c.ccode.size(), 0, err);
+        if (*err != hipSuccess)
+            return;
+        v.ccode = ccode;
+        v.cb = c.cb;
+    }
+    v.vtab = tab;
+    v.nvals = static_cast<int32_t>(c.tab.size());
+}
+
 void free_amg(mrhs_amg_s *H)
 {
     if (!H)
@@ -791,6 +824,7 @@ MRHS_API mrhs_status amg_create(mrhs_csr A, double theta, int32_t max_coarse, in
         return set_error(MRHS_ENOMEM, "host allocation failed");
     H->A = A;
     H->device = A->device;
+    const bool use_dict = env_int("MRHS_CSR_DICT", 1, 0, 1) != 0;
     const int L = static_cast<int>(HH.levels.size());
     H->dev.nlev = L;
     int64_t nz_all = 0;
@@ -803,8 +837,9 @@ MRHS_API mrhs_status amg_create(mrhs_csr A, double theta, int32_t max_coarse, in
         const int32_t reach = median_reach(hl.A);
         d.A = upload_csr(H, hl.A, nullptr, reach, &e);
         d.dl1_inv = upload(H, hl.dl1_inv.data(), hl.dl1_inv.size(), 0, &e);
+        std::vector<double> vah;
         if (l + 1 < L) {
-            std::vector<double> vah(hl.A.va.size());
+            vah.resize(hl.A.va.size());
             for (int32_t i = 0; i < hl.A.nr; ++i)
                 for (int32_t k = hl.A.rp[i]; k < hl.A.rp[i + 1]; ++k)
                     vah[k] = hl.A.va[k] * hl.dl1_inv[hl.A.ci[k]];
@@ -814,6 +849,17 @@ MRHS_API mrhs_status amg_create(mrhs_csr A, double theta, int32_t max_coarse, in
             d.nnext = hl.P.nc;
             d.nnz_p = hl.P.nnz();
             H->cf.push_back(hl.cf);
+        }
+        // the tiled products of A_l and A_l D_l1^-1 read codes where the
+        // level's operator has a dictionary form (MRHS_CSR_DICT=0: never)
+        if (use_dict && !d.A.split && hl.A.nnz() > 0 && e == hipSuccess) {
+            dict::Offsets offs;
+            dict::offsets(hl.A.nr, hl.A.rp.data(), hl.A.ci.data(), offs);
+            std::vector<int32_t> otab(offs.set.keys.begin(), offs.set.keys.end());
+            const int32_t *dotab = offs.ok ? upload(H, otab.data(), otab.size(), 0, &e) : nullptr;
+            attach_dict(H, hl.A, hl.A.va, offs, dotab, d.A, &e);
+            if (l + 1 < L)
+                attach_dict(H, hl.A, vah, offs, dotab, d.Ah, &e);
         }
         if (e != hipSuccess)
             break;

@@ -5,10 +5,10 @@
 #include <cstring>
 #include <mutex>
 #include <string>
-#include <thread>
 #include <unordered_map>
 #include <vector>
 
+#include "dict.h"
 #include "internal.h"
 
 #define MRHS_API extern "C" __attribute__((visibility("default")))
@@ -264,178 +264,34 @@ mrhs_status dev_alloc(T **p, size_t count, size_t &total)
 
 constexpr size_t kPad = 4;  // elements of padding after the nnz entries
 
-// ---- dictionary form (CsrView::code) ----------------------------------------
-// Distinct keys in order of first appearance, at most `limit`; open
-// addressing over a power-of-two table.
-template <typename K>
-struct KeySet {
-    std::vector<K> keys;
-    std::vector<int32_t> slot;  // index into keys + 1, 0 empty
-    uint64_t mask = 0;
-    explicit KeySet(int limit)
-    {
-        size_t cap = 16;
-        while (cap < 4 * static_cast<size_t>(limit))
-            cap *= 2;
-        slot.assign(cap, 0);
-        mask = cap - 1;
-    }
-    // MurmurHash3's 64-bit finalizer: every key bit reaches the low bits the
-    // table uses (values such as 4 + k 2^-10 have zero low mantissa bits)
-    static uint64_t hash(K k)
-    {
-        uint64_t z = static_cast<uint64_t>(k);
-        z ^= z >> 33;
-        z *= 0xff51afd7ed558ccdull;
-        z ^= z >> 33;
-        z *= 0xc4ceb9fe1a85ec53ull;
-        return z ^ (z >> 33);
-    }
-    // index of k, inserting it; -1 when that would exceed limit
-    int32_t add(K k, int limit)
-    {
-        for (uint64_t h = hash(k) & mask;; h = (h + 1) & mask) {
-            const int32_t e = slot[h];
-            if (!e) {
-                if (static_cast<int>(keys.size()) >= limit)
-                    return -1;
-                keys.push_back(k);
-                slot[h] = static_cast<int32_t>(keys.size());
-                return slot[h] - 1;
-            }
-            if (keys[e - 1] == k)
-                return e - 1;
-        }
-    }
-    int32_t find(K k) const
-    {
-        for (uint64_t h = hash(k) & mask;; h = (h + 1) & mask) {
-            const int32_t e = slot[h];
-            if (!e || keys[e - 1] == k)
-                return e - 1;
-        }
-    }
-};
-
-int dict_threads()
-{
-    const unsigned hw = std::thread::hardware_concurrency();
-    return std::max(1, std::min(16, static_cast<int>(hw ? hw : 1)));
-}
-
-// Runs fn(lo, hi, t) over T contiguous row ranges of [0, n) in threads.
-template <class F>
-void row_ranges(int32_t n, int T, F &&fn)
-{
-    std::vector<std::thread> th;
-    for (int t = 0; t < T; ++t) {
-        const int32_t lo = static_cast<int32_t>(static_cast<int64_t>(n) * t / T);
-        const int32_t hi = static_cast<int32_t>(static_cast<int64_t>(n) * (t + 1) / T);
-        th.emplace_back([&fn, lo, hi, t] { fn(lo, hi, t); });
-    }
-    for (auto &x : th)
-        x.join();
-}
-
-// Distinct keys of key(j) over the entries of rows [0, n), in order of first
-// appearance in row order, at most limit (false when there are more).
-template <typename K, class KeyOf>
-bool distinct_keys(int32_t n, const int32_t *rp, int limit, KeyOf key, KeySet<K> &out)
-{
-    const int T = dict_threads();
-    std::vector<KeySet<K>> local(T, KeySet<K>(limit));
-    std::vector<char> over(T, 0);
-    row_ranges(n, T, [&](int32_t lo, int32_t hi, int t) {
-        for (int32_t i = lo; i < hi && !over[t]; ++i)
-            for (int32_t j = rp[i]; j < rp[i + 1]; ++j)
-                if (local[t].add(key(i, j), limit) < 0) {
-                    over[t] = 1;
-                    break;
-                }
-    });
-    for (int t = 0; t < T; ++t) {
-        if (over[t])
-            return false;
-        for (K k : local[t].keys)
-            if (out.add(k, limit) < 0)
-                return false;
-    }
-    return true;
-}
-
-template <typename V>
-struct BitsOf;
-template <>
-struct BitsOf<double> {
-    using U = uint64_t;
-};
-template <>
-struct BitsOf<float> {
-    using U = uint32_t;
-};
-
-// Codes and value table of one value array (host values hv): 16-bit codes
-// over the offset set offs, or (offs null) 32-bit column codes; false
-// (nothing allocated) when it has too many distinct values or, for column
-// codes, the columns do not fit beside the value index.
+// ---- dictionary form (CsrView::code, CsrView::ccode) --------------------------
+// Uploads the codes and value table of value array k (host values hv) when
+// it has a dictionary form.
 template <typename V>
 mrhs_status dict_array(mrhs_csr_s *A, const int32_t *rp, const int32_t *ci, const V *hv,
-                       const KeySet<int64_t> *offs, int k, size_t &total)
+                       const dict::Offsets &offs, int k, size_t &total)
 {
-    using U = typename BitsOf<V>::U;
-    const int32_t n = A->n;
-    const int64_t nnz = A->nnz;
-    const int limit = offs ? std::min(kDictVals, 1 << (16 - A->ob)) : kDictVals;
-    KeySet<U> vals(limit);
-    auto bits = [&](int32_t, int32_t j) {
-        U u;
-        std::memcpy(&u, &hv[j], sizeof(U));
-        return u;
-    };
-    if (!distinct_keys<U>(n, rp, limit, bits, vals))
+    dict::Codes<V> c = dict::codes<V>(A->n, A->nnz, rp, ci, hv, offs);
+    if (!c.ok)
         return MRHS_OK;
-    int cb = 0;
-    if (!offs) {
-        int vb = 1;  // at least one bit, so the column field is at most 31 bits
-        while ((1 << vb) < static_cast<int>(vals.keys.size()))
-            ++vb;
-        cb = 32 - vb;
-        if (static_cast<int64_t>(n) > (static_cast<int64_t>(1) << cb))
-            return MRHS_OK;
-    }
-    const size_t ncode = static_cast<size_t>(nnz) + (offs ? 8 : kPad);
-    std::vector<uint16_t> code(offs ? ncode : 0, 0);
-    std::vector<uint32_t> ccode(offs ? 0 : ncode, 0);
-    row_ranges(n, dict_threads(), [&](int32_t lo, int32_t hi, int) {
-        for (int32_t i = lo; i < hi; ++i)
-            for (int32_t j = rp[i]; j < rp[i + 1]; ++j) {
-                const uint32_t v = static_cast<uint32_t>(vals.find(bits(i, j)));
-                if (offs)
-                    code[j] = static_cast<uint16_t>((v << A->ob) | offs->find(static_cast<int64_t>(ci[j]) - i));
-                else
-                    ccode[j] = (v << cb) | static_cast<uint32_t>(ci[j]);
-            }
-    });
-    std::vector<V> tab(vals.keys.size());
-    std::memcpy(tab.data(), vals.keys.data(), sizeof(V) * tab.size());
     V *dtab = nullptr;
     mrhs_status st;
-    if ((st = dev_alloc(&dtab, tab.size(), total)))
+    if ((st = dev_alloc(&dtab, c.tab.size(), total)))
         return st;
     A->vtab[k] = dtab;
-    A->nvals[k] = static_cast<int32_t>(tab.size());
-    hipError_t e = hipMemcpy(dtab, tab.data(), sizeof(V) * tab.size(), hipMemcpyHostToDevice);
-    if (offs) {
-        if ((st = dev_alloc(&A->code[k], ncode, total)))
+    A->nvals[k] = static_cast<int32_t>(c.tab.size());
+    hipError_t e = hipMemcpy(dtab, c.tab.data(), sizeof(V) * c.tab.size(), hipMemcpyHostToDevice);
+    if (offs.ok) {
+        if ((st = dev_alloc(&A->code[k], c.code.size(), total)))
             return st;
         if (e == hipSuccess)
-            e = hipMemcpy(A->code[k], code.data(), sizeof(uint16_t) * ncode, hipMemcpyHostToDevice);
+            e = hipMemcpy(A->code[k], c.code.data(), sizeof(uint16_t) * c.code.size(), hipMemcpyHostToDevice);
     } else {
-        if ((st = dev_alloc(&A->ccode[k], ncode, total)))
+        if ((st = dev_alloc(&A->ccode[k], c.ccode.size(), total)))
             return st;
-        A->cbits[k] = cb;
+        A->cbits[k] = c.cb;
         if (e == hipSuccess)
-            e = hipMemcpy(A->ccode[k], ccode.data(), sizeof(uint32_t) * ncode, hipMemcpyHostToDevice);
+            e = hipMemcpy(A->ccode[k], c.ccode.data(), sizeof(uint32_t) * c.ccode.size(), hipMemcpyHostToDevice);
     }
     if (e != hipSuccess)
         return set_error(MRHS_EDEVICE, "dictionary upload failed: %s", hipGetErrorString(e));
@@ -451,23 +307,20 @@ mrhs_status build_dict(mrhs_csr_s *A, const int32_t *rp, const int32_t *ci, cons
 {
     if (!env_int("MRHS_CSR_DICT", 1, 0, 1) || A->nnz == 0)
         return MRHS_OK;
-    KeySet<int64_t> offs(kDictOffs);
-    auto off = [&](int32_t i, int32_t j) { return static_cast<int64_t>(ci[j]) - i; };
-    const bool by_offset = distinct_keys<int64_t>(A->n, rp, kDictOffs, off, offs);
+    dict::Offsets offs;
+    dict::offsets(A->n, rp, ci, offs);
     mrhs_status st;
     hipError_t e;
-    if (by_offset) {
-        A->noffs = static_cast<int32_t>(offs.keys.size());
-        A->ob = 0;
-        while ((1 << A->ob) < A->noffs)
-            ++A->ob;
-        std::vector<int32_t> otab(offs.keys.begin(), offs.keys.end());
+    if (offs.ok) {
+        A->noffs = static_cast<int32_t>(offs.set.keys.size());
+        A->ob = offs.ob;
+        std::vector<int32_t> otab(offs.set.keys.begin(), offs.set.keys.end());
         if ((st = dev_alloc(&A->otab, otab.size(), total)))
             return st;
         if ((e = hipMemcpy(A->otab, otab.data(), sizeof(int32_t) * otab.size(), hipMemcpyHostToDevice)))
             return set_error(MRHS_EDEVICE, "dictionary upload failed: %s", hipGetErrorString(e));
     }
-    const KeySet<int64_t> *po = by_offset ? &offs : nullptr;
+    const dict::Offsets &po = offs;
     const size_t nnz = static_cast<size_t>(A->nnz);
     if ((st = dict_array<double>(A, rp, ci, sval, po, 0, total)))
         return st;
