@@ -735,9 +735,27 @@ float *round32(mrhs_amg_s *H, const double *src, int64_t count, hipError_t *err)
     return static_cast<float *>(p);
 }
 
+// The binary32 view of a level operator: its values rounded (nearest even);
+// a binary64 dictionary form carries over with its value table rounded the
+// same way (equal values round alike, so each entry's code still names its
+// rounded value; the table may then hold repeats).
 CsrView<float> view32(mrhs_amg_s *H, const CsrView<double> &v, int64_t nnz, hipError_t *err)
 {
-    return {v.rp, v.ci, round32(H, v.va, nnz + static_cast<int64_t>(kPadElems), err), v.n, v.reach, v.split};
+    CsrView<float> w{v.rp, v.ci, round32(H, v.va, nnz + static_cast<int64_t>(kPadElems), err), v.n, v.reach, v.split};
+    if (v.vtab && *err == hipSuccess) {
+        const float *tab = round32(H, v.vtab, v.nvals, err);
+        if (*err == hipSuccess) {
+            w.vtab = tab;
+            w.nvals = v.nvals;
+            w.code = v.code;
+            w.otab = v.otab;
+            w.noffs = v.noffs;
+            w.ob = v.ob;
+            w.ccode = v.ccode;
+            w.cb = v.cb;
+        }
+    }
+    return w;
 }
 
 } // namespace
